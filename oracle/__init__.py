@@ -1,0 +1,144 @@
+"""ORACLE -- test infrastructure only (loaded by tests/, the smoke check and the
+benchmark's CPU-baseline leg; never by the product path).
+
+Thin ctypes marshalling over ``oracle.c``: a plain sequential CPU statement of
+what in-place super scalar samplesort computes.  The arithmetic lives in the C
+file, each function citing its passage of the paper.  Shares no code with the
+HIP library.
+
+Arrays use the same host layouts as the workloads module: u64 -> uint64[n],
+f64 -> float64[n], pair -> uint64[n,2], quartet -> uint64[n,4],
+bytes100 -> uint8[n,100].  Splitters are whole elements of the same dtype.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+DTYPES = {"u64": 0, "f64": 1, "pair": 2, "quartet": 3, "bytes100": 4}
+ELEM_BYTES = {"u64": 8, "f64": 8, "pair": 16, "quartet": 32, "bytes100": 100}
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp,
+                               os.path.join(_HERE, "oracle.c")])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u64, vp, u32, i32 = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+        L.or_sort.argtypes = [vp, u64, i32]; L.or_sort.restype = i32
+        L.or_compare.argtypes = [vp, vp, i32]; L.or_compare.restype = i32
+        L.or_bucket.argtypes = [vp, i32, vp, u32, i32]; L.or_bucket.restype = u32
+        L.or_num_buckets.argtypes = [i32, vp, u32, i32]; L.or_num_buckets.restype = u32
+        L.or_classify.argtypes = [vp, u64, i32, vp, u32, i32, vp]; L.or_classify.restype = i32
+        L.or_bucket_bounds.argtypes = [vp, u64, i32, vp, u32, i32, vp, vp]
+        L.or_bucket_bounds.restype = i32
+        L.or_splitmix64_at.argtypes = [u64, u64]; L.or_splitmix64_at.restype = u64
+        L.or_select_splitters.argtypes = [vp, u64, i32, u32, u32, u64, vp, vp,
+                                          ctypes.POINTER(u32), ctypes.POINTER(i32)]
+        L.or_select_splitters.restype = i32
+        L.or_tree.argtypes = [vp, u32, vp]; L.or_tree.restype = None
+        L.or_tree_descend.argtypes = [vp, u32, u64]; L.or_tree_descend.restype = u32
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _n(a):
+    return a.shape[0]
+
+
+def sort(arr: np.ndarray, dtype: str) -> np.ndarray:
+    """Sorted copy of arr (keys non-decreasing under the dtype's order)."""
+    out = np.ascontiguousarray(arr).copy()
+    if _load().or_sort(_ptr(out), _n(out), DTYPES[dtype]) != 0:
+        raise ValueError(dtype)
+    return out
+
+
+def compare(a: np.ndarray, b: np.ndarray, dtype: str) -> int:
+    a = np.ascontiguousarray(a); b = np.ascontiguousarray(b)
+    return int(_load().or_compare(_ptr(a), _ptr(b), DTYPES[dtype]))
+
+
+def num_buckets(splitters: np.ndarray, dtype: str, eq: bool) -> int:
+    sp = np.ascontiguousarray(splitters)
+    return int(_load().or_num_buckets(DTYPES[dtype], _ptr(sp), _n(sp), int(eq)))
+
+
+def classify(arr: np.ndarray, splitters: np.ndarray, dtype: str, eq: bool) -> np.ndarray:
+    a = np.ascontiguousarray(arr); sp = np.ascontiguousarray(splitters)
+    out = np.empty(_n(a), dtype=np.uint32)
+    rc = _load().or_classify(_ptr(a), _n(a), DTYPES[dtype], _ptr(sp), _n(sp), int(eq), _ptr(out))
+    if rc != 0:
+        raise ValueError(dtype)
+    return out
+
+
+def bucket_bounds(arr: np.ndarray, splitters: np.ndarray, dtype: str, eq: bool):
+    """(counts[K], bounds[K+1]) of one distribution step with given splitters."""
+    a = np.ascontiguousarray(arr); sp = np.ascontiguousarray(splitters)
+    K = num_buckets(sp, dtype, eq)
+    counts = np.zeros(K, dtype=np.uint64); bounds = np.zeros(K + 1, dtype=np.uint64)
+    rc = _load().or_bucket_bounds(_ptr(a), _n(a), DTYPES[dtype], _ptr(sp), _n(sp), int(eq),
+                                  counts.ctypes.data, bounds.ctypes.data)
+    if rc != 0:
+        raise ValueError(dtype)
+    return counts, bounds
+
+
+def splitmix64_at(seed: int, i: int) -> int:
+    return int(_load().or_splitmix64_at(seed & (2**64 - 1), i))
+
+
+def select_splitters(arr: np.ndarray, dtype: str, k: int, alpha: int, seed: int):
+    """(unique splitters as elements, equality flag) for k buckets, oversampling alpha."""
+    a = np.ascontiguousarray(arr)
+    shape_tail = a.shape[1:]
+    scratch = np.empty((alpha * k - 1,) + shape_tail, dtype=a.dtype)
+    out = np.empty((k - 1,) + shape_tail, dtype=a.dtype)
+    mu = ctypes.c_uint32(0); eq = ctypes.c_int(0)
+    rc = _load().or_select_splitters(_ptr(a), _n(a), DTYPES[dtype], k, alpha, seed & (2**64 - 1),
+                                     _ptr(scratch), _ptr(out), ctypes.byref(mu), ctypes.byref(eq))
+    if rc != 0:
+        raise ValueError("select_splitters: bad arguments")
+    return out[:mu.value].copy(), bool(eq.value)
+
+
+def tree(splitters_u64: np.ndarray, k: int) -> np.ndarray:
+    """Level-order search tree a_1..a_{k-1} of k-1 sorted u64 splitters."""
+    s = np.ascontiguousarray(splitters_u64, dtype=np.uint64)
+    assert s.shape[0] == k - 1
+    a = np.empty(k - 1, dtype=np.uint64)
+    _load().or_tree(_ptr(s), k, _ptr(a))
+    return a
+
+
+def tree_descend(a: np.ndarray, k: int, e: int) -> int:
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return int(_load().or_tree_descend(_ptr(a), k, e))
+
+
+def alpha_default(n: int) -> int:
+    """Oversampling factor 0.2*log2(n), at least 1 (Section 4, Implementation Details)."""
+    import math
+    return max(1, int(0.2 * math.log2(n))) if n > 1 else 1

@@ -1,0 +1,240 @@
+/*
+ * ORACLE -- test infrastructure only.
+ *
+ * A plain, slow, sequential CPU statement of what the in-place super scalar
+ * samplesort of Axtmann, Witt, Ferizovic and Sanders ("In-place Parallel Super
+ * Scalar Samplesort (IPS4o)", arXiv 1705.02257) computes.  Only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * Each function cites the passage it follows.  Where the method reaches a
+ * result with a plain definition (a sorted arrangement, a bucket index, a
+ * histogram, a prefix sum) the function is that definition written out, with
+ * the C library's qsort as the one library step.
+ *
+ * Element types (Section 5, data types): U64 and F64 keys; Pair = {u64 key,
+ * u64 payload}; Quartet = {u64 w0, w1, w2 key, u64 payload}, lexicographic;
+ * 100Bytes = {10-byte key, 90-byte payload}, lexicographic (unsigned bytes).
+ * F64 keys are ordered by IEEE 754 totalOrder, written out from its definition
+ * (sign first; then magnitude, reversed for negative numbers).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_U64 = 0, OR_F64 = 1, OR_PAIR = 2, OR_QUARTET = 3, OR_BYTES100 = 4 };
+
+size_t or_elem_size(int dtype) {
+    switch (dtype) {
+    case OR_U64: case OR_F64: return 8;
+    case OR_PAIR: return 16;
+    case OR_QUARTET: return 32;
+    case OR_BYTES100: return 100;
+    }
+    return 0;
+}
+
+static int cmp_u64_val(uint64_t x, uint64_t y) { return (x > y) - (x < y); }
+
+/* IEEE 754 totalOrder on binary64 bit patterns: every negative-signed value
+ * precedes every positive-signed one; among positive-signed values a larger
+ * magnitude field (exponent, then fraction, i.e. the low 63 bits read as an
+ * unsigned integer) is larger, NaNs above +inf; among negative-signed values
+ * the order of magnitudes is reversed, so -NaN < -inf < ... < -0 < +0. */
+static int cmp_f64_total(uint64_t x, uint64_t y) {
+    int sx = (int)(x >> 63), sy = (int)(y >> 63);
+    if (sx != sy) return sx ? -1 : 1;
+    uint64_t mx = x & 0x7fffffffffffffffULL, my = y & 0x7fffffffffffffffULL;
+    int c = cmp_u64_val(mx, my);
+    return sx ? -c : c;
+}
+
+static uint64_t ld64(const void *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+
+/* Three-way comparison of the keys of two elements of `dtype`. */
+int or_compare(const void *a, const void *b, int dtype) {
+    const unsigned char *x = (const unsigned char *)a, *y = (const unsigned char *)b;
+    switch (dtype) {
+    case OR_U64: case OR_PAIR: return cmp_u64_val(ld64(x), ld64(y));
+    case OR_F64: return cmp_f64_total(ld64(x), ld64(y));
+    case OR_QUARTET:
+        for (int w = 0; w < 3; ++w) {
+            int c = cmp_u64_val(ld64(x + 8 * w), ld64(y + 8 * w));
+            if (c) return c;
+        }
+        return 0;
+    case OR_BYTES100: {
+        int c = memcmp(x, y, 10);
+        return (c > 0) - (c < 0);
+    }
+    }
+    return 0;
+}
+
+static int q_u64(const void *a, const void *b) { return or_compare(a, b, OR_U64); }
+static int q_f64(const void *a, const void *b) { return or_compare(a, b, OR_F64); }
+static int q_pair(const void *a, const void *b) { return or_compare(a, b, OR_PAIR); }
+static int q_quartet(const void *a, const void *b) { return or_compare(a, b, OR_QUARTET); }
+static int q_bytes(const void *a, const void *b) { return or_compare(a, b, OR_BYTES100); }
+
+typedef int (*qcmp_t)(const void *, const void *);
+static qcmp_t qcmp_for(int dtype) {
+    switch (dtype) {
+    case OR_U64: return q_u64;
+    case OR_F64: return q_f64;
+    case OR_PAIR: return q_pair;
+    case OR_QUARTET: return q_quartet;
+    case OR_BYTES100: return q_bytes;
+    }
+    return 0;
+}
+
+/* Problem statement (Section 1): arrange A[0..n) so that the keys are
+ * non-decreasing under the total order.  The key sequence of the result is
+ * unique; the order of payloads among equal keys is not (samplesort is not
+ * stable).  Library step: qsort.  Returns 0, or -1 for a bad dtype. */
+int or_sort(void *data, uint64_t n, int dtype) {
+    qcmp_t c = qcmp_for(dtype);
+    if (!c) return -1;
+    if (n > 1) qsort(data, (size_t)n, or_elem_size(dtype), c);
+    return 0;
+}
+
+/* Bucket of one element for splitters s_1..s_m (sorted, non-decreasing).
+ *  eq == 0 (Section 3, Preliminaries): element e goes to bucket i when
+ *     s_{i-1} <= e < s_i with s_0 = -inf and s_{m+1} = +inf, i.e. the bucket
+ *     index is the number of splitters <= e, in [0, m].
+ *  eq != 0 (Section 4, "The Case of Many Identical Keys", and "Implementation
+ *     Details"): duplicates are removed first, giving unique u_1 < ... < u_m'.
+ *     Elements equal to a splitter get a bucket of their own between the two
+ *     open ranges around it; the buckets in order are
+ *     (-inf,u_1), {u_1}, (u_1,u_2), {u_2}, ..., {u_m'}, (u_m',+inf),
+ *     numbered 0 .. 2m'.  With j = #{u <= e}: 2j-1 if j >= 1 and u_j == e,
+ *     else 2j. */
+uint32_t or_bucket(const void *elem, int dtype, const void *splitters, uint32_t m, int eq) {
+    size_t s = or_elem_size(dtype);
+    const unsigned char *sp = (const unsigned char *)splitters;
+    if (!eq) {
+        uint32_t cnt = 0;
+        for (uint32_t i = 0; i < m; ++i)
+            if (or_compare(sp + i * s, elem, dtype) <= 0) ++cnt;
+        return cnt;
+    }
+    uint32_t j = 0;            /* number of distinct splitter keys <= e */
+    int last_equal = 0;        /* the largest such key equals e */
+    for (uint32_t i = 0; i < m; ++i) {
+        if (i > 0 && or_compare(sp + (i - 1) * s, sp + i * s, dtype) == 0) continue;
+        int c = or_compare(sp + i * s, elem, dtype);
+        if (c <= 0) { ++j; last_equal = (c == 0); }
+    }
+    return (j >= 1 && last_equal) ? 2 * j - 1 : 2 * j;
+}
+
+/* Number of logical buckets for the given splitters. */
+uint32_t or_num_buckets(int dtype, const void *splitters, uint32_t m, int eq) {
+    if (!eq) return m + 1;
+    size_t s = or_elem_size(dtype);
+    const unsigned char *sp = (const unsigned char *)splitters;
+    uint32_t u = 0;
+    for (uint32_t i = 0; i < m; ++i)
+        if (i == 0 || or_compare(sp + (i - 1) * s, sp + i * s, dtype) != 0) ++u;
+    return 2 * u + 1;
+}
+
+/* Bucket index of every element (the classification step, Section 4.1). */
+int or_classify(const void *data, uint64_t n, int dtype, const void *splitters,
+                uint32_t m, int eq, uint32_t *out) {
+    size_t s = or_elem_size(dtype);
+    if (!s) return -1;
+    const unsigned char *d = (const unsigned char *)data;
+    for (uint64_t i = 0; i < n; ++i) out[i] = or_bucket(d + i * s, dtype, splitters, m, eq);
+    return 0;
+}
+
+/* Bucket sizes (the counts kept during local classification, Section 4.1)
+ * and their exclusive prefix sum, the bucket boundaries (Section 4.2):
+ * bounds[i] = sum of counts[0..i), bounds[K] = n. */
+int or_bucket_bounds(const void *data, uint64_t n, int dtype, const void *splitters,
+                     uint32_t m, int eq, uint64_t *counts, uint64_t *bounds) {
+    size_t s = or_elem_size(dtype);
+    if (!s) return -1;
+    uint32_t K = or_num_buckets(dtype, splitters, m, eq);
+    const unsigned char *d = (const unsigned char *)data;
+    for (uint32_t i = 0; i < K; ++i) counts[i] = 0;
+    for (uint64_t i = 0; i < n; ++i) counts[or_bucket(d + i * s, dtype, splitters, m, eq)]++;
+    bounds[0] = 0;
+    for (uint32_t i = 0; i < K; ++i) bounds[i + 1] = bounds[i] + counts[i];
+    return 0;
+}
+
+/* splitmix64 (Steele, Lea and Flood, OOPSLA 2014): the i-th (0-based) output
+ * of the generator whose state starts at `seed`. */
+uint64_t or_splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Sampling (Section 3, Preliminaries, and Section 4, "Sampling"): draw
+ * alpha*k - 1 input elements at random, sort them, and pick the k-1 splitters
+ * equidistantly: s_i = sample[i*alpha - 1] (1-based i, 0-based sample), so
+ * that exactly alpha-1 sample elements lie strictly between two picks.  Then
+ * (Section 4, "Implementation Details") duplicates are removed and equality
+ * buckets are switched on exactly when there were duplicates.
+ *
+ * Sample positions: with replacement, position i = floor(h_i * n / 2^64) with
+ * h_i = splitmix64 output i of stream `seed`.  Writes the m' unique splitters
+ * (whole elements) to `out` (room for k-1), their number to *m_unique and the
+ * equality flag to *eq.  `scratch` must hold alpha*k - 1 elements. */
+int or_select_splitters(const void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha,
+                        uint64_t seed, void *scratch, void *out, uint32_t *m_unique, int *eq) {
+    size_t s = or_elem_size(dtype);
+    if (!s || n == 0 || k < 2 || alpha < 1) return -1;
+    const unsigned char *d = (const unsigned char *)data;
+    unsigned char *smp = (unsigned char *)scratch, *o = (unsigned char *)out;
+    uint64_t S = (uint64_t)alpha * k - 1;
+    for (uint64_t i = 0; i < S; ++i) {
+        uint64_t h = or_splitmix64_at(seed, i);
+        uint64_t pos = (uint64_t)(((unsigned __int128)h * n) >> 64);
+        memcpy(smp + i * s, d + pos * s, s);
+    }
+    or_sort(smp, S, dtype);
+    uint32_t u = 0;
+    for (uint32_t i = 1; i < k; ++i) {
+        const unsigned char *pick = smp + ((uint64_t)i * alpha - 1) * s;
+        if (u > 0 && or_compare(o + (u - 1) * s, pick, dtype) == 0) continue;
+        memcpy(o + u * s, pick, s);
+        ++u;
+    }
+    *m_unique = u;
+    *eq = (u < k - 1);
+    return 0;
+}
+
+/* The implicit search tree of super scalar samplesort (Section 3,
+ * Preliminaries): for k a power of two and splitters s_1..s_{k-1}, the array
+ * a_1..a_{k-1} is the complete binary search tree in level order with
+ * a_1 = s_{k/2}, a_2 = s_{k/4}, a_3 = s_{3k/4}, and the children of a_i are
+ * a_{2i} and a_{2i+1}.  Built recursively: node i holds the middle splitter of
+ * the index range [lo, hi) it covers, its children the middles of the halves.
+ * s[0..k-2] holds s_1..s_{k-1}; a[0..k-2] receives a_1..a_{k-1}. */
+static void tree_fill(const uint64_t *s, uint64_t *a, uint32_t node, uint32_t lo, uint32_t hi,
+                      uint32_t k) {
+    if (node >= k) return;
+    uint32_t mid = (lo + hi) / 2;      /* splitter index s_mid */
+    a[node - 1] = s[mid - 1];
+    tree_fill(s, a, 2 * node, lo, mid, k);
+    tree_fill(s, a, 2 * node + 1, mid, hi, k);
+}
+
+void or_tree(const uint64_t *s, uint32_t k, uint64_t *a) { tree_fill(s, a, 1, 0, k, k); }
+
+/* Branchless descent through that tree: j = 1, then log2(k) times
+ * j = 2j + [a_j <= e]; the bucket is j - k.  (u64 keys.) */
+uint32_t or_tree_descend(const uint64_t *a, uint32_t k, uint64_t e) {
+    uint32_t j = 1;
+    while (j < k) j = 2 * j + (a[j - 1] <= e ? 1u : 0u);
+    return j - k;
+}

@@ -1,0 +1,198 @@
+/*
+ * ips4o.h -- C ABI of an MI355X (gfx950) in-place super scalar samplesort.
+ *
+ * The library sorts an array that already lives in device memory, in place,
+ * following "In-place Parallel Super Scalar Samplesort (IPS4o)" (Axtmann,
+ * Witt, Ferizovic, Sanders; arXiv 1705.02257).  Problem statement (Section 1):
+ * arrange A[0..n) so that the keys are non-decreasing under a total order.
+ * Extra device memory is O(k * b) per workgroup (Theorem 2), independent of n
+ * for a bounded workgroup count; it is owned by the handle and reused.
+ *
+ * Element types (Section 5, data types):
+ *   IPS4O_U64       8-byte unsigned keys.
+ *   IPS4O_F64       8-byte IEEE binary64 keys ordered by IEEE 754 totalOrder
+ *                   (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN); output
+ *                   bit patterns are the input bit patterns, permuted.
+ *   IPS4O_PAIR      16-byte records {u64 key, u64 payload}, ordered by key.
+ *   IPS4O_QUARTET   32-byte records {u64 w0, w1, w2, u64 payload}, ordered
+ *                   lexicographically by (w0, w1, w2).
+ *   IPS4O_BYTES100  100-byte records {u8 key[10], u8 payload[90]}, ordered
+ *                   lexicographically by the key bytes read as unsigned.
+ * Records with equal keys keep their payloads but in no defined order
+ * (samplesort is not stable).
+ *
+ * Pointers: "device" pointers are addresses in the memory of the handle's
+ * HIP device (hipMalloc or a torch tensor's data_ptr()); "host" pointers are
+ * ordinary process memory.  Alignment: 8 bytes for U64/F64/PAIR/QUARTET,
+ * 4 bytes for BYTES100.  The caller owns all arrays it passes.
+ *
+ * Streams: `hip_stream` is a hipStream_t (NULL = the null stream).  Work is
+ * enqueued on that stream.  The calls read per-level results back to the
+ * host (the recursion is planned on the host) or copy host arguments, so
+ * they synchronize the stream before returning.
+ *
+ * Errors: every call validates its arguments before touching the device and
+ * returns IPS4O_OK (0) or a negative status (ips4o_status_string describes
+ * it).  n = 0 and n = 1 are valid no-ops.  After IPS4O_ERR_DEVICE_FAULT (a
+ * bounded wait inside a kernel ran out) the contents of the array are
+ * undefined: blocks held in flight by the permutation may be lost.
+ */
+#ifndef IPS4O_H
+#define IPS4O_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IPS4O_OK                    0
+#define IPS4O_ERR_INVALID_ARG      -1  /* NULL / misaligned pointer, unknown dtype, bad parameter */
+#define IPS4O_ERR_OUT_OF_MEMORY    -2  /* workspace allocation failed */
+#define IPS4O_ERR_HIP              -3  /* a HIP runtime call failed */
+#define IPS4O_ERR_NOT_SUPPORTED    -4  /* device is not gfx950, or n too large */
+#define IPS4O_ERR_DEVICE_FAULT     -5  /* a kernel's bounded wait expired; data undefined */
+
+typedef enum {
+    IPS4O_U64 = 0,
+    IPS4O_F64 = 1,
+    IPS4O_PAIR = 2,
+    IPS4O_QUARTET = 3,
+    IPS4O_BYTES100 = 4
+} ips4o_dtype;
+
+/* Tuning parameters (Section 4, Implementation Details).  A zero field takes
+ * the default; a NULL params pointer takes all defaults.
+ *   k           buckets of the first level, a power of two in [2, 512]
+ *               (default 256).  Deeper levels choose k adaptively.
+ *   block_bytes target block size in bytes; b = max(1, 2^floor(log2(
+ *               block_bytes / s))) elements (default 2048, as in the paper).
+ *   base_cap    largest subproblem (elements) sorted by the base case
+ *               (default and maximum depend on the dtype).
+ *   alpha_x100  oversampling factor times 100 (default 0.2 * log2 n, at
+ *               least 1).
+ *   stripes     classification workgroups for the first level (default:
+ *               chosen from n).
+ *   workers     permutation workers (wavefronts) per level (default: chosen
+ *               from the device).
+ *   seed        sampling seed (default a fixed constant).
+ *   flags       IPS4O_FLAG_* bits.
+ *   spin_limit  iterations a kernel may wait for another workgroup before it
+ *               reports IPS4O_ERR_DEVICE_FAULT (default 2^26). */
+typedef struct {
+    uint32_t k;
+    uint32_t block_bytes;
+    uint32_t base_cap;
+    uint32_t alpha_x100;
+    uint32_t stripes;
+    uint32_t workers;
+    uint64_t seed;
+    uint32_t flags;
+    uint32_t spin_limit;
+} ips4o_params;
+
+#define IPS4O_FLAG_NO_SKIP 1u   /* do not skip blocks already in place during the permutation */
+
+typedef struct ips4o_handle ips4o_handle;
+
+/* Create a handle bound to HIP device `hip_device`.  Fails with
+ * IPS4O_ERR_NOT_SUPPORTED unless the device is gfx950.  *out is set to NULL
+ * on failure. */
+int ips4o_create(int hip_device, ips4o_handle **out);
+
+/* Release the handle and its workspace.  NULL is ignored. */
+void ips4o_destroy(ips4o_handle *h);
+
+/* Device bytes of workspace the handle holds after the calls so far. */
+int ips4o_workspace_bytes(const ips4o_handle *h, size_t *bytes);
+
+/* Sort d_data[0..n) of `dtype` in place (the whole method: sampling,
+ * classification, block permutation, cleanup, recursion, base case;
+ * Sections 3 and 4).  d_data: device pointer to n elements. */
+int ips4o_sort(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
+               const ips4o_params *params, void *hip_stream);
+
+/* One distribution step with caller-given splitters (Section 4: local
+ * classification, block permutation, cleanup; no sampling, no recursion).
+ * h_splitters: host pointer to num_splitters whole elements of `dtype`
+ * whose keys are non-decreasing; only their keys are read.
+ * equality_buckets: 0 -> K = num_splitters + 1 buckets with
+ * s_{i-1} <= e < s_i (Section 3); 1 -> duplicates are removed and K = 2u + 1
+ * buckets over the u unique keys, equal keys in buckets of their own
+ * (Section 4, "The Case of Many Identical Keys").
+ * h_bounds_out: host pointer to K + 1 uint64 values receiving the bucket
+ * boundaries (bounds[0] = 0, bounds[K] = n).  On return d_data[bounds[i] ..
+ * bounds[i+1]) holds exactly the elements of bucket i, in no defined order.
+ * *num_buckets_out (host, may be NULL) receives K.
+ * Limits: 1 <= num_splitters <= 511 (K <= 1023). */
+int ips4o_distribute(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
+                     const void *h_splitters, uint32_t num_splitters, int equality_buckets,
+                     uint64_t *h_bounds_out, uint32_t *num_buckets_out,
+                     const ips4o_params *params, void *hip_stream);
+
+/* Bucket index of every element for caller-given splitters (the branchless
+ * tree classification of Section 3 with the equality test of Section 4).
+ * Splitter rules as for ips4o_distribute.  d_bucket_out: device pointer to n
+ * uint32 values.  d_data is not modified. */
+int ips4o_classify(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,
+                   const void *h_splitters, uint32_t num_splitters, int equality_buckets,
+                   uint32_t *d_bucket_out, void *hip_stream);
+
+/* The sampling step of a sort's first level (Section 3 and Section 4,
+ * "Sampling" and "Implementation Details"): alpha*k - 1 elements drawn at
+ * positions floor(h_i * n / 2^64), h_i the i-th output of splitmix64 started
+ * at `seed` (params->seed, or the default); the sample is sorted and the
+ * splitters s_i = sample[i*alpha - 1], i = 1..k-1, are picked; duplicates are
+ * removed and equality buckets switched on when there were any.
+ * h_splitters_out: host buffer of k - 1 elements of `dtype` (whole elements;
+ * only the key fields are meaningful) receiving the u unique splitters;
+ * *num_unique_out and *equality_out (host) receive u and the flag.
+ * d_data is not modified.  Requires n >= 1. */
+int ips4o_select_splitters(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,
+                           const ips4o_params *params, void *h_splitters_out,
+                           uint32_t *num_unique_out, int *equality_out, void *hip_stream);
+
+/* The argument checks that ips4o_sort applies before any device work,
+ * without a handle: returns IPS4O_OK, or the status ips4o_sort would return
+ * for these arguments (d_data is only inspected for NULL and alignment). */
+int ips4o_check_args(const void *d_data, uint64_t n, int dtype, const ips4o_params *params);
+
+/* The checks ips4o_distribute and ips4o_classify apply to caller-given
+ * splitters (host pointer to num_splitters elements of `dtype`): count in
+ * [1, 511], keys non-decreasing, equality_buckets 0 or 1. */
+int ips4o_check_splitters(const void *h_splitters, uint32_t num_splitters, int dtype,
+                          int equality_buckets);
+
+/* Wait for the stream and report a device fault raised by an earlier call. */
+int ips4o_sync(ips4o_handle *h, void *hip_stream);
+
+/* Static text for a status code. */
+const char *ips4o_status_string(int status);
+
+/* Statistics of the most recent ips4o_sort / ips4o_distribute on `h`
+ * (host values, filled when the call returns):
+ *   levels         distribution levels run
+ *   fault_bits     device error bits of the last call (0 = none): 1 a wait
+ *                  expired, 2 cleanup counts disagreed, 4 a permutation
+ *                  pointer left its bucket, 8 empty-block fix counts disagreed
+ *   block_moves    blocks written by the permutations (all levels)
+ *   block_skips    blocks found already in place and left there
+ *   elements_base  elements sorted by the base case
+ *   elements_distributed  sum over levels of the elements partitioned */
+typedef struct {
+    uint32_t levels;
+    uint32_t fault_bits;
+    uint64_t block_moves;
+    uint64_t block_skips;
+    uint64_t elements_base;
+    uint64_t elements_distributed;
+} ips4o_stats;
+
+int ips4o_last_stats(const ips4o_handle *h, ips4o_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPS4O_H */

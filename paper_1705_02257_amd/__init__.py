@@ -1,0 +1,224 @@
+"""Python binding of libips4o.so, the gfx950 in-place super scalar samplesort
+(Axtmann, Witt, Ferizovic, Sanders, "In-place Parallel Super Scalar
+Samplesort (IPS4o)", arXiv 1705.02257).
+
+Argument marshalling only: every step of the sort runs in the HIP kernels of
+the library.  The functions carry the C ABI's names (include/ips4o.h); array
+arguments may be torch tensors on the handle's GPU (their data_ptr() is
+passed) or raw device addresses as ints.  Host-side arrays (splitters,
+bounds) are numpy arrays.  A nonzero status raises Ips4oError.  The library
+must have been built (``python -m paper_1705_02257_amd.build``); importing
+this module without it raises ImportError -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+# torch first: it brings its own HIP runtime, and libips4o.so must bind to
+# that same runtime (it resolves libamdhip64.so.7 to the copy already loaded)
+# so that device pointers and streams from torch are valid in the library
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libips4o.so")
+
+U64, F64, PAIR, QUARTET, BYTES100 = 0, 1, 2, 3, 4
+DTYPES = {"u64": U64, "f64": F64, "pair": PAIR, "quartet": QUARTET, "bytes100": BYTES100}
+ELEM_BYTES = {U64: 8, F64: 8, PAIR: 16, QUARTET: 32, BYTES100: 100}
+FLAG_NO_SKIP = 1
+
+#: C symbols the library exports (as declared in include/ips4o.h)
+EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",
+           "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters", "ips4o_sync",
+           "ips4o_status_string", "ips4o_last_stats", "ips4o_check_args", "ips4o_check_splitters"]
+
+
+class Ips4oError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({ips4o_status_string(status)})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("block_bytes", ctypes.c_uint32),
+                ("base_cap", ctypes.c_uint32), ("alpha_x100", ctypes.c_uint32),
+                ("stripes", ctypes.c_uint32), ("workers", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("spin_limit", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_uint32), ("fault_bits", ctypes.c_uint32),
+                ("block_moves", ctypes.c_uint64), ("block_skips", ctypes.c_uint64),
+                ("elements_base", ctypes.c_uint64), ("elements_distributed", ctypes.c_uint64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1705_02257_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    L.ips4o_create.argtypes = [i32, ctypes.POINTER(vp)]
+    L.ips4o_destroy.argtypes = [vp]
+    L.ips4o_destroy.restype = None
+    L.ips4o_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
+    L.ips4o_distribute.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, ctypes.POINTER(u32),
+                                   ctypes.POINTER(Params), vp]
+    L.ips4o_classify.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp]
+    L.ips4o_select_splitters.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp,
+                                         ctypes.POINTER(u32), ctypes.POINTER(i32), vp]
+    L.ips4o_check_args.argtypes = [vp, u64, i32, ctypes.POINTER(Params)]
+    L.ips4o_check_splitters.argtypes = [vp, u32, i32, i32]
+    L.ips4o_sync.argtypes = [vp, vp]
+    L.ips4o_status_string.argtypes = [i32]
+    L.ips4o_status_string.restype = ctypes.c_char_p
+    L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_distribute",
+                 "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
+                 "ips4o_check_args", "ips4o_check_splitters"]:
+        getattr(L, name).restype = i32
+    return L
+
+
+lib = _load()
+
+
+def _dtype(dt):
+    return DTYPES[dt] if isinstance(dt, str) else int(dt)
+
+
+def _addr(x):
+    """Device address of a torch tensor or an int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _params(p):
+    if p is None:
+        return None
+    if isinstance(p, Params):
+        return ctypes.byref(p)
+    q = Params()
+    for k, v in p.items():
+        setattr(q, k, v)
+    return ctypes.byref(q)
+
+
+def _check(rc, where, h=None):
+    if rc != 0:
+        if rc == -5 and h is not None:
+            where = f"{where} (fault bits {ips4o_last_stats(h)['fault_bits']})"
+        raise Ips4oError(rc, where)
+
+
+def n_elements(t, dtype):
+    """Element count of a tensor laid out for `dtype` (rows for records)."""
+    d = _dtype(dtype)
+    if d in (U64, F64):
+        return t.numel()
+    return t.shape[0]
+
+
+def ips4o_status_string(status: int) -> str:
+    return lib.ips4o_status_string(status).decode()
+
+
+def ips4o_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.ips4o_create(device, ctypes.byref(h)), "ips4o_create")
+    return h.value
+
+
+def ips4o_destroy(h: int) -> None:
+    lib.ips4o_destroy(h)
+
+
+def ips4o_workspace_bytes(h: int) -> int:
+    v = ctypes.c_size_t()
+    _check(lib.ips4o_workspace_bytes(h, ctypes.byref(v)), "ips4o_workspace_bytes")
+    return v.value
+
+
+def ips4o_sort(h, data, n, dtype, params=None, stream=None) -> None:
+    _check(lib.ips4o_sort(h, _addr(data), n, _dtype(dtype), _params(params), _stream(stream)),
+           "ips4o_sort", h)
+
+
+def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool,
+                     params=None, stream=None) -> np.ndarray:
+    sp = np.ascontiguousarray(splitters)
+    m = sp.shape[0]
+    bounds = np.zeros(2 * m + 2, dtype=np.uint64)
+    K = ctypes.c_uint32(0)
+    _check(lib.ips4o_distribute(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, m,
+                                int(bool(equality_buckets)), bounds.ctypes.data, ctypes.byref(K),
+                                _params(params), _stream(stream)), "ips4o_distribute", h)
+    return bounds[:K.value + 1].copy()
+
+
+def ips4o_classify(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool, out,
+                   stream=None) -> None:
+    sp = np.ascontiguousarray(splitters)
+    _check(lib.ips4o_classify(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, sp.shape[0],
+                              int(bool(equality_buckets)), _addr(out), _stream(stream)),
+           "ips4o_classify")
+
+
+def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np.ndarray = None):
+    """Returns (unique splitters as a host array shaped like one element row of
+    `like` (or raw bytes rows), equality flag)."""
+    d = _dtype(dtype)
+    k = 256
+    if params is not None:
+        k = (params.k if isinstance(params, Params) else params.get("k", 0)) or 256
+    s = ELEM_BYTES[d]
+    out = np.zeros((k - 1) * s, dtype=np.uint8)
+    nu = ctypes.c_uint32(0)
+    eq = ctypes.c_int(0)
+    _check(lib.ips4o_select_splitters(h, _addr(data), n, d, _params(params), out.ctypes.data,
+                                      ctypes.byref(nu), ctypes.byref(eq), _stream(stream)),
+           "ips4o_select_splitters")
+    raw = out[:nu.value * s]
+    if like is not None:
+        raw = raw.view(like.dtype).reshape((nu.value,) + like.shape[1:])
+    return raw, bool(eq.value)
+
+
+def ips4o_sync(h, stream=None) -> None:
+    _check(lib.ips4o_sync(h, _stream(stream)), "ips4o_sync")
+
+
+def ips4o_last_stats(h) -> dict:
+    st = Stats()
+    _check(lib.ips4o_last_stats(h, ctypes.byref(st)), "ips4o_last_stats")
+    return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+
+_handles = {}
+
+
+def handle(device: int = 0) -> int:
+    """Process-wide handle for a device (created on first use)."""
+    if device not in _handles:
+        _handles[device] = ips4o_create(device)
+    return _handles[device]
+
+
+def sort_(tensor, dtype="u64", params=None, stream=None, device=None):
+    """Sort a device tensor in place; returns the tensor."""
+    dev = tensor.device.index if device is None else device
+    ips4o_sort(handle(dev or 0), tensor, n_elements(tensor, dtype), dtype, params, stream)
+    return tensor

@@ -1,0 +1,842 @@
+// Host side of the gfx950 samplesort: the C ABI declared in include/ips4o.h,
+// argument validation, workspace management and the recursion planner.
+//
+// Recursion (Section 4: "as long as problems with at least beta*n/t elements
+// exist, we partition those problems ... then we assign remaining problems"):
+// here every level partitions all current subproblems at once, as tasks of
+// one set of launches; subproblems no larger than the base-case capacity are
+// collected and sorted by one base-case launch at the end; equality buckets
+// are never recursed into (Section 4, many identical keys).  The host reads
+// the bucket boundaries back after each level to plan the next one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ips4o.h"
+#include "kernels.hpp"
+
+using namespace ips4o;
+
+namespace {
+
+constexpr uint32_t kDefaultK = 256;
+constexpr uint32_t kDefaultBlockBytes = 2048;
+constexpr uint32_t kMaxBlockBytes = 8192;
+constexpr uint64_t kDefaultSeed = 0x1705022570ull;
+constexpr uint32_t kDefaultSpin = 1u << 26;
+constexpr uint32_t kMaxLevels = 48;
+constexpr uint32_t kLevelStripes = 512;      // classification workgroups per level
+constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
+constexpr uint32_t kBaseGrid = 1024;
+
+size_t elem_size(int dt) {
+    switch (dt) {
+    case DT_U64: case DT_F64: return 8;
+    case DT_PAIR: return 16;
+    case DT_QUARTET: return 32;
+    case DT_BYTES100: return 100;
+    }
+    return 0;
+}
+size_t elem_align(int dt) { return dt == DT_BYTES100 ? 4 : 8; }
+
+uint32_t next_pow2(uint64_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Arena {  // grow-only device buffer
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need) {
+        if (need <= bytes) return IPS4O_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t want = need + need / 4;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return IPS4O_ERR_OUT_OF_MEMORY;
+        }
+        bytes = want;
+        return IPS4O_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct Carve {  // sequential sub-allocation with 256-byte alignment
+    char* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T* r = (T*)(base + off);
+        off += count * sizeof(T);
+        return r;
+    }
+    static size_t size_of(size_t off, size_t bytes) { return ((off + 255) & ~(size_t)255) + bytes; }
+};
+
+struct Seg {
+    uint64_t off, m;
+};
+
+}  // namespace
+
+struct ips4o_handle {
+    int device = 0;
+    int num_cus = 256;
+    Arena work;       // per-level workspace
+    Arena misc;       // error word, stats, ticket
+    Arena segs;       // base-case segment list
+    Arena scratch;    // base-case record scratch
+    ips4o_stats last{};
+    hipError_t last_hip = hipSuccess;
+};
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) {                        \
+            h->last_hip = e_;                          \
+            return IPS4O_ERR_HIP;                      \
+        }                                              \
+    } while (0)
+
+namespace {
+
+struct Resolved {
+    uint32_t k, b, cap, alpha_x100, stripes, workers, flags, spin;
+    uint64_t seed;
+};
+
+template <int DT>
+int resolve(const ips4o_params* p, Resolved* r) {
+    const size_t s = sizeof(typename Traits<DT>::Elem);
+    ips4o_params d{};
+    if (p) d = *p;
+    r->k = d.k ? d.k : kDefaultK;
+    if (r->k < 2 || r->k > (uint32_t)KT_MAX || (r->k & (r->k - 1))) return IPS4O_ERR_INVALID_ARG;
+    uint32_t bb = d.block_bytes ? d.block_bytes : kDefaultBlockBytes;
+    if (bb < s || bb > kMaxBlockBytes) return IPS4O_ERR_INVALID_ARG;
+    // b = max(1, 2^floor(log2(block_bytes / s))) (Section 4, Implementation Details)
+    uint32_t q = (uint32_t)(bb / s), b = 1;
+    while (b * 2 <= q) b *= 2;
+    r->b = b;
+    uint32_t cap = d.base_cap ? d.base_cap : (uint32_t)Traits<DT>::kBaseCap;
+    if (cap < 2 || cap > (uint32_t)Traits<DT>::kBaseCap) return IPS4O_ERR_INVALID_ARG;
+    r->cap = cap;
+    r->alpha_x100 = d.alpha_x100;
+    r->stripes = d.stripes;
+    if (d.stripes > STRIPES_PER_TASK_MAX) return IPS4O_ERR_INVALID_ARG;
+    r->workers = d.workers ? ((d.workers + 3) & ~3u) : kDefaultWorkers;
+    r->flags = d.flags;
+    r->spin = d.spin_limit ? d.spin_limit : kDefaultSpin;
+    r->seed = d.seed ? d.seed : kDefaultSeed;
+    return IPS4O_OK;
+}
+
+uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k) {
+    uint32_t a;
+    if (R.alpha_x100) a = std::max(1u, R.alpha_x100 / 100);
+    else a = std::max<uint32_t>(1u, (uint32_t)std::floor(0.2 * std::log2((double)std::max<uint64_t>(m, 2))));
+    while (a > 1 && (uint64_t)a * k > (uint64_t)SAMPLE_MAX) --a;
+    return a;
+}
+
+// splitmix64 finaliser, used to derive per-task sampling streams
+uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Host copy of the per-task splitter state for caller-given splitters.
+template <int DT>
+struct HostTree {
+    using Key = typename Traits<DT>::Key;
+    std::vector<Key> tree, spl;
+    TaskS ts{};
+};
+
+template <int DT>
+int build_host_tree(const void* h_split, uint32_t m, int eq, uint64_t nseg, uint32_t b,
+                    HostTree<DT>* out) {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    using Elem = typename TR::Elem;
+    if (m < 1 || m > (uint32_t)KT_MAX - 1 || !h_split) return IPS4O_ERR_INVALID_ARG;
+    std::vector<Key> keys(m);
+    const char* src = (const char*)h_split;
+    for (uint32_t i = 0; i < m; ++i) {
+        Elem e;
+        std::memcpy(&e, src + (size_t)i * sizeof(Elem), sizeof(Elem));
+        keys[i] = TR::key(e);
+        if (i > 0 && keys[i] < keys[i - 1]) return IPS4O_ERR_INVALID_ARG;
+    }
+    std::vector<Key> u;
+    if (eq) {
+        for (uint32_t i = 0; i < m; ++i)
+            if (u.empty() || !(u.back() == keys[i])) u.push_back(keys[i]);
+    } else {
+        u = keys;
+    }
+    const uint32_t nu = (uint32_t)u.size();
+    uint32_t kt = next_pow2((uint64_t)nu + 1);
+    if (kt < 2) kt = 2;
+    out->spl.assign(kt, u.back());
+    for (uint32_t i = 0; i < nu; ++i) out->spl[i] = u[i];
+    out->tree.assign(kt, u.back());
+    for (uint32_t i = 1; i < kt; ++i) {
+        uint32_t l = 31u - (uint32_t)__builtin_clz(i), p = i - (1u << l);
+        uint32_t idx = ((2 * p + 1) * kt) >> (l + 1);
+        out->tree[i] = out->spl[idx - 1];
+    }
+    TaskS& s = out->ts;
+    s.K = eq ? 2 * nu + 1 : nu + 1;
+    s.kt = kt;
+    s.eq = eq ? 1 : 0;
+    s.nuniq = nu;
+    s.nblocks = (uint32_t)((nseg + b - 1) / b);
+    s.ovf_bucket = NO_BUCKET;
+    return IPS4O_OK;
+}
+
+// One level: device pointers carved from the workspace, host plan.
+template <int DT>
+struct Level {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    using Elem = typename TR::Elem;
+    std::vector<TaskD> tasks;
+    std::vector<StripeD> stripes;
+    uint32_t total_slots = 0, total_tree = 0, total_workers = 0;
+    uint64_t total_buf = 0;
+    Ctx<DT> c{};
+};
+
+template <int DT>
+void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, uint32_t level,
+                bool first, uint32_t k_given) {
+    const uint32_t b = R.b;
+    uint64_t total_m = 0, total_blocks = 0;
+    for (const Seg& s : segs) {
+        total_m += s.m;
+        total_blocks += (s.m + b - 1) / b;
+    }
+    L.tasks.clear();
+    L.stripes.clear();
+    uint32_t slot = 0, treeb = 0, wk = 0;
+    uint64_t bufoff = 0;
+    for (size_t i = 0; i < segs.size(); ++i) {
+        const Seg& s = segs[i];
+        TaskD t{};
+        t.off = s.off;
+        t.m = s.m;
+        uint32_t k;
+        if (k_given) k = k_given;
+        else if (first) k = R.k;
+        else k = std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * s.m + R.cap - 1) / R.cap)));
+        t.k = k;
+        t.alpha = alpha_for(s.m, R, k);
+        t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
+        const uint64_t nb = (s.m + b - 1) / b;
+        // stripes: enough blocks per stripe to keep the partial buffers small
+        // (at least 8 buffer sets of k blocks each), and about kLevelStripes
+        // stripes over the whole level
+        uint64_t by_size = nb / (8ull * k);
+        uint64_t by_share = (uint64_t)std::ceil((double)kLevelStripes * (double)s.m / (double)total_m);
+        uint64_t ns = std::max<uint64_t>(1, std::min(by_size, by_share));
+        if (first && R.stripes) ns = R.stripes;
+        ns = std::min<uint64_t>(ns, std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
+        t.stripe_begin = (uint32_t)L.stripes.size();
+        t.nstripes = (uint32_t)ns;
+        for (uint64_t q = 0; q < ns; ++q) {
+            StripeD sd{};
+            sd.task = (uint32_t)i;
+            sd.blk_begin = (uint32_t)(nb * q / ns);
+            sd.blk_end = (uint32_t)(nb * (q + 1) / ns);
+            sd.buf_off = bufoff;
+            bufoff += (uint64_t)2 * k * b;
+            L.stripes.push_back(sd);
+        }
+        uint64_t w = (uint64_t)std::llround((double)R.workers * (double)nb / (double)total_blocks);
+        w = std::max<uint64_t>(4, (w + 3) & ~3ull);
+        t.worker_begin = wk;
+        t.nworkers = (uint32_t)w;
+        wk += (uint32_t)w;
+        t.slot_begin = slot;
+        slot += 2 * k;
+        t.tree_begin = treeb;
+        treeb += k;
+        L.tasks.push_back(t);
+    }
+    L.total_slots = slot;
+    L.total_tree = treeb;
+    L.total_workers = wk;
+    L.total_buf = bufoff;
+}
+
+template <int DT>
+size_t level_bytes(const Level<DT>& L, uint32_t b) {
+    using Key = typename Traits<DT>::Key;
+    using Elem = typename Traits<DT>::Elem;
+    const size_t T = L.tasks.size(), S = L.stripes.size();
+    size_t off = 0;
+    auto add = [&](size_t bytes) { off = Carve::size_of(off, bytes); };
+    add(T * sizeof(TaskD));
+    add(S * sizeof(StripeD));
+    add(T * sizeof(TaskS));
+    add(L.total_tree * sizeof(Key));
+    add(L.total_tree * sizeof(Key));
+    add((L.total_slots + T) * sizeof(uint64_t));
+    add((L.total_slots + T) * sizeof(uint32_t));
+    add(L.total_slots * sizeof(uint64_t));
+    add(L.total_slots * sizeof(uint32_t));
+    add(L.total_slots * sizeof(uint32_t));
+    add(S * (size_t)KMAX * sizeof(uint32_t));
+    add(S * sizeof(uint32_t));
+    add(L.total_buf * sizeof(Elem));
+    add(T * (size_t)b * sizeof(Elem));
+    return off + 256;
+}
+
+template <int DT>
+void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolved& R) {
+    using Key = typename Traits<DT>::Key;
+    using Elem = typename Traits<DT>::Elem;
+    const size_t T = L.tasks.size(), S = L.stripes.size();
+    Carve cv(base);
+    Ctx<DT>& c = L.c;
+    c.data = (Elem*)data;
+    c.tasks = cv.take<TaskD>(T);
+    c.stripes = cv.take<StripeD>(S);
+    c.ts = cv.take<TaskS>(T);
+    c.tree = cv.take<Key>(L.total_tree);
+    c.spl = cv.take<Key>(L.total_tree);
+    c.bounds = cv.take<uint64_t>(L.total_slots + T);
+    c.delim = cv.take<uint32_t>(L.total_slots + T);
+    c.wr = cv.take<uint64_t>(L.total_slots);
+    c.readers = cv.take<uint32_t>(L.total_slots);
+    c.flags = cv.take<uint32_t>(L.total_slots);
+    c.counts = cv.take<uint32_t>(S * (size_t)KMAX);
+    c.stripe_full = cv.take<uint32_t>(S);
+    c.bufs = cv.take<Elem>(L.total_buf);
+    c.ovf = cv.take<Elem>(T * (size_t)R.b);
+    c.ntasks = (uint32_t)T;
+    c.nstripes = (uint32_t)S;
+    char* m = (char*)misc;
+    c.err = (uint32_t*)m;
+    c.ticket = (uint32_t*)(m + 64);
+    c.stats = (unsigned long long*)(m + 128);
+    c.b = R.b;
+    c.spin_limit = R.spin;
+    c.total_workers = L.total_workers;
+    c.total_slots = L.total_slots;
+    c.skip_inplace = (R.flags & IPS4O_FLAG_NO_SKIP) ? 0u : 1u;
+}
+
+// Kernel shapes per element type.
+template <int DT> struct Shape;
+template <> struct Shape<DT_U64> { static constexpr int CNT = 1024, EPT = 8, BNT = 512; };
+template <> struct Shape<DT_F64> { static constexpr int CNT = 1024, EPT = 8, BNT = 512; };
+template <> struct Shape<DT_PAIR> { static constexpr int CNT = 1024, EPT = 4, BNT = 512; };
+template <> struct Shape<DT_QUARTET> { static constexpr int CNT = 1024, EPT = 2, BNT = 512; };
+template <> struct Shape<DT_BYTES100> { static constexpr int CNT = 512, EPT = 1, BNT = 512; };
+
+template <int DT, int WPL>
+hipError_t launch_permute_wpl(const Ctx<DT>& c, hipStream_t st) {
+    uint32_t grid = (c.total_workers + 3) / 4;
+    hipLaunchKernelGGL((k_permute<DT, WPL>), dim3(grid), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_permute(const Ctx<DT>& c, hipStream_t st) {
+    using TR = Traits<DT>;
+    const uint32_t words = c.b * (uint32_t)(sizeof(typename TR::Elem) / sizeof(typename TR::Word));
+    const uint32_t wpl = (words + 63) / 64;
+    if (wpl <= 4) return launch_permute_wpl<DT, 4>(c, st);
+    if (wpl <= 8) return launch_permute_wpl<DT, 8>(c, st);
+    if (wpl <= 16) return launch_permute_wpl<DT, 16>(c, st);
+    return launch_permute_wpl<DT, 32>(c, st);
+}
+
+template <int DT>
+int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given) {
+    using Key = typename Traits<DT>::Key;
+    using Elem = typename Traits<DT>::Elem;
+    constexpr int CNT = Shape<DT>::CNT, EPT = Shape<DT>::EPT;
+    Ctx<DT>& c = L.c;
+    const size_t T = L.tasks.size(), S = L.stripes.size();
+    HIP_TRY(hipMemcpyAsync((void*)c.tasks, L.tasks.data(), T * sizeof(TaskD), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)c.stripes, L.stripes.data(), S * sizeof(StripeD), hipMemcpyHostToDevice, st));
+    if (given) {
+        HIP_TRY(hipMemcpyAsync(c.tree, given->tree.data(), given->tree.size() * sizeof(Key), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(c.ts, &given->ts, sizeof(TaskS), hipMemcpyHostToDevice, st));
+    } else {
+        hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
+        HIP_TRY(hipGetLastError());
+    }
+    const size_t cls_lds = sizeof(ClassifyLds<DT, CNT, EPT>);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_classify<DT, CNT, EPT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cls_lds));
+    hipLaunchKernelGGL((k_classify<DT, CNT, EPT>), dim3(S), dim3(CNT), cls_lds, st, c);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_scan<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_fix_empty<DT, 256>), dim3(L.total_slots), dim3(256), 0, st, c);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_permute<DT>(c, st));
+    const size_t cl_lds = (size_t)c.b * sizeof(Elem);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_cleanup<DT, 256>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cl_lds));
+    hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(L.total_slots), dim3(256), cl_lds, st, c);
+    HIP_TRY(hipGetLastError());
+    return IPS4O_OK;
+}
+
+int check_device_error(ips4o_handle* h, hipStream_t st) {
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->misc.p, sizeof(err), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    h->last.fault_bits = err;
+    return err ? IPS4O_ERR_DEVICE_FAULT : IPS4O_OK;
+}
+
+int reset_misc(ips4o_handle* h, hipStream_t st) {
+    int rc = h->misc.ensure(4096);
+    if (rc) return rc;
+    HIP_TRY(hipMemsetAsync(h->misc.p, 0, 256, st));
+    return IPS4O_OK;
+}
+
+// Read back the per-task state and bounds of a finished level.
+template <int DT>
+int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>& ts,
+               std::vector<uint64_t>& bounds, unsigned long long* stats) {
+    const size_t T = L.tasks.size();
+    ts.resize(T);
+    bounds.resize(L.total_slots + T);
+    HIP_TRY(hipMemcpyAsync(ts.data(), L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bounds.data(), L.c.bounds, bounds.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stats, L.c.stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    return check_device_error(h, st);
+}
+
+template <int DT>
+int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, const Resolved& R,
+                 hipStream_t st) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    using Key = typename TR::Key;
+    if (list.empty()) return IPS4O_OK;
+    constexpr int BNT = Shape<DT>::BNT;
+    constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
+    int rc = h->segs.ensure(list.size() * sizeof(SegD));
+    if (rc) return rc;
+    const uint32_t grid = (uint32_t)std::min<size_t>(list.size(), kBaseGrid);
+    Elem* scr = nullptr;
+    if (!plain) {
+        rc = h->scratch.ensure((size_t)grid * TR::kBaseCap * sizeof(Elem));
+        if (rc) return rc;
+        scr = (Elem*)h->scratch.p;
+    }
+    HIP_TRY(hipMemcpyAsync(h->segs.p, list.data(), list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
+    Ctx<DT> c{};
+    c.data = (Elem*)d_data;
+    const size_t lds = plain ? (size_t)R.cap * sizeof(uint64_t) : (size_t)R.cap * sizeof(KeyIdx<Key>);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_basecase<DT, BNT>), dim3(grid), dim3(BNT), lds, st, c, (const SegD*)h->segs.p,
+                       (uint32_t)list.size(), scr);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));   // the host list must outlive the copy
+    return IPS4O_OK;
+}
+
+template <int DT>
+int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, hipStream_t st) {
+    Resolved R;
+    int rc = resolve<DT>(p, &R);
+    if (rc) return rc;
+    h->last = ips4o_stats{};
+    if (n <= 1) return IPS4O_OK;
+    rc = reset_misc(h, st);
+    if (rc) return rc;
+    std::vector<SegD> base;
+    std::vector<Seg> cur;
+    if (n <= R.cap) base.push_back(SegD{0, (uint32_t)n, 0});
+    else cur.push_back(Seg{0, n});
+    uint32_t level = 0;
+    Level<DT> L;
+    std::vector<TaskS> ts;
+    std::vector<uint64_t> bounds;
+    while (!cur.empty()) {
+        if (level >= kMaxLevels) return IPS4O_ERR_DEVICE_FAULT;
+        plan_level<DT>(L, cur, R, level, level == 0, 0);
+        rc = h->work.ensure(level_bytes<DT>(L, R.b));
+        if (rc) return rc;
+        carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+        rc = run_level<DT>(h, L, st, nullptr);
+        if (rc) return rc;
+        unsigned long long stats[2] = {0, 0};
+        rc = read_level<DT>(h, L, st, ts, bounds, stats);
+        if (rc) return rc;
+        h->last.block_moves = stats[0];
+        h->last.block_skips = stats[1];
+        for (const Seg& s : cur) h->last.elements_distributed += s.m;
+        std::vector<Seg> next;
+        for (size_t t = 0; t < L.tasks.size(); ++t) {
+            const TaskD& td = L.tasks[t];
+            const uint64_t* bd = bounds.data() + td.slot_begin + t;
+            for (uint32_t i = 0; i < ts[t].K; ++i) {
+                uint64_t sz = bd[i + 1] - bd[i];
+                if (sz <= 1) continue;
+                if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
+                uint64_t off = td.off + bd[i];
+                if (sz <= R.cap) base.push_back(SegD{off, (uint32_t)sz, 0});
+                else next.push_back(Seg{off, sz});
+            }
+        }
+        cur.swap(next);
+        ++level;
+    }
+    h->last.levels = level;
+    for (const SegD& s : base) h->last.elements_base += s.len;
+    rc = run_basecase<DT>(h, d_data, base, R, st);
+    if (rc) return rc;
+    return check_device_error(h, st);
+}
+
+template <int DT>
+int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_split, uint32_t m, int eq,
+                   uint64_t* h_bounds, uint32_t* nb_out, const ips4o_params* p, hipStream_t st) {
+    Resolved R;
+    int rc = resolve<DT>(p, &R);
+    if (rc) return rc;
+    HostTree<DT> ht;
+    rc = build_host_tree<DT>(h_split, m, eq, n, R.b, &ht);
+    if (rc) return rc;
+    const uint32_t K = ht.ts.K;
+    h->last = ips4o_stats{};
+    if (n == 0) {
+        for (uint32_t i = 0; i <= K; ++i) h_bounds[i] = 0;
+        if (nb_out) *nb_out = K;
+        return IPS4O_OK;
+    }
+    rc = reset_misc(h, st);
+    if (rc) return rc;
+    Level<DT> L;
+    std::vector<Seg> cur{Seg{0, n}};
+    plan_level<DT>(L, cur, R, 0, true, ht.ts.kt);
+    rc = h->work.ensure(level_bytes<DT>(L, R.b));
+    if (rc) return rc;
+    carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+    rc = run_level<DT>(h, L, st, &ht);
+    if (rc) return rc;
+    std::vector<TaskS> ts;
+    std::vector<uint64_t> bounds;
+    unsigned long long stats[2] = {0, 0};
+    rc = read_level<DT>(h, L, st, ts, bounds, stats);
+    h->last.levels = 1;
+    h->last.block_moves = stats[0];
+    h->last.block_skips = stats[1];
+    h->last.elements_distributed = n;
+    if (rc) return rc;
+    for (uint32_t i = 0; i <= K; ++i) h_bounds[i] = bounds[i];
+    if (nb_out) *nb_out = K;
+    return IPS4O_OK;
+}
+
+template <int DT>
+int run_classify(ips4o_handle* h, const void* d_data, uint64_t n, const void* h_split, uint32_t m, int eq,
+                 uint32_t* d_out, hipStream_t st) {
+    using Key = typename Traits<DT>::Key;
+    using Elem = typename Traits<DT>::Elem;
+    HostTree<DT> ht;
+    int rc = build_host_tree<DT>(h_split, m, eq, n, 1, &ht);
+    if (rc) return rc;
+    if (n == 0) return IPS4O_OK;
+    // workspace: one task descriptor, task state, tree, splitters
+    const size_t need = 4096 + 2 * KT_MAX * sizeof(Key);
+    rc = h->work.ensure(need);
+    if (rc) return rc;
+    Carve cv(h->work.p);
+    Ctx<DT> c{};
+    c.data = (Elem*)d_data;
+    TaskD td{};
+    c.tasks = cv.take<TaskD>(1);
+    c.ts = cv.take<TaskS>(1);
+    c.tree = cv.take<Key>(KT_MAX);
+    c.spl = cv.take<Key>(KT_MAX);
+    HIP_TRY(hipMemcpyAsync((void*)c.tasks, &td, sizeof(td), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.ts, &ht.ts, sizeof(TaskS), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.tree, ht.tree.data(), ht.tree.size() * sizeof(Key), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(c.spl, ht.spl.data(), ht.spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
+    uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_bucket_ids<DT, 256>), dim3(grid), dim3(256), 0, st, c, n, d_out);
+    HIP_TRY(hipGetLastError());
+    // the host copies above read stack memory: finish them before returning
+    HIP_TRY(hipStreamSynchronize(st));
+    return IPS4O_OK;
+}
+
+template <int DT>
+int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_params* p, void* h_out,
+               uint32_t* nu_out, int* eq_out, hipStream_t st) {
+    using Key = typename Traits<DT>::Key;
+    using Elem = typename Traits<DT>::Elem;
+    Resolved R;
+    int rc = resolve<DT>(p, &R);
+    if (rc) return rc;
+    rc = reset_misc(h, st);
+    if (rc) return rc;
+    Level<DT> L;
+    std::vector<Seg> cur{Seg{0, n}};
+    plan_level<DT>(L, cur, R, 0, true, 0);
+    L.tasks[0].seed = R.seed;   // the caller's stream, not a derived one
+    rc = h->work.ensure(level_bytes<DT>(L, R.b));
+    if (rc) return rc;
+    carve_level<DT>(L, h->work.p, h->misc.p, (void*)d_data, R);
+    HIP_TRY(hipMemcpyAsync((void*)L.c.tasks, L.tasks.data(), sizeof(TaskD), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(1), dim3(1024), 0, st, L.c);
+    HIP_TRY(hipGetLastError());
+    TaskS ts{};
+    std::vector<Key> spl(L.tasks[0].k);
+    HIP_TRY(hipMemcpyAsync(&ts, L.c.ts, sizeof(TaskS), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(spl.data(), L.c.spl, spl.size() * sizeof(Key), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // keys back to whole elements: the key fields are the element's leading
+    // words for every type except f64 (inverse totalOrder image) and the
+    // 100-byte records (big-endian bytes)
+    char* out = (char*)h_out;
+    for (uint32_t i = 0; i < ts.nuniq; ++i) {
+        Elem e;
+        std::memset(&e, 0, sizeof(e));
+        const Key& k = spl[i];
+        if constexpr (DT == DT_F64) {
+            e = Traits<DT_F64>::unkey(k.v);
+        } else if constexpr (DT == DT_BYTES100) {
+            e.w[0] = bswap32((uint32_t)(k.hi >> 32));
+            e.w[1] = bswap32((uint32_t)k.hi);
+            e.w[2] = bswap32(k.lo << 16);
+        } else if constexpr (DT == DT_U64) {
+            e = k.v;
+        } else if constexpr (DT == DT_PAIR) {
+            e.w[0] = k.v;
+        } else {
+            e.w[0] = k.a; e.w[1] = k.b; e.w[2] = k.c;
+        }
+        std::memcpy(out + (size_t)i * sizeof(Elem), &e, sizeof(Elem));
+    }
+    *nu_out = ts.nuniq;
+    *eq_out = (int)ts.eq;
+    return check_device_error(h, st);
+}
+
+int check_ptr(const void* p, uint64_t n, int dt) {
+    if (n > 0 && !p) return IPS4O_ERR_INVALID_ARG;
+    if (p && ((uintptr_t)p % elem_align(dt))) return IPS4O_ERR_INVALID_ARG;
+    return IPS4O_OK;
+}
+
+int check_params(const ips4o_params* params, int dtype) {
+    Resolved R;
+    switch (dtype) {
+    case DT_U64: return resolve<DT_U64>(params, &R);
+    case DT_F64: return resolve<DT_F64>(params, &R);
+    case DT_PAIR: return resolve<DT_PAIR>(params, &R);
+    case DT_QUARTET: return resolve<DT_QUARTET>(params, &R);
+    case DT_BYTES100: return resolve<DT_BYTES100>(params, &R);
+    }
+    return IPS4O_ERR_INVALID_ARG;
+}
+
+template <int DT>
+int check_splitter_order(const void* h_split, uint32_t m) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    const char* src = (const char*)h_split;
+    typename TR::Key prev{};
+    for (uint32_t i = 0; i < m; ++i) {
+        Elem e;
+        std::memcpy(&e, src + (size_t)i * sizeof(Elem), sizeof(Elem));
+        typename TR::Key k = TR::key(e);
+        if (i > 0 && k < prev) return IPS4O_ERR_INVALID_ARG;
+        prev = k;
+    }
+    return IPS4O_OK;
+}
+
+int set_device(ips4o_handle* h) {
+    HIP_TRY(hipSetDevice(h->device));
+    return IPS4O_OK;
+}
+
+}  // namespace
+
+#define DISPATCH(dt, CALL)                                   \
+    switch (dt) {                                            \
+    case DT_U64: { constexpr int D = DT_U64; return CALL; }  \
+    case DT_F64: { constexpr int D = DT_F64; return CALL; }  \
+    case DT_PAIR: { constexpr int D = DT_PAIR; return CALL; } \
+    case DT_QUARTET: { constexpr int D = DT_QUARTET; return CALL; } \
+    case DT_BYTES100: { constexpr int D = DT_BYTES100; return CALL; } \
+    default: return IPS4O_ERR_INVALID_ARG;                   \
+    }
+
+extern "C" {
+
+int ips4o_create(int hip_device, ips4o_handle** out) {
+    if (!out) return IPS4O_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return IPS4O_ERR_NOT_SUPPORTED;
+    if (hip_device < 0 || hip_device >= count) return IPS4O_ERR_INVALID_ARG;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return IPS4O_ERR_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return IPS4O_ERR_NOT_SUPPORTED;
+    ips4o_handle* h = new (std::nothrow) ips4o_handle();
+    if (!h) return IPS4O_ERR_OUT_OF_MEMORY;
+    h->device = hip_device;
+    h->num_cus = prop.multiProcessorCount;
+    *out = h;
+    return IPS4O_OK;
+}
+
+void ips4o_destroy(ips4o_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    h->work.release();
+    h->misc.release();
+    h->segs.release();
+    h->scratch.release();
+    delete h;
+}
+
+int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
+    if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
+    *bytes = h->work.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
+    return IPS4O_OK;
+}
+
+int ips4o_sort(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const ips4o_params* params,
+               void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, params);
+    if (rc) return rc;
+    if (n <= 1) return IPS4O_OK;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_sort<D>(h, d_data, n, params, st));
+}
+
+int ips4o_distribute(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const void* h_splitters,
+                     uint32_t num_splitters, int equality_buckets, uint64_t* h_bounds_out,
+                     uint32_t* num_buckets_out, const ips4o_params* params, void* hip_stream) {
+    if (!h || !h_bounds_out) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, params);
+    if (rc) return rc;
+    rc = ips4o_check_splitters(h_splitters, num_splitters, dtype, equality_buckets);
+    if (rc) return rc;
+    if (n > 0) {
+        rc = set_device(h);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_distribute<D>(h, d_data, n, h_splitters, num_splitters, equality_buckets,
+                                      h_bounds_out, num_buckets_out, params, st));
+}
+
+int ips4o_classify(ips4o_handle* h, const void* d_data, uint64_t n, int dtype, const void* h_splitters,
+                   uint32_t num_splitters, int equality_buckets, uint32_t* d_bucket_out, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, nullptr);
+    if (rc) return rc;
+    rc = ips4o_check_splitters(h_splitters, num_splitters, dtype, equality_buckets);
+    if (rc) return rc;
+    if (n > 0 && (!d_bucket_out || ((uintptr_t)d_bucket_out & 3))) return IPS4O_ERR_INVALID_ARG;
+    if (n > 0) {
+        rc = set_device(h);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_classify<D>(h, d_data, n, h_splitters, num_splitters, equality_buckets,
+                                    d_bucket_out, st));
+}
+
+int ips4o_select_splitters(ips4o_handle* h, const void* d_data, uint64_t n, int dtype,
+                           const ips4o_params* params, void* h_splitters_out, uint32_t* num_unique_out,
+                           int* equality_out, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, params);
+    if (rc) return rc;
+    if (n < 1 || !h_splitters_out || !num_unique_out || !equality_out) return IPS4O_ERR_INVALID_ARG;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_select<D>(h, d_data, n, params, h_splitters_out, num_unique_out, equality_out, st));
+}
+
+int ips4o_check_args(const void* d_data, uint64_t n, int dtype, const ips4o_params* params) {
+    if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    int rc = check_ptr(d_data, n, dtype);
+    if (rc) return rc;
+    rc = check_params(params, dtype);
+    if (rc) return rc;
+    if (n >= (1ull << 32)) return IPS4O_ERR_NOT_SUPPORTED;
+    return IPS4O_OK;
+}
+
+int ips4o_check_splitters(const void* h_splitters, uint32_t num_splitters, int dtype, int equality_buckets) {
+    if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    if (!h_splitters || num_splitters < 1 || num_splitters > (uint32_t)KT_MAX - 1) return IPS4O_ERR_INVALID_ARG;
+    if (equality_buckets != 0 && equality_buckets != 1) return IPS4O_ERR_INVALID_ARG;
+    DISPATCH(dtype, check_splitter_order<D>(h_splitters, num_splitters));
+}
+
+int ips4o_sync(ips4o_handle* h, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!h->misc.p) {
+        HIP_TRY(hipStreamSynchronize(st));
+        return IPS4O_OK;
+    }
+    return check_device_error(h, st);
+}
+
+const char* ips4o_status_string(int status) {
+    switch (status) {
+    case IPS4O_OK: return "ok";
+    case IPS4O_ERR_INVALID_ARG: return "invalid argument";
+    case IPS4O_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case IPS4O_ERR_HIP: return "HIP runtime error";
+    case IPS4O_ERR_NOT_SUPPORTED: return "not supported (device is not gfx950, or n too large)";
+    case IPS4O_ERR_DEVICE_FAULT: return "device fault: a bounded wait expired; data undefined";
+    }
+    return "unknown status";
+}
+
+int ips4o_last_stats(const ips4o_handle* h, ips4o_stats* out) {
+    if (!h || !out) return IPS4O_ERR_INVALID_ARG;
+    *out = h->last;
+    return IPS4O_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,970 @@
+// gfx950 kernels of one in-place super scalar samplesort level (Section 4 of
+// Axtmann, Witt, Ferizovic, Sanders, arXiv 1705.02257) and of the base case.
+//
+// A level partitions a list of independent subproblems ("tasks", each a
+// contiguous segment of the array) in six launches:
+//   k_sample      one workgroup per task: oversampled splitters, duplicate
+//                 removal, equality flag, level-order search tree (Section 3,
+//                 Preliminaries; Section 4, Sampling, Implementation Details)
+//   k_classify    one workgroup per stripe: local classification into
+//                 per-workgroup buffer blocks of b elements, full blocks
+//                 written back to the stripe front (Section 4.1)
+//   k_scan        one workgroup per task: bucket boundaries and block
+//                 delimiters from the per-stripe counts (Section 4.2)
+//   k_fix_empty   one workgroup per bucket: move full blocks of buckets that
+//                 cross stripe ends so every bucket is [full | empty]
+//                 (Appendix A, empty block movement); sets (w_i, r_i)
+//   k_permute     wavefront workers: the block permutation with atomic
+//                 read/write pointers and reader counts (Section 4.2)
+//   k_cleanup     one workgroup per bucket: heads, tails, partial buffers and
+//                 the overflow block (Section 4.3)
+// and k_basecase sorts small subproblems inside LDS.
+//
+// Block indices are relative to the task's segment start; block q covers
+// elements [q*b, (q+1)*b) of the segment, the last block may be partial.
+#pragma once
+#include "traits.hpp"
+
+namespace ips4o {
+
+constexpr int KT_MAX = 512;     // search tree leaves (power of two)
+constexpr int KMAX = 1024;      // logical buckets: up to 2*KT_MAX - 1
+constexpr int SAMPLE_MAX = 4096;
+constexpr int STRIPES_PER_TASK_MAX = 1024;
+constexpr uint32_t NO_BUCKET = 0xffffffffu;
+
+struct TaskD {                  // host-planned, one per task
+    uint64_t off;               // first element of the segment
+    uint64_t m;                 // segment length
+    uint64_t seed;              // sampling stream
+    uint32_t k;                 // requested tree leaves
+    uint32_t alpha;             // oversampling factor
+    uint32_t stripe_begin, nstripes;
+    uint32_t worker_begin, nworkers;
+    uint32_t slot_begin;        // first bucket slot (sum of 2k over earlier tasks)
+    uint32_t tree_begin;        // first tree slot (sum of k over earlier tasks)
+};
+
+struct StripeD {                // host-planned, one per stripe
+    uint32_t task;
+    uint32_t blk_begin, blk_end;
+    uint32_t pad;
+    uint64_t buf_off;           // element offset of this stripe's bucket buffers
+};
+
+struct TaskS {                  // device-written per task
+    uint32_t K;                 // logical buckets
+    uint32_t kt;                // tree leaves (power of two)
+    uint32_t eq;                // equality buckets on
+    uint32_t nuniq;             // splitters in spl[] (unique when eq)
+    uint32_t nblocks;           // ceil(m / b)
+    uint32_t ovf_bucket;        // bucket that filled the overflow block
+    uint32_t pad0, pad1;
+};
+
+template <int DT>
+struct Ctx {
+    using T = Traits<DT>;
+    using Elem = typename T::Elem;
+    using Key = typename T::Key;
+    Elem* data;
+    const TaskD* tasks;
+    uint32_t ntasks;
+    uint32_t nstripes;
+    const StripeD* stripes;
+    TaskS* ts;
+    Key* tree;                  // [sum k]: tree_begin + i, i in 1..kt-1
+    Key* spl;                   // [sum k]: tree_begin + j, sorted splitters (padded)
+    uint64_t* bounds;           // [sum (2k+1)]: slot_begin + task + i
+    uint32_t* delim;            // same indexing as bounds
+    uint64_t* wr;               // [sum 2k]: packed (w << 32) | (r + 2^31)
+    uint32_t* readers;          // [sum 2k]
+    uint32_t* flags;            // [sum 2k] cleanup ordering flags
+    uint32_t* counts;           // [stripes][KMAX]
+    uint32_t* stripe_full;      // [stripes] full blocks after classification
+    Elem* bufs;                 // stripe bucket buffers
+    Elem* ovf;                  // [tasks][b]
+    uint32_t* err;              // device error word (0 = ok)
+    unsigned long long* stats;  // [0] block moves, [1] skips
+    uint32_t* ticket;           // cleanup workgroup ticket
+    uint32_t b;                 // elements per block
+    uint32_t spin_limit;
+    uint32_t total_workers;
+    uint32_t total_slots;
+    uint32_t skip_inplace;
+    uint32_t pad;
+};
+
+enum ErrCode : uint32_t { ERR_SPIN = 1, ERR_CLEANUP_COUNT = 2, ERR_PERMUTE_RANGE = 4, ERR_FIX = 8 };
+
+__device__ inline void raise_err(uint32_t* err, uint32_t code) {
+    __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// largest index t in [0, n) with begin(t) <= x, for a non-decreasing begin()
+template <class F>
+__device__ inline uint32_t upper_find(uint32_t n, uint64_t x, F begin) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) / 2;
+        if (begin(mid) <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ block scan
+// Exclusive scan of one value per thread over the workgroup (NT threads).
+// `sh` needs NT/64 + 1 entries.  Returns the exclusive prefix; *total gets
+// the sum.  Contains barriers: call from every thread.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+    constexpr int NW = NT / 64;
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        uint32_t t = lane < NW ? sh[lane] : 0u, ti = t;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            uint32_t u = __shfl_up(ti, d, 64);
+            if (lane >= (uint32_t)d) ti += u;
+        }
+        if (lane < NW) sh[lane] = ti - t;
+        if (lane == NW - 1) sh[NW] = ti;
+    }
+    __syncthreads();
+    uint32_t r = inc - v + sh[wid];
+    *total = sh[NW];
+    __syncthreads();
+    return r;
+}
+
+// In-place exclusive scan of arr[0..n) in LDS (n <= NT * 4).  Returns total.
+template <int NT>
+__device__ inline uint32_t lds_excl_scan(uint32_t* arr, uint32_t n, uint32_t* sh) {
+    const uint32_t per = (n + NT - 1) / NT;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t loc = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < n) loc += arr[b0 + i];
+    uint32_t total;
+    uint32_t pre = block_excl_scan<NT>(loc, sh, &total);
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < n) {
+            uint32_t v = arr[b0 + i];
+            arr[b0 + i] = pre;
+            pre += v;
+        }
+    __syncthreads();
+    return total;
+}
+
+// ------------------------------------------------------- classification
+// Branchless descent through the implicit tree (Section 3): j = 1, then
+// log2(kt) times j = 2j + [a_j <= e]; leaf = j - kt counts the (padded)
+// splitters <= e.  With equality buckets (Section 4, many identical keys)
+// one more comparison against the splitter just below decides between the
+// equality bucket 2j-1 and the open bucket 2j.
+template <class Key>
+__device__ inline uint32_t classify_key(const Key& e, const Key* stree, const Key* sspl,
+                                        uint32_t log_kt, uint32_t nuniq, uint32_t eq) {
+    uint32_t j = 1;
+    for (uint32_t l = 0; l < log_kt; ++l) j = 2 * j + (stree[j] <= e ? 1u : 0u);
+    j -= (1u << log_kt);
+    j = j < nuniq ? j : nuniq;
+    if (!eq) return j;
+    uint32_t is_eq = (j >= 1 && sspl[j > 0 ? j - 1 : 0] == e) ? 1u : 0u;
+    return 2 * j - is_eq;
+}
+
+template <int DT>
+struct TreeLds {
+    typename Traits<DT>::Key tree[KT_MAX];
+    typename Traits<DT>::Key spl[KT_MAX];
+};
+
+template <int DT>
+__device__ inline void load_tree(const Ctx<DT>& c, const TaskD& td, uint32_t kt, uint32_t nuniq,
+                                 TreeLds<DT>& L) {
+    for (uint32_t i = threadIdx.x; i < kt; i += blockDim.x) {
+        L.tree[i] = c.tree[td.tree_begin + i];
+        L.spl[i] = c.spl[td.tree_begin + i];
+    }
+    __syncthreads();
+}
+
+__device__ inline uint32_t ilog2(uint32_t x) { return 31u - __clz(x); }
+
+// ------------------------------------------------------------- sampling
+// One workgroup per task.  Draws S = alpha*k - 1 sample keys at positions
+// floor(h_i * m / 2^64) (h_i: splitmix64 of the task's stream), sorts them in
+// LDS (bitonic network), picks s_i = sample[i*alpha - 1], removes
+// duplicates, switches equality buckets on when there were any, pads the
+// splitter array to a power-of-two tree and stores the level-order tree
+// a_i = s_{(2p+1) kt / 2^(l+1)} (l = floor(log2 i), p = i - 2^l).
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    __shared__ Key smp[SAMPLE_MAX];
+    __shared__ uint32_t isnew[KT_MAX];
+    __shared__ uint32_t scan_sh[NT / 64 + 1];
+    const TaskD td = c.tasks[blockIdx.x];
+    const uint32_t k = td.k, alpha = td.alpha;
+    const uint32_t S = alpha * k - 1;
+    uint32_t P = 1;
+    while (P < S) P <<= 1;
+    for (uint32_t i = threadIdx.x; i < P; i += NT) {
+        if (i < S) {
+            uint64_t h = splitmix64_at(td.seed, i);
+            uint64_t pos = __umul64hi(h, td.m);
+            smp[i] = TR::key(c.data[td.off + pos]);
+        } else {
+            smp[i] = TR::max_key();
+        }
+    }
+    __syncthreads();
+    // bitonic sort, ascending, P a power of two
+    for (uint32_t size = 2; size <= P; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
+                uint32_t i = (t / stride) * 2 * stride + (t % stride);
+                uint32_t j = i + stride;
+                bool up = ((i & size) == 0);
+                Key a = smp[i], bb = smp[j];
+                bool sw = up ? (bb < a) : (a < bb);
+                if (sw) { smp[i] = bb; smp[j] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    // picks and duplicate removal
+    for (uint32_t i = threadIdx.x; i < KT_MAX; i += NT) {
+        uint32_t f = 0;
+        if (i >= 1 && i < k) {
+            f = (i == 1) ? 1u : (smp[(i - 1) * alpha - 1] == smp[i * alpha - 1] ? 0u : 1u);
+        }
+        isnew[i] = f;
+    }
+    __syncthreads();
+    // position of each new pick among the unique ones
+    uint32_t nuniq = lds_excl_scan<NT>(isnew, KT_MAX, scan_sh);
+    Key* spl = c.spl + td.tree_begin;
+    Key* tree = c.tree + td.tree_begin;
+    for (uint32_t i = 1 + threadIdx.x; i < k; i += NT) {
+        Key pick = smp[i * alpha - 1];
+        bool nw = (i == 1) || !(smp[(i - 1) * alpha - 1] == pick);
+        if (nw) spl[isnew[i]] = pick;
+    }
+    const uint32_t eq = nuniq < k - 1 ? 1u : 0u;
+    uint32_t kt = k;
+    if (eq) {
+        kt = 2;
+        while (kt < nuniq + 1) kt <<= 1;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // pad with the largest splitter
+    Key last = smp[0];
+    {
+        // the largest pick is the last one
+        last = smp[(k - 1) * alpha - 1];
+    }
+    for (uint32_t j = nuniq + threadIdx.x; j < kt; j += NT) spl[j] = last;
+    __syncthreads();
+    __threadfence();
+    __syncthreads();
+    const uint32_t lk = ilog2(kt);
+    for (uint32_t i = 1 + threadIdx.x; i < kt; i += NT) {
+        uint32_t l = ilog2(i), p = i - (1u << l);
+        uint32_t idx = ((2 * p + 1) * kt) >> (l + 1);   // 1-based splitter index
+        (void)lk;
+        tree[i] = spl[idx - 1];
+    }
+    if (threadIdx.x == 0) {
+        TaskS s;
+        s.K = eq ? 2 * nuniq + 1 : nuniq + 1;
+        s.kt = kt;
+        s.eq = eq;
+        s.nuniq = nuniq;
+        s.nblocks = (uint32_t)((td.m + c.b - 1) / c.b);
+        s.ovf_bucket = NO_BUCKET;
+        s.pad0 = s.pad1 = 0;
+        c.ts[blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------ local classification
+// One workgroup per stripe.  The stripe is read in tiles of NT*EPT elements.
+// Each tile is classified in registers, counting-sorted by bucket in LDS,
+// and then merged with the workgroup's per-bucket buffer blocks (b elements
+// each, in global memory): a bucket whose buffer plus new elements reach b
+// or more emits full blocks to the stripe's write front, the rest stays
+// buffered.  The write front never passes the read front because a full
+// block is only emitted for b elements already read (Section 4.1).
+template <int DT, int NT, int EPT>
+struct ClassifyLds {
+    using Elem = typename Traits<DT>::Elem;
+    TreeLds<DT> tr;
+    Elem tile[NT * EPT];
+    uint16_t ids[NT * EPT];
+    uint32_t cnt[KMAX];
+    uint32_t off[KMAX];
+    uint32_t fill[KMAX];
+    uint32_t nblk[KMAX];
+    uint32_t bbase[KMAX];
+    uint32_t scan_sh[NT / 64 + 1];
+    uint32_t wf;
+};
+
+template <int DT, int NT, int EPT>
+__global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    constexpr uint32_t TILE = NT * EPT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    auto& L = *reinterpret_cast<ClassifyLds<DT, NT, EPT>*>(smem_raw);
+
+    const StripeD sd = c.stripes[blockIdx.x];
+    const TaskD td = c.tasks[sd.task];
+    const TaskS st = c.ts[sd.task];
+    const uint32_t b = c.b, K = st.K, kt = st.kt, lkt = ilog2(kt);
+    load_tree<DT>(c, td, kt, st.nuniq, L.tr);
+    for (uint32_t j = threadIdx.x; j < K; j += NT) {
+        L.cnt[j] = 0; L.fill[j] = 0; L.nblk[j] = 0;
+    }
+    if (threadIdx.x == 0) L.wf = 0;
+    __syncthreads();
+
+    Elem* seg = c.data + td.off;
+    Elem* buf = c.bufs + sd.buf_off;
+    const uint64_t s_begin = (uint64_t)sd.blk_begin * b;
+    const uint64_t s_end = ((uint64_t)sd.blk_end * b < td.m) ? (uint64_t)sd.blk_end * b : td.m;
+    const uint64_t stripe_blk0 = sd.blk_begin;
+
+    for (uint64_t t0 = s_begin; t0 < s_end; t0 += TILE) {
+        const uint32_t tn = (uint32_t)((s_end - t0) < TILE ? (s_end - t0) : TILE);
+        Elem x[EPT];
+        uint32_t bk[EPT], rk[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uint32_t p = e * NT + threadIdx.x;
+            if (p < tn) x[e] = seg[t0 + p];
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uint32_t p = e * NT + threadIdx.x;
+            if (p < tn) {
+                bk[e] = classify_key(TR::key(x[e]), L.tr.tree, L.tr.spl, lkt, st.nuniq, st.eq);
+                rk[e] = atomicAdd(&L.cnt[bk[e]], 1u);
+            }
+        }
+        __syncthreads();
+        // per bucket: tile offsets and full blocks emitted
+        for (uint32_t j = threadIdx.x; j < K; j += NT) {
+            L.off[j] = L.cnt[j];
+            L.bbase[j] = (L.fill[j] + L.cnt[j]) / b;
+        }
+        __syncthreads();
+        lds_excl_scan<NT>(L.off, K, L.scan_sh);
+        uint32_t nfull = lds_excl_scan<NT>(L.bbase, K, L.scan_sh);
+        const uint32_t wf = L.wf;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            uint32_t p = e * NT + threadIdx.x;
+            if (p < tn) {
+                uint32_t q = L.off[bk[e]] + rk[e];
+                L.tile[q] = x[e];
+                L.ids[q] = (uint16_t)bk[e];
+            }
+        }
+        __syncthreads();
+        // phase A: buffered elements of buckets that complete a block go to
+        // the front of their first new block (one wavefront per bucket)
+        {
+            const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            for (uint32_t j = wid; j < K; j += NT / 64) {
+                uint32_t f = L.fill[j], nf = (f + L.cnt[j]) / b;
+                if (nf == 0 || f == 0) continue;
+                Elem* dst = seg + (stripe_blk0 + wf + L.bbase[j]) * (uint64_t)b;
+                const Elem* src = buf + (uint64_t)j * b;
+                for (uint32_t i = lane; i < f; i += 64) dst[i] = src[i];
+            }
+        }
+        __syncthreads();
+        // phase B: tile elements to full blocks or to the buffers
+        for (uint32_t p = threadIdx.x; p < tn; p += NT) {
+            uint32_t j = L.ids[p];
+            uint32_t q = p - L.off[j];
+            uint32_t f = L.fill[j];
+            uint32_t pos = f + q;
+            uint32_t nf = (f + L.cnt[j]) / b;
+            if (pos < nf * b) {
+                uint64_t blk = stripe_blk0 + wf + L.bbase[j] + pos / b;
+                seg[blk * b + (pos % b)] = L.tile[p];
+            } else {
+                buf[(uint64_t)j * b + (pos - nf * b)] = L.tile[p];
+            }
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < K; j += NT) {
+            uint32_t tot = L.fill[j] + L.cnt[j];
+            L.nblk[j] += tot / b;
+            L.fill[j] = tot % b;
+            L.cnt[j] = 0;
+        }
+        if (threadIdx.x == 0) L.wf = wf + nfull;
+        __syncthreads();
+    }
+    uint32_t* cnt_out = c.counts + (uint64_t)blockIdx.x * KMAX;
+    for (uint32_t j = threadIdx.x; j < K; j += NT) cnt_out[j] = L.nblk[j] * b + L.fill[j];
+    if (threadIdx.x == 0) c.stripe_full[blockIdx.x] = L.wf;
+}
+
+// --------------------------------------------------------------- scan
+// One workgroup per task: C_i = sum over stripes, bounds B_i (exclusive
+// prefix), delimiters d_i = ceil(B_i / b) (Section 4.2).  Also resets the
+// reader counts, the cleanup flags and the overflow owner of the task.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
+    __shared__ uint32_t tot[KMAX];
+    __shared__ uint32_t sh[NT / 64 + 1];
+    const uint32_t t = blockIdx.x;
+    const TaskD td = c.tasks[t];
+    const uint32_t K = c.ts[t].K;
+    for (uint32_t j = threadIdx.x; j < K; j += NT) {
+        uint32_t s = 0;
+        for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
+        tot[j] = s;
+    }
+    __syncthreads();
+    // 64-bit prefix: per-thread chunk sums fit 32 bits only if m < 2^32;
+    // segments are limited to < 2^32 elements by the planner.
+    uint32_t total = lds_excl_scan<NT>(tot, K, sh);
+    (void)total;
+    uint64_t* bd = c.bounds + td.slot_begin + t;
+    uint32_t* dl = c.delim + td.slot_begin + t;
+    for (uint32_t j = threadIdx.x; j <= K; j += NT) {
+        uint64_t B = (j < K) ? (uint64_t)tot[j] : td.m;
+        bd[j] = B;
+        dl[j] = (uint32_t)((B + c.b - 1) / c.b);
+    }
+    for (uint32_t j = threadIdx.x; j < K; j += NT) {
+        c.readers[td.slot_begin + j] = 0;
+        c.flags[td.slot_begin + j] = 0;
+    }
+    if (threadIdx.x == 0) {
+        c.ts[t].ovf_bucket = NO_BUCKET;
+        if (t == 0) *c.ticket = 0;
+    }
+}
+
+// ------------------------------------------------------ empty-block fix
+// One workgroup per bucket slot.  Within the bucket's block range
+// [d_i, d_{i+1}) the stripes contribute runs "full, then empty".  Count the
+// full blocks occ; the first occ positions must all be full: the empty ones
+// among them ("holes") receive, in order, the full blocks found at or after
+// d_i + occ ("stragglers"), as in Appendix A.  Then w_i = d_i and
+// r_i = d_i + occ - 1.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
+    using Elem = typename Traits<DT>::Elem;
+    using Word = typename Traits<DT>::Word;
+    __shared__ uint32_t hpre[STRIPES_PER_TASK_MAX + 1];
+    __shared__ uint32_t spre[STRIPES_PER_TASK_MAX + 1];
+    __shared__ uint32_t occpre[STRIPES_PER_TASK_MAX + 1];
+    __shared__ uint32_t sh[NT / 64 + 1];
+    const uint32_t g = blockIdx.x;
+    const uint32_t t = upper_find(c.ntasks, g, [&](uint32_t i) { return (uint64_t)c.tasks[i].slot_begin; });
+    const TaskD td = c.tasks[t];
+    const uint32_t j = g - td.slot_begin;
+    const uint32_t K = c.ts[t].K;
+    if (j >= K) return;
+    const uint32_t b = c.b;
+    const uint32_t* dl = c.delim + td.slot_begin + t;
+    const uint32_t d0 = dl[j], d1 = dl[j + 1];
+    const uint32_t ns = td.nstripes;
+    // per-stripe occupied counts inside [d0, d1)
+    for (uint32_t q = threadIdx.x; q < ns; q += NT) {
+        const StripeD sd = c.stripes[td.stripe_begin + q];
+        uint32_t lo = sd.blk_begin > d0 ? sd.blk_begin : d0;
+        uint32_t hi = sd.blk_end < d1 ? sd.blk_end : d1;
+        uint32_t fe = sd.blk_begin + c.stripe_full[td.stripe_begin + q];
+        uint32_t o = 0;
+        if (lo < hi && fe > lo) o = (fe < hi ? fe : hi) - lo;
+        occpre[q] = o;
+    }
+    __syncthreads();
+    const uint32_t occ = lds_excl_scan<NT>(occpre, ns, sh);
+    const uint32_t target = d0 + occ;
+    for (uint32_t q = threadIdx.x; q < ns; q += NT) {
+        const StripeD sd = c.stripes[td.stripe_begin + q];
+        uint32_t lo = sd.blk_begin > d0 ? sd.blk_begin : d0;
+        uint32_t hi = sd.blk_end < d1 ? sd.blk_end : d1;
+        uint32_t fe = sd.blk_begin + c.stripe_full[td.stripe_begin + q];
+        uint32_t h = 0, s = 0;
+        if (lo < hi) {
+            uint32_t oe = fe < lo ? lo : (fe < hi ? fe : hi);     // end of the full run
+            uint32_t he = hi < target ? hi : target;               // holes: [oe, he)
+            if (he > oe) h = he - oe;
+            uint32_t sb = lo > target ? lo : target;               // stragglers: [sb, oe)
+            if (oe > sb) s = oe - sb;
+        }
+        hpre[q] = h;
+        spre[q] = s;
+    }
+    __syncthreads();
+    const uint32_t nh = lds_excl_scan<NT>(hpre, ns, sh);
+    const uint32_t nsg = lds_excl_scan<NT>(spre, ns, sh);
+    if (nh != nsg && threadIdx.x == 0) raise_err(c.err, ERR_FIX);
+    hpre[ns] = nh;
+    spre[ns] = nsg;
+    __syncthreads();
+    // moves: the x-th hole receives the x-th straggler; one wavefront per move
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Elem* seg = c.data + td.off;
+    const uint32_t words = b * (uint32_t)(sizeof(Elem) / sizeof(Word));
+    for (uint32_t x = wid; x < nh; x += NT / 64) {
+        uint32_t qh = upper_find(ns, x, [&](uint32_t i) { return (uint64_t)hpre[i]; });
+        while (qh + 1 < ns && hpre[qh + 1] <= x) ++qh;
+        uint32_t qs = upper_find(ns, x, [&](uint32_t i) { return (uint64_t)spre[i]; });
+        while (qs + 1 < ns && spre[qs + 1] <= x) ++qs;
+        const StripeD sh_ = c.stripes[td.stripe_begin + qh];
+        const StripeD ss_ = c.stripes[td.stripe_begin + qs];
+        uint32_t lo_h = sh_.blk_begin > d0 ? sh_.blk_begin : d0;
+        uint32_t fe_h = sh_.blk_begin + c.stripe_full[td.stripe_begin + qh];
+        uint32_t oe_h = fe_h < lo_h ? lo_h : fe_h;
+        uint32_t dst_blk = oe_h + (x - hpre[qh]);
+        uint32_t lo_s = ss_.blk_begin > d0 ? ss_.blk_begin : d0;
+        uint32_t sb = lo_s > target ? lo_s : target;
+        uint32_t src_blk = sb + (x - spre[qs]);
+        const uint64_t full_blocks = td.m / b;
+        if (dst_blk >= full_blocks || src_blk >= full_blocks || dst_blk < d0 || src_blk >= d1) {
+            if (lane == 0) raise_err(c.err, ERR_FIX);
+            continue;
+        }
+        Word* dw = reinterpret_cast<Word*>(seg + (uint64_t)dst_blk * b);
+        const Word* sw = reinterpret_cast<const Word*>(seg + (uint64_t)src_blk * b);
+        for (uint32_t i = lane; i < words; i += 64) dw[i] = sw[i];
+    }
+    if (threadIdx.x == 0) {
+        uint64_t w = d0, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
+        c.wr[td.slot_begin + j] = (w << 32) | (r & 0xffffffffull);
+    }
+}
+
+// ------------------------------------------------------ block permutation
+// Wavefront workers (Section 4.2).  A worker takes an unprocessed block from
+// its primary bucket by decrementing r_p (announcing itself in the bucket's
+// reader count first), classifies the block's first element to get its
+// destination bucket, and increments w_dest: if the block at the old w_dest
+// is unprocessed it swaps (reads that block, writes its own) and continues
+// with the block it read, unless that block already belongs to dest, in
+// which case it is left in place; if the old w_dest is empty it waits until
+// no worker is still reading from dest, writes its block there and goes back
+// to the primary bucket.  (w_i, r_i) live in one 64-bit word so that every
+// update sees a consistent pair.  A worker stops after a full cycle over the
+// buckets finds no unprocessed block.  The partial last block of a segment is
+// never written in place: the overflow block stands in for it.
+template <int DT, int WPL>
+__global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    using Word = typename TR::Word;
+    using Key = typename TR::Key;
+    __shared__ TreeLds<DT> trl;
+    const uint32_t lane = threadIdx.x & 63;
+    // workers are planned in groups of four, so a workgroup serves one task
+    // and shares one copy of its search tree in LDS
+    const uint32_t g0 = blockIdx.x * 4;
+    const uint32_t gw = g0 + (threadIdx.x >> 6);
+    const uint32_t t = upper_find(c.ntasks, g0, [&](uint32_t i) { return (uint64_t)c.tasks[i].worker_begin; });
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t b = c.b, K = st.K, lkt = ilog2(st.kt);
+    load_tree<DT>(c, td, st.kt, st.nuniq, trl);
+    const Key* gtree = trl.tree;
+    const Key* gspl = trl.spl;
+    if (gw >= c.total_workers || gw >= td.worker_begin + td.nworkers) return;
+    const uint32_t lw = gw - td.worker_begin;
+    uint64_t* wr = c.wr + td.slot_begin;
+    uint32_t* readers = c.readers + td.slot_begin;
+    const uint32_t* dl = c.delim + td.slot_begin + t;
+    Elem* seg = c.data + td.off;
+    constexpr uint32_t WPE = sizeof(Elem) / sizeof(Word);
+    const uint32_t words = b * WPE;
+    const bool partial = (td.m % b) != 0;
+    const uint32_t last_blk = st.nblocks - 1;
+    Word* ovf = reinterpret_cast<Word*>(c.ovf + (uint64_t)t * b);
+
+    // words of block blk that lie inside the segment (all of them except for
+    // a partial last block, which is never unprocessed and so never read)
+    auto valid_words = [&](uint32_t blk) -> uint32_t {
+        uint64_t rest = td.m - (uint64_t)blk * b;
+        return rest >= b ? words : (uint32_t)rest * WPE;
+    };
+    auto load_block = [&](uint32_t blk, Word (&r)[WPL]) {
+        const Word* src = reinterpret_cast<const Word*>(seg + (uint64_t)blk * b);
+        const uint32_t vw = valid_words(blk);
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            uint32_t w = lane + 64u * i;
+            if (w < vw) r[i] = src[w];
+        }
+    };
+    auto store_block = [&](uint32_t blk, const Word (&r)[WPL]) {
+        Word* dst = (partial && blk == last_blk) ? ovf : reinterpret_cast<Word*>(seg + (uint64_t)blk * b);
+#pragma unroll
+        for (int i = 0; i < WPL; ++i) {
+            uint32_t w = lane + 64u * i;
+            if (w < words) dst[w] = r[i];
+        }
+    };
+    // bucket of the first element of a block held in registers: its words
+    // sit in lanes 0..WPE-1 of register 0
+    auto first_bucket = [&](const Word (&r)[WPL]) -> uint32_t {
+        Elem e;
+        Word* ew = reinterpret_cast<Word*>(&e);
+#pragma unroll
+        for (uint32_t i = 0; i < WPE; ++i) {
+            if constexpr (sizeof(Word) == 8) {
+                uint32_t lo = read_lane((uint32_t)r[0], i), hi = read_lane((uint32_t)(r[0] >> 32), i);
+                ew[i] = ((uint64_t)hi << 32) | lo;
+            } else {
+                ew[i] = read_lane((uint32_t)r[0], i);
+            }
+        }
+        return classify_key(TR::key(e), gtree, gspl, lkt, st.nuniq, st.eq);
+    };
+
+    Word A[WPL], B[WPL];
+    uint32_t p = (uint32_t)(((uint64_t)lw * K) / td.nworkers);
+    unsigned long long moves = 0, skips = 0;
+    const uint32_t limit = c.spin_limit;
+    while (true) {
+        // ---- fetch an unprocessed block from the primary bucket (or the next ones)
+        bool got = false;
+        uint32_t destA = 0;
+        for (uint32_t scanned = 0; scanned < K;) {
+            // look at 64 buckets at once, starting at p
+            uint32_t q = p + lane;
+            if (q >= K) q -= K;
+            bool cand = false;
+            if (scanned + lane < K) {
+                uint64_t v = __hip_atomic_load(&wr[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int64_t w = (int64_t)(v >> 32), r = (int64_t)(v & 0xffffffffull) - 0x80000000ll;
+                cand = r >= w;
+            }
+            uint64_t mask = __ballot(cand);
+            if (mask == 0) {
+                uint32_t adv = (K - scanned) < 64 ? (K - scanned) : 64;
+                scanned += adv;
+                p += adv;
+                if (p >= K) p -= K;
+                continue;
+            }
+            uint32_t first = __ffsll((long long)mask) - 1;
+            scanned += first;
+            p += first;
+            if (p >= K) p -= K;
+            // try to claim a block of bucket p
+            uint64_t old = 0;
+            if (lane == 0) {
+                __hip_atomic_fetch_add(&readers[p], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                old = __hip_atomic_fetch_add(&wr[p], ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            old = bcast_u64(old);
+            int64_t w0 = (int64_t)(old >> 32), r0 = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
+            if (r0 >= w0) {
+                load_block((uint32_t)r0, A);
+                wait_vmem();
+                if (lane == 0)
+                    __hip_atomic_fetch_add(&readers[p], ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                destA = first_bucket(A);
+                got = true;
+                break;
+            }
+            if (lane == 0)
+                __hip_atomic_fetch_add(&readers[p], ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!got) break;
+        // ---- place the block, swapping along the way
+        while (true) {
+            uint64_t old = 0;
+            if (lane == 0)
+                old = __hip_atomic_fetch_add(&wr[destA], 1ull << 32, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+            old = bcast_u64(old);
+            int64_t x = (int64_t)(old >> 32), r = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
+            if (x >= (int64_t)dl[destA + 1] || x < 0) {   // cannot happen for consistent counts
+                if (lane == 0) raise_err(c.err, ERR_PERMUTE_RANGE);
+                break;
+            }
+            if (x <= r && partial && (uint32_t)x == last_blk) {   // never unprocessed
+                if (lane == 0) raise_err(c.err, ERR_PERMUTE_RANGE);
+                break;
+            }
+            if (x <= r) {
+                // unprocessed block at x: read it, then decide
+                load_block((uint32_t)x, B);
+                wait_vmem();
+                uint32_t destB = first_bucket(B);
+                if (destB == destA && c.skip_inplace) {
+                    ++skips;
+                    continue;                       // already in place; w moved past it
+                }
+                store_block((uint32_t)x, A);
+                ++moves;
+#pragma unroll
+                for (int i = 0; i < WPL; ++i) A[i] = B[i];
+                destA = destB;
+                continue;
+            }
+            // empty block at x: wait for readers of dest, then write
+            uint32_t spins = 0;
+            while (true) {
+                uint32_t rd = 0;
+                if (lane == 0) rd = __hip_atomic_load(&readers[destA], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                rd = bcast_u32(rd);
+                if (rd == 0) break;
+                if (++spins > limit) {
+                    if (lane == 0) raise_err(c.err, ERR_SPIN);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            store_block((uint32_t)x, A);
+            ++moves;
+            if (partial && (uint32_t)x == last_blk && lane == 0) c.ts[t].ovf_bucket = destA;
+            break;
+        }
+    }
+    if (lane == 0) {
+        atomicAdd(&c.stats[0], moves);
+        atomicAdd(&c.stats[1], skips);
+    }
+}
+
+// ---------------------------------------------------------------- cleanup
+// One workgroup per bucket slot, in ticket order (Section 4.3).  Bucket i
+// owns [B_i, B_{i+1}).  After the permutation its full blocks fill
+// [d_i b, w_i b), except that a block written to the partial last block went
+// to the overflow block.  Elements still to place: the overhang
+// [B_{i+1}, w_i b) (bucket-i data inside bucket i+1's head), the partial
+// buffers of every stripe of the task, and the overflow block if bucket i
+// wrote it.  Free positions: the head [B_i, min(d_i b, B_{i+1})) and the tail
+// after the full blocks.  Bucket i first copies its overhang to LDS and
+// raises its flag; it writes only after bucket i-1 has raised its flag,
+// because bucket i-1's overhang sits in bucket i's head.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
+    using Elem = typename Traits<DT>::Elem;
+    __shared__ uint32_t gsh;
+    __shared__ uint32_t pre[STRIPES_PER_TASK_MAX + 3];
+    __shared__ uint32_t sh[NT / 64 + 1];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Elem* oh = reinterpret_cast<Elem*>(smem_raw);   // overhang, < b elements
+    if (threadIdx.x == 0) gsh = atomicAdd(c.ticket, 1u);
+    __syncthreads();
+    const uint32_t g = gsh;
+    if (g >= c.total_slots) return;
+    const uint32_t t = upper_find(c.ntasks, g, [&](uint32_t i) { return (uint64_t)c.tasks[i].slot_begin; });
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = g - td.slot_begin;
+    if (j >= st.K) return;
+    const uint32_t b = c.b;
+    const uint64_t* bd = c.bounds + td.slot_begin + t;
+    const uint32_t* dl = c.delim + td.slot_begin + t;
+    const uint64_t B0 = bd[j], B1 = bd[j + 1];
+    const uint64_t cs = (uint64_t)dl[j] * b;
+    const uint64_t w = c.wr[td.slot_begin + j] >> 32;
+    const bool ovf_case = st.ovf_bucket == j;
+    // end of the correct full blocks (no blocks: the region is empty at cs;
+    // with blocks the bucket holds at least b elements, so cs < B1)
+    const bool has_blocks = w > dl[j];
+    const uint64_t ce = !has_blocks ? cs : (ovf_case ? (uint64_t)(st.nblocks - 1) * b : w * b);
+    Elem* seg = c.data + td.off;
+    // overhang: bucket-j elements of the last full block beyond B1
+    uint64_t ohn = (has_blocks && !ovf_case && ce > B1) ? ce - B1 : 0;
+    if (B1 + ohn > td.m || ohn >= b) {   // cannot happen for consistent state
+        if (threadIdx.x == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        ohn = 0;
+    }
+    for (uint32_t i = threadIdx.x; i < ohn; i += NT) oh[i] = seg[B1 + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(&c.flags[td.slot_begin + j], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (j > 0) {
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&c.flags[td.slot_begin + j - 1], __ATOMIC_ACQUIRE,
+                                     __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                if (++spins > c.spin_limit) { raise_err(c.err, ERR_SPIN); break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    __syncthreads();
+    // sources: [overhang | buffer of stripe 0 | ... | buffer of stripe ns-1 | overflow]
+    const uint32_t ns = td.nstripes;
+    for (uint32_t q = threadIdx.x; q < ns + 2; q += NT) {
+        uint32_t v;
+        if (q == 0) v = (uint32_t)ohn;
+        else if (q <= ns) v = c.counts[(uint64_t)(td.stripe_begin + q - 1) * KMAX + j] % b;
+        else v = ovf_case ? b : 0;
+        pre[q] = v;
+    }
+    __syncthreads();
+    const uint32_t nsrc = lds_excl_scan<NT>(pre, ns + 2, sh);
+    // free positions: head [B0, he) and tail [tb, B1)
+    const uint64_t he = cs < B1 ? cs : B1;
+    const uint64_t tb0 = ce > cs ? ce : cs;
+    const uint64_t tb = tb0 < B1 ? tb0 : B1;
+    const uint64_t nhead = he - B0, nfree = nhead + (B1 - tb);
+    if (nfree != nsrc) {
+        if (threadIdx.x == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        return;
+    }
+    const Elem* ovfp = c.ovf + (uint64_t)t * b;
+    for (uint32_t x = threadIdx.x; x < nsrc; x += NT) {
+        uint32_t q = upper_find(ns + 2, x, [&](uint32_t i) { return (uint64_t)pre[i]; });
+        while (q + 1 < ns + 2 && pre[q + 1] <= x) ++q;
+        uint32_t o = x - pre[q];
+        Elem e;
+        if (q == 0) e = oh[o];
+        else if (q <= ns) e = c.bufs[c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b + o];
+        else e = ovfp[o];
+        uint64_t dst = x < nhead ? B0 + x : tb + (x - nhead);
+        seg[dst] = e;
+    }
+}
+
+// -------------------------------------------------------------- base case
+// Sorts each listed segment (<= the LDS capacity) inside one workgroup's
+// LDS.  Network: bitonic sort in its "mirror" form, where every
+// compare-exchange puts the smaller key at the lower index; positions at or
+// beyond the segment length act as +infinity and never move, so any length
+// is sorted without padding.  u64/f64 sort the keys themselves (f64 through
+// the bijective totalOrder image); records sort (key, index) pairs and then
+// gather whole records through the workgroup's scratch slot.
+struct SegD {
+    uint64_t off;
+    uint32_t len;
+    uint32_t pad;
+};
+
+template <class Key>
+struct KeyIdx {
+    Key k;
+    uint32_t i;
+};
+
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, uint32_t nseg,
+                                                 typename Traits<DT>::Elem* scratch) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    using Key = typename TR::Key;
+    constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
+        const SegD sg = segs[si];
+        const uint32_t len = sg.len;
+        Elem* seg = c.data + sg.off;
+        uint32_t P = 1;
+        while (P < len) P <<= 1;
+        if constexpr (kPlain) {
+            uint64_t* keys = reinterpret_cast<uint64_t*>(smem_raw);
+            for (uint32_t i = threadIdx.x; i < len; i += NT) keys[i] = TR::key(seg[i]).v;
+            __syncthreads();
+            for (uint32_t size = 2; size <= P; size <<= 1) {
+                const uint32_t half = size >> 1;
+                for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
+                    uint32_t blk = x / half, o = x % half;
+                    uint32_t i = blk * size + o, jj = blk * size + size - 1 - o;
+                    if (jj < len) {
+                        uint64_t a = keys[i], bb = keys[jj];
+                        if (bb < a) { keys[i] = bb; keys[jj] = a; }
+                    }
+                }
+                __syncthreads();
+                for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
+                    for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
+                        uint32_t i = (x / stride) * 2 * stride + (x % stride), jj = i + stride;
+                        if (jj < len) {
+                            uint64_t a = keys[i], bb = keys[jj];
+                            if (bb < a) { keys[i] = bb; keys[jj] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < len; i += NT) {
+                if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(keys[i]);
+                else seg[i] = keys[i];
+            }
+            __syncthreads();
+        } else {
+            KeyIdx<Key>* kv = reinterpret_cast<KeyIdx<Key>*>(smem_raw);
+            Elem* scr = scratch + (uint64_t)blockIdx.x * TR::kBaseCap;
+            for (uint32_t i = threadIdx.x; i < len; i += NT) {
+                Elem e = seg[i];
+                scr[i] = e;
+                kv[i].k = TR::key(e);
+                kv[i].i = i;
+            }
+            __syncthreads();
+            for (uint32_t size = 2; size <= P; size <<= 1) {
+                const uint32_t half = size >> 1;
+                for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
+                    uint32_t blk = x / half, o = x % half;
+                    uint32_t i = blk * size + o, jj = blk * size + size - 1 - o;
+                    if (jj < len) {
+                        KeyIdx<Key> a = kv[i], bb = kv[jj];
+                        if (bb.k < a.k) { kv[i] = bb; kv[jj] = a; }
+                    }
+                }
+                __syncthreads();
+                for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
+                    for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
+                        uint32_t i = (x / stride) * 2 * stride + (x % stride), jj = i + stride;
+                        if (jj < len) {
+                            KeyIdx<Key> a = kv[i], bb = kv[jj];
+                            if (bb.k < a.k) { kv[i] = bb; kv[jj] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < len; i += NT) seg[i] = scr[kv[i].i];
+            __syncthreads();
+        }
+    }
+}
+
+// --------------------------------------------------- bucket ids (classify)
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_bucket_ids(Ctx<DT> c, uint64_t n, uint32_t* out) {
+    using TR = Traits<DT>;
+    __shared__ TreeLds<DT> tr;
+    const TaskS st = c.ts[0];
+    load_tree<DT>(c, c.tasks[0], st.kt, st.nuniq, tr);
+    const uint32_t lkt = ilog2(st.kt);
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * NT)
+        out[i] = classify_key(TR::key(c.data[i]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
+}
+
+}  // namespace ips4o

@@ -12,6 +12,13 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    # build what is missing (only then): the HIP library, the oracle, the generators
+    from paper_1705_02257_amd.build import build_library
+    build_library(force=False)
+    import oracle
+    import workloads
+    oracle.build()
+    workloads.build()
 
 
 def golden_lines(name):

@@ -1,0 +1,261 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Keys are compared bit-exactly; bucket boundaries and bucket ids exactly;
+records by keys exactly plus payload checks (payload = original index, so the
+output must be a permutation whose every record equals the input record its
+payload names).  Sizes span several tiles and blocks with ragged tails."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DISTS = workloads.DISTRIBUTIONS
+SHAPE_TAIL = {"u64": (), "f64": (), "pair": (2,), "quartet": (4,), "bytes100": (100,)}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1705_02257_amd as ips
+    oracle.build()
+    workloads.build()
+    h = ips.handle(0)
+    return torch, ips, h
+
+
+def to_dev(torch, arr):
+    flat = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
+    return torch.from_numpy(flat.copy()).to("cuda:0")
+
+
+def from_dev(t, like):
+    return t.cpu().numpy().view(like.dtype).reshape(like.shape)
+
+
+def gpu_sort(env, arr, dtype, params=None):
+    torch, ips, h = env
+    d = to_dev(torch, arr)
+    ips.ips4o_sort(h, d, arr.shape[0], dtype, params)
+    torch.cuda.synchronize()
+    return from_dev(d, arr)
+
+
+def keys_of(arr, dtype):
+    if dtype in ("u64", "f64"):
+        return arr.view(np.uint64)
+    if dtype == "pair":
+        return arr[:, :1]
+    if dtype == "quartet":
+        return arr[:, :3]
+    return arr[:, :10]
+
+
+def payload_of(arr, dtype):
+    if dtype in ("pair", "quartet"):
+        return arr[:, -1].astype(np.int64)
+    return arr[:, 10:18].copy().view(np.uint64).ravel().astype(np.int64)
+
+
+def same_multiset(a, b):
+    """Equal as multisets of whole elements (rows compared bytewise)."""
+    rb = a.dtype.itemsize * (a.shape[1] if a.ndim == 2 else 1)
+    va = np.ascontiguousarray(a).view(np.dtype((np.void, rb))).ravel()
+    vb = np.ascontiguousarray(b).view(np.dtype((np.void, rb))).ravel()
+    return np.array_equal(np.sort(va), np.sort(vb))
+
+
+def assert_sorted_like_oracle(out, inp, dtype):
+    ref = oracle.sort(inp, dtype)
+    assert np.array_equal(keys_of(out, dtype), keys_of(ref, dtype)), "keys differ from the oracle"
+    if dtype in ("u64", "f64"):
+        assert np.array_equal(out.view(np.uint64), ref.view(np.uint64))
+    else:
+        pay = payload_of(out, dtype)
+        assert np.array_equal(np.sort(pay), np.arange(inp.shape[0]))
+        assert np.array_equal(out, inp[pay]), "a record was torn or mixed"
+
+
+# ------------------------------------------------------------- full sort
+@pytest.mark.parametrize("dtype", ["u64", "f64"])
+@pytest.mark.parametrize("dist", DISTS)
+def test_sort_2pow20_all_distributions(env, dtype, dist):
+    """The small configuration: 2^20 keys, k = 256, b = 2 KiB, every
+    distribution, keys bit-exact against the oracle."""
+    n = 1 << 20
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(0, dist, dtype))
+    print(f"[gpu] sort {dtype} {dist} n={n}", flush=True)
+    out = gpu_sort(env, inp, dtype, {"k": 256, "block_bytes": 2048})
+    assert_sorted_like_oracle(out, inp, dtype)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 17, 255, 256, 257, 4095, 16384, 16385, 65535, 65536,
+                               65537, 100003, 262147, 1000003])
+def test_sort_sizes_u64(env, n):
+    inp = workloads.generate("uniform", "u64", n, 1000 + n)
+    print(f"[gpu] sort u64 uniform n={n}", flush=True)
+    out = gpu_sort(env, inp, "u64")
+    assert_sorted_like_oracle(out, inp, "u64")
+
+
+@pytest.mark.parametrize("dtype", ["pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("dist", ["uniform", "rootdup", "sorted", "ones"])
+@pytest.mark.parametrize("n", [5000, 300007])
+def test_sort_records(env, dtype, dist, n):
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(2, dist, dtype))
+    print(f"[gpu] sort {dtype} {dist} n={n}", flush=True)
+    out = gpu_sort(env, inp, dtype)
+    assert_sorted_like_oracle(out, inp, dtype)
+
+
+def test_sort_f64_special_values(env):
+    """Signed zeros, infinities, NaNs with payloads and subnormals sort by
+    IEEE totalOrder with their bit patterns intact."""
+    rng = np.random.default_rng(5)
+    specials = np.array([0x0000000000000000, 0x8000000000000000, 0x7ff0000000000000,
+                         0xfff0000000000000, 0x7ff8000000000000, 0xfff8000000000000,
+                         0x7ff0000000000001, 0xfff0000000000123, 0x0000000000000001,
+                         0x8000000000000001, 0x000fffffffffffff, 0x7fefffffffffffff],
+                        dtype=np.uint64)
+    n = 200003
+    base = workloads.generate("uniform", "u64", n, 77)
+    idx = rng.integers(0, n, 30000)
+    base[idx] = specials[rng.integers(0, specials.shape[0], idx.shape[0])]
+    inp = base.view(np.float64)
+    out = gpu_sort(env, inp, "f64")
+    assert_sorted_like_oracle(out, inp, "f64")
+
+
+def test_sort_robust_to_parameters(env):
+    """The same input sorts to the same keys under different bucket counts,
+    block sizes, stripe and worker counts, and with skipping disabled."""
+    n = 700001
+    inp = workloads.generate("twodup", "u64", n, 31)
+    ref = oracle.sort(inp, "u64")
+    for params in [{"k": 2}, {"k": 16}, {"k": 512}, {"block_bytes": 512}, {"block_bytes": 8192},
+                   {"stripes": 1}, {"stripes": 7}, {"workers": 4}, {"workers": 64},
+                   {"flags": 1}, {"alpha_x100": 100}, {"base_cap": 1000}, {"seed": 12345}]:
+        print(f"[gpu] sort u64 twodup n={n} params={params}", flush=True)
+        out = gpu_sort(env, inp, "u64", params)
+        assert np.array_equal(out, ref), params
+
+
+# ---------------------------------------------------- one distribution step
+def _splitters(inp, dtype, m, seed, dup=False):
+    srt = oracle.sort(inp, dtype)
+    rng = np.random.default_rng(seed)
+    pos = np.sort(rng.integers(0, inp.shape[0], m))
+    if dup:
+        pos[1::3] = pos[0::3][:pos[1::3].shape[0]]
+        pos = np.sort(pos)
+    return srt[pos]
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("eq", [False, True])
+@pytest.mark.parametrize("m,n", [(1, 1000), (15, 65537), (255, 300001), (511, 1 << 18)])
+def test_distribute_parity(env, dtype, eq, m, n):
+    """Boundaries equal the oracle's exactly; each bucket's range holds exactly
+    the elements the oracle's bucket rule assigns to it."""
+    torch, ips, h = env
+    dist = "rootdup" if eq else "uniform"
+    inp = workloads.generate(dist, dtype, n, 4242 + m)
+    sp = _splitters(inp, dtype, m, m, dup=eq)
+    counts, bounds = oracle.bucket_bounds(inp, sp, dtype, eq)
+    d = to_dev(torch, inp)
+    print(f"[gpu] distribute {dtype} eq={eq} m={m} n={n}", flush=True)
+    gb = ips.ips4o_distribute(h, d, n, dtype, sp, eq)
+    out = from_dev(d, inp)
+    assert np.array_equal(gb, bounds)
+    ids = oracle.classify(out, sp, dtype, eq).astype(np.int64)
+    want = np.repeat(np.arange(counts.shape[0]), counts.astype(np.int64))
+    assert np.array_equal(ids, want)
+    assert same_multiset(out, inp)
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 513])
+def test_distribute_tiny(env, n):
+    torch, ips, h = env
+    inp = workloads.generate("uniform", "u64", n, 9 + n)
+    sp = np.sort(inp[: min(n, 5)]).astype(np.uint64)
+    for eq in (False, True):
+        counts, bounds = oracle.bucket_bounds(inp, sp, "u64", eq)
+        d = to_dev(torch, inp)
+        gb = ips.ips4o_distribute(h, d, n, "u64", sp, eq)
+        out = from_dev(d, inp)
+        assert np.array_equal(gb, bounds)
+        ids = oracle.classify(out, sp, "u64", eq).astype(np.int64)
+        assert np.array_equal(ids, np.repeat(np.arange(counts.shape[0]), counts.astype(np.int64)))
+
+
+# ------------------------------------------------------- classification
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("eq", [False, True])
+def test_classify_parity(env, dtype, eq):
+    torch, ips, h = env
+    n = 100003
+    inp = workloads.generate("eightdup", dtype, n, 5)
+    for m in (1, 2, 7, 64, 255, 511):
+        sp = _splitters(inp, dtype, m, 100 + m, dup=True)
+        d = to_dev(torch, inp)
+        out = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+        ips.ips4o_classify(h, d, n, dtype, sp, eq, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, oracle.classify(inp, sp, dtype, eq)), (m, eq)
+
+
+# -------------------------------------------------------------- sampling
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("dist", ["uniform", "rootdup", "ones"])
+def test_select_splitters_parity(env, dtype, dist):
+    torch, ips, h = env
+    n = 200000
+    inp = workloads.generate(dist, dtype, n, 3)
+    for k in (2, 16, 256):
+        alpha = oracle.alpha_default(n)
+        seed = 0xABCDEF + k
+        want, weq = oracle.select_splitters(inp, dtype, k, alpha, seed)
+        d = to_dev(torch, inp)
+        got, geq = ips.ips4o_select_splitters(h, d, n, dtype, {"k": k, "seed": seed}, like=inp)
+        assert geq == weq
+        assert np.array_equal(keys_of(got, dtype), keys_of(want, dtype)), (k, dist)
+
+
+# -------------------------------------------------- full size (2^30 keys)
+def test_sort_2pow30_properties(env):
+    """At the full size (2^30 u64 Uniform): sorted, the same multiset (sum of
+    a mixing hash), and at sampled ranks r the output value v has
+    #{input < v} <= r < #{input <= v}, counted on the untouched input."""
+    torch, ips, h = env
+    n = 1 << 30
+    inp = workloads.generate("uniform", "u64", n, workloads.seed_for(1, "uniform", "u64"))
+    d = torch.from_numpy(inp.view(np.int64)).to("cuda:0")
+    del inp
+    d0 = d.clone()
+    sign = torch.tensor(-(1 << 63), dtype=torch.int64, device="cuda:0")
+
+    def mixhash(t):
+        z = t * 0x5851F42D4C957F2D + 0x14057B7EF767814F
+        return z ^ (z >> 29)
+
+    h0 = int(mixhash(d0).sum())
+    print("[gpu] sort u64 uniform n=2^30", flush=True)
+    ips.ips4o_sort(h, d, n, "u64")
+    torch.cuda.synchronize()
+    s = torch.bitwise_xor(d, sign)      # unsigned order as signed order
+    s0 = torch.bitwise_xor(d0, sign)
+    assert bool((s[1:] >= s[:-1]).all())
+    assert int(mixhash(d).sum()) == h0
+    rng = np.random.default_rng(1)
+    for r in rng.integers(0, n, 4):
+        v = s[int(r)]
+        assert int((s0 < v).sum()) <= int(r) < int((s0 <= v).sum())
+    del d, d0, s, s0
+    torch.cuda.empty_cache()

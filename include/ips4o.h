@@ -93,6 +93,7 @@ typedef struct {
 } ips4o_params;
 
 #define IPS4O_FLAG_NO_SKIP 1u   /* do not skip blocks already in place during the permutation */
+#define IPS4O_FLAG_TIMING  2u   /* time every kernel launch with HIP events on the call's stream */
 
 typedef struct ips4o_handle ips4o_handle;
 
@@ -190,6 +191,24 @@ typedef struct {
 } ips4o_stats;
 
 int ips4o_last_stats(const ips4o_handle *h, ips4o_stats *out);
+
+/* Per-kernel device time of the most recent ips4o_sort / ips4o_distribute
+ * made with IPS4O_FLAG_TIMING (zeros otherwise), from HIP events recorded
+ * around each launch on the call's stream.  out[] has IPS4O_KERNEL_KINDS
+ * entries in this order: sample, classify, scan, fix_empty, permute,
+ * cleanup, basecase.  alg_bytes is the data the launches had to move by the
+ * method's definition: 2*s per element classified, per element of a moved
+ * block (permutation and empty-block fix), per element placed by cleanup and
+ * per element sorted by the base case. */
+#define IPS4O_KERNEL_KINDS 7
+typedef struct {
+    uint32_t launches;
+    uint32_t reserved;
+    double ms;
+    double alg_bytes;
+} ips4o_kernel_stat;
+
+int ips4o_last_kernel_stats(const ips4o_handle *h, ips4o_kernel_stat *out);
 
 #ifdef __cplusplus
 }

@@ -7,8 +7,8 @@ the library.  The functions carry the C ABI's names (include/ips4o.h); array
 arguments may be torch tensors on the handle's GPU (their data_ptr() is
 passed) or raw device addresses as ints.  Host-side arrays (splitters,
 bounds) are numpy arrays.  A nonzero status raises Ips4oError.  The library
-must have been built (``python -m paper_1705_02257_amd.build``); importing
-this module without it raises ImportError -- there is no fallback path.
+must have been built (``python paper_1705_02257_amd/build.py``); the first
+call without it raises ImportError -- there is no fallback path.
 """
 import ctypes
 import os
@@ -30,7 +30,8 @@ FLAG_NO_SKIP = 1
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",
            "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters", "ips4o_sync",
-           "ips4o_status_string", "ips4o_last_stats", "ips4o_check_args", "ips4o_check_splitters"]
+           "ips4o_status_string", "ips4o_last_stats", "ips4o_check_args", "ips4o_check_splitters",
+           "ips4o_last_kernel_stats"]
 
 
 class Ips4oError(RuntimeError):
@@ -53,10 +54,19 @@ class Stats(ctypes.Structure):
                 ("elements_base", ctypes.c_uint64), ("elements_distributed", ctypes.c_uint64)]
 
 
+KERNEL_KINDS = ["sample", "classify", "scan", "fix_empty", "permute", "cleanup", "basecase"]
+FLAG_TIMING = 2
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_1705_02257_amd.build` (no CPU fallback exists)")
+                          "`python paper_1705_02257_amd/build.py` (no CPU fallback exists)")
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     L.ips4o_create.argtypes = [i32, ctypes.POINTER(vp)]
@@ -75,14 +85,29 @@ def _load():
     L.ips4o_status_string.argtypes = [i32]
     L.ips4o_status_string.restype = ctypes.c_char_p
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
-                 "ips4o_check_args", "ips4o_check_splitters"]:
+                 "ips4o_check_args", "ips4o_check_splitters", "ips4o_last_kernel_stats"]:
         getattr(L, name).restype = i32
     return L
 
 
-lib = _load()
+_lib_cache = None
+
+
+def _L():
+    """The loaded library (loaded on first use; raises if it was never built)."""
+    global _lib_cache
+    if _lib_cache is None:
+        _lib_cache = _load()
+    return _lib_cache
+
+
+def __getattr__(name):
+    if name == "lib":
+        return _L()
+    raise AttributeError(name)
 
 
 def _dtype(dt):
@@ -133,27 +158,27 @@ def n_elements(t, dtype):
 
 
 def ips4o_status_string(status: int) -> str:
-    return lib.ips4o_status_string(status).decode()
+    return _L().ips4o_status_string(status).decode()
 
 
 def ips4o_create(device: int = 0) -> int:
     h = ctypes.c_void_p()
-    _check(lib.ips4o_create(device, ctypes.byref(h)), "ips4o_create")
+    _check(_L().ips4o_create(device, ctypes.byref(h)), "ips4o_create")
     return h.value
 
 
 def ips4o_destroy(h: int) -> None:
-    lib.ips4o_destroy(h)
+    _L().ips4o_destroy(h)
 
 
 def ips4o_workspace_bytes(h: int) -> int:
     v = ctypes.c_size_t()
-    _check(lib.ips4o_workspace_bytes(h, ctypes.byref(v)), "ips4o_workspace_bytes")
+    _check(_L().ips4o_workspace_bytes(h, ctypes.byref(v)), "ips4o_workspace_bytes")
     return v.value
 
 
 def ips4o_sort(h, data, n, dtype, params=None, stream=None) -> None:
-    _check(lib.ips4o_sort(h, _addr(data), n, _dtype(dtype), _params(params), _stream(stream)),
+    _check(_L().ips4o_sort(h, _addr(data), n, _dtype(dtype), _params(params), _stream(stream)),
            "ips4o_sort", h)
 
 
@@ -163,7 +188,7 @@ def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets:
     m = sp.shape[0]
     bounds = np.zeros(2 * m + 2, dtype=np.uint64)
     K = ctypes.c_uint32(0)
-    _check(lib.ips4o_distribute(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, m,
+    _check(_L().ips4o_distribute(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, m,
                                 int(bool(equality_buckets)), bounds.ctypes.data, ctypes.byref(K),
                                 _params(params), _stream(stream)), "ips4o_distribute", h)
     return bounds[:K.value + 1].copy()
@@ -172,7 +197,7 @@ def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets:
 def ips4o_classify(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool, out,
                    stream=None) -> None:
     sp = np.ascontiguousarray(splitters)
-    _check(lib.ips4o_classify(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, sp.shape[0],
+    _check(_L().ips4o_classify(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, sp.shape[0],
                               int(bool(equality_buckets)), _addr(out), _stream(stream)),
            "ips4o_classify")
 
@@ -188,7 +213,7 @@ def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np
     out = np.zeros((k - 1) * s, dtype=np.uint8)
     nu = ctypes.c_uint32(0)
     eq = ctypes.c_int(0)
-    _check(lib.ips4o_select_splitters(h, _addr(data), n, d, _params(params), out.ctypes.data,
+    _check(_L().ips4o_select_splitters(h, _addr(data), n, d, _params(params), out.ctypes.data,
                                       ctypes.byref(nu), ctypes.byref(eq), _stream(stream)),
            "ips4o_select_splitters")
     raw = out[:nu.value * s]
@@ -198,13 +223,21 @@ def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np
 
 
 def ips4o_sync(h, stream=None) -> None:
-    _check(lib.ips4o_sync(h, _stream(stream)), "ips4o_sync")
+    _check(_L().ips4o_sync(h, _stream(stream)), "ips4o_sync")
 
 
 def ips4o_last_stats(h) -> dict:
     st = Stats()
-    _check(lib.ips4o_last_stats(h, ctypes.byref(st)), "ips4o_last_stats")
+    _check(_L().ips4o_last_stats(h, ctypes.byref(st)), "ips4o_last_stats")
     return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+
+def ips4o_last_kernel_stats(h) -> dict:
+    """{kernel kind: {launches, ms, alg_bytes}} of the last timed call."""
+    arr = (KernelStat * len(KERNEL_KINDS))()
+    _check(_L().ips4o_last_kernel_stats(h, arr), "ips4o_last_kernel_stats")
+    return {name: {"launches": arr[i].launches, "ms": arr[i].ms, "alg_bytes": arr[i].alg_bytes}
+            for i, name in enumerate(KERNEL_KINDS)}
 
 
 _handles = {}

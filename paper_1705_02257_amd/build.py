@@ -1,6 +1,6 @@
 """Build libips4o.so (the HIP library behind include/ips4o.h) for gfx950.
 
-    python -m paper_1705_02257_amd.build        # or build_library() from Python
+    python paper_1705_02257_amd/build.py        # or build_library() from Python
 
 hipcc cross-compiles here; no GPU is needed to build.
 """

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -95,6 +96,8 @@ struct Seg {
 
 }  // namespace
 
+enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_BASE, KK_N };
+
 struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
@@ -103,8 +106,67 @@ struct ips4o_handle {
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
     ips4o_stats last{};
+    ips4o_kernel_stat kstats[KK_N]{};
+    std::vector<hipEvent_t> events;   // pool for IPS4O_FLAG_TIMING
     hipError_t last_hip = hipSuccess;
 };
+
+namespace {
+
+// HIP events around every launch of one call (only with IPS4O_FLAG_TIMING).
+struct Timer {
+    ips4o_handle* h;
+    hipStream_t st;
+    bool on;
+    struct Rec {
+        int kind;
+        size_t e0;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    size_t used = 0;
+    Timer(ips4o_handle* hh, hipStream_t s, bool enabled) : h(hh), st(s), on(enabled) {}
+    hipEvent_t ev(size_t i) {
+        while (h->events.size() <= i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            h->events.push_back(e);
+        }
+        return h->events[i];
+    }
+    int begin(int kind) {
+        if (!on) return -1;
+        hipEvent_t e = ev(used);
+        if (!e || !ev(used + 1)) { on = false; return -1; }
+        (void)hipEventRecord(e, st);
+        recs.push_back(Rec{kind, used, 0.0});
+        used += 2;
+        return (int)recs.size() - 1;
+    }
+    void end(int idx, double bytes) {
+        if (!on || idx < 0) return;
+        (void)hipEventRecord(h->events[recs[idx].e0 + 1], st);
+        recs[idx].bytes = bytes;
+    }
+    void set_bytes(int idx, double bytes) {
+        if (on && idx >= 0) recs[idx].bytes = bytes;
+    }
+    // after the stream has been synchronized
+    void finish() {
+        for (auto& k : h->kstats) k = ips4o_kernel_stat{};
+        if (!on) return;
+        for (const Rec& r : recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, h->events[r.e0], h->events[r.e0 + 1]) != hipSuccess) ms = 0.f;
+            ips4o_kernel_stat& k = h->kstats[r.kind];
+            k.launches += 1;
+            k.ms += ms;
+            k.alg_bytes += r.bytes;
+        }
+    }
+};
+
+}  // namespace
 
 #define HIP_TRY(expr)                                  \
     do {                                               \
@@ -146,6 +208,15 @@ int resolve(const ips4o_params* p, Resolved* r) {
     r->spin = d.spin_limit ? d.spin_limit : kDefaultSpin;
     r->seed = d.seed ? d.seed : kDefaultSeed;
     return IPS4O_OK;
+}
+
+bool log_enabled() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = std::getenv("IPS4O_LOG");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
 }
 
 uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k) {
@@ -374,8 +445,13 @@ hipError_t launch_permute(const Ctx<DT>& c, hipStream_t st) {
     return launch_permute_wpl<DT, 32>(c, st);
 }
 
+struct LevelMarks {    // timer records whose byte counts are known after the level
+    int fix = -1, permute = -1, cleanup = -1;
+};
+
 template <int DT>
-int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given) {
+int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
+              LevelMarks& mk) {
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     constexpr int CNT = Shape<DT>::CNT, EPT = Shape<DT>::EPT;
@@ -388,25 +464,49 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
         HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(c.ts, &given->ts, sizeof(TaskS), hipMemcpyHostToDevice, st));
     } else {
+        int r = tm.begin(KK_SAMPLE);
         hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
         HIP_TRY(hipGetLastError());
+        tm.end(r, 0.0);
     }
+    uint64_t level_m = 0;
+    for (const TaskD& t : L.tasks) level_m += t.m;
     const size_t cls_lds = sizeof(ClassifyLds<DT, CNT, EPT>);
     HIP_TRY(hipFuncSetAttribute((const void*)k_classify<DT, CNT, EPT>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)cls_lds));
+    int r = tm.begin(KK_CLASSIFY);
     hipLaunchKernelGGL((k_classify<DT, CNT, EPT>), dim3(S), dim3(CNT), cls_lds, st, c);
     HIP_TRY(hipGetLastError());
+    tm.end(r, 2.0 * sizeof(Elem) * (double)level_m);
+    r = tm.begin(KK_SCAN);
     hipLaunchKernelGGL((k_scan<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
     HIP_TRY(hipGetLastError());
+    tm.end(r, 0.0);
+    mk.fix = tm.begin(KK_FIX);
     hipLaunchKernelGGL((k_fix_empty<DT, 256>), dim3(L.total_slots), dim3(256), 0, st, c);
     HIP_TRY(hipGetLastError());
+    tm.end(mk.fix, 0.0);
+    mk.permute = tm.begin(KK_PERMUTE);
     HIP_TRY(launch_permute<DT>(c, st));
+    tm.end(mk.permute, 0.0);
     const size_t cl_lds = (size_t)c.b * sizeof(Elem);
     HIP_TRY(hipFuncSetAttribute((const void*)k_cleanup<DT, 256>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)cl_lds));
+    mk.cleanup = tm.begin(KK_CLEANUP);
     hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(L.total_slots), dim3(256), cl_lds, st, c);
     HIP_TRY(hipGetLastError());
+    tm.end(mk.cleanup, 0.0);
     return IPS4O_OK;
+}
+
+// bytes of the launches whose amount of work is counted on the device
+template <int DT>
+void account_level(Timer& tm, const LevelMarks& mk, const unsigned long long* now,
+                   const unsigned long long* before, uint32_t b) {
+    const double s = (double)sizeof(typename Traits<DT>::Elem);
+    tm.set_bytes(mk.permute, 2.0 * s * b * (double)(now[0] - before[0]));
+    tm.set_bytes(mk.cleanup, 2.0 * s * (double)(now[2] - before[2]));
+    tm.set_bytes(mk.fix, 2.0 * s * b * (double)(now[3] - before[3]));
 }
 
 int check_device_error(ips4o_handle* h, hipStream_t st) {
@@ -433,13 +533,13 @@ int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>
     bounds.resize(L.total_slots + T);
     HIP_TRY(hipMemcpyAsync(ts.data(), L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(bounds.data(), L.c.bounds, bounds.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(stats, L.c.stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stats, L.c.stats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     return check_device_error(h, st);
 }
 
 template <int DT>
 int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, const Resolved& R,
-                 hipStream_t st) {
+                 hipStream_t st, Timer& tm) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     using Key = typename TR::Key;
@@ -460,9 +560,13 @@ int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, c
     c.data = (Elem*)d_data;
     const size_t lds = plain ? (size_t)R.cap * sizeof(uint64_t) : (size_t)R.cap * sizeof(KeyIdx<Key>);
     HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    double elems = 0;
+    for (const SegD& sg : list) elems += sg.len;
+    int r = tm.begin(KK_BASE);
     hipLaunchKernelGGL((k_basecase<DT, BNT>), dim3(grid), dim3(BNT), lds, st, c, (const SegD*)h->segs.p,
                        (uint32_t)list.size(), scr);
     HIP_TRY(hipGetLastError());
+    tm.end(r, 2.0 * sizeof(Elem) * elems);
     HIP_TRY(hipStreamSynchronize(st));   // the host list must outlive the copy
     return IPS4O_OK;
 }
@@ -484,17 +588,32 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     Level<DT> L;
     std::vector<TaskS> ts;
     std::vector<uint64_t> bounds;
+    Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
+    unsigned long long before[4] = {0, 0, 0, 0};
     while (!cur.empty()) {
         if (level >= kMaxLevels) return IPS4O_ERR_DEVICE_FAULT;
         plan_level<DT>(L, cur, R, level, level == 0, 0);
         rc = h->work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
         carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
-        rc = run_level<DT>(h, L, st, nullptr);
+        LevelMarks mk;
+        rc = run_level<DT>(h, L, st, nullptr, tm, mk);
         if (rc) return rc;
-        unsigned long long stats[2] = {0, 0};
+        unsigned long long stats[4] = {0, 0, 0, 0};
         rc = read_level<DT>(h, L, st, ts, bounds, stats);
         if (rc) return rc;
+        account_level<DT>(tm, mk, stats, before, R.b);
+        for (int q = 0; q < 4; ++q) before[q] = stats[q];
+        if (log_enabled()) {
+            std::fprintf(stderr, "[ips4o] level %u: %zu tasks, %zu stripes, %u workers, moves %llu skips %llu\n",
+                         level, L.tasks.size(), L.stripes.size(), L.total_workers, stats[0], stats[1]);
+            for (size_t t = 0; t < L.tasks.size() && t < 64; ++t) {
+                const TaskD& td = L.tasks[t];
+                std::fprintf(stderr, "[ips4o]   task %zu off %llu m %llu k %u alpha %u K %u eq %u stripes %u\n", t,
+                             (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, ts[t].K,
+                             ts[t].eq, td.nstripes);
+            }
+        }
         h->last.block_moves = stats[0];
         h->last.block_skips = stats[1];
         for (const Seg& s : cur) h->last.elements_distributed += s.m;
@@ -516,9 +635,11 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     }
     h->last.levels = level;
     for (const SegD& s : base) h->last.elements_base += s.len;
-    rc = run_basecase<DT>(h, d_data, base, R, st);
+    rc = run_basecase<DT>(h, d_data, base, R, st, tm);
     if (rc) return rc;
-    return check_device_error(h, st);
+    rc = check_device_error(h, st);
+    tm.finish();
+    return rc;
 }
 
 template <int DT>
@@ -545,12 +666,16 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
     carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
-    rc = run_level<DT>(h, L, st, &ht);
+    Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
+    LevelMarks mk;
+    rc = run_level<DT>(h, L, st, &ht, tm, mk);
     if (rc) return rc;
     std::vector<TaskS> ts;
     std::vector<uint64_t> bounds;
-    unsigned long long stats[2] = {0, 0};
+    unsigned long long stats[4] = {0, 0, 0, 0}, zero[4] = {0, 0, 0, 0};
     rc = read_level<DT>(h, L, st, ts, bounds, stats);
+    account_level<DT>(tm, mk, stats, zero, R.b);
+    tm.finish();
     h->last.levels = 1;
     h->last.block_moves = stats[0];
     h->last.block_skips = stats[1];
@@ -720,6 +845,7 @@ int ips4o_create(int hip_device, ips4o_handle** out) {
 void ips4o_destroy(ips4o_handle* h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->work.release();
     h->misc.release();
     h->segs.release();
@@ -831,6 +957,12 @@ const char* ips4o_status_string(int status) {
     case IPS4O_ERR_DEVICE_FAULT: return "device fault: a bounded wait expired; data undefined";
     }
     return "unknown status";
+}
+
+int ips4o_last_kernel_stats(const ips4o_handle* h, ips4o_kernel_stat* out) {
+    if (!h || !out) return IPS4O_ERR_INVALID_ARG;
+    for (int i = 0; i < KK_N; ++i) out[i] = h->kstats[i];
+    return IPS4O_OK;
 }
 
 int ips4o_last_stats(const ips4o_handle* h, ips4o_stats* out) {

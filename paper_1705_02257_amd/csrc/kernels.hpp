@@ -85,7 +85,7 @@ struct Ctx {
     Elem* bufs;                 // stripe bucket buffers
     Elem* ovf;                  // [tasks][b]
     uint32_t* err;              // device error word (0 = ok)
-    unsigned long long* stats;  // [0] block moves, [1] skips
+    unsigned long long* stats;  // [0] block moves, [1] skips, [2] cleanup placements, [3] fix moves
     uint32_t* ticket;           // cleanup workgroup ticket
     uint32_t b;                 // elements per block
     uint32_t spin_limit;
@@ -532,6 +532,7 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
     if (nh != nsg && threadIdx.x == 0) raise_err(c.err, ERR_FIX);
     hpre[ns] = nh;
     spre[ns] = nsg;
+    if (threadIdx.x == 0 && nh) atomicAdd(&c.stats[3], (unsigned long long)nh);
     __syncthreads();
     // moves: the x-th hole receives the x-th straggler; one wavefront per move
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -767,8 +768,9 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
 // buffers of every stripe of the task, and the overflow block if bucket i
 // wrote it.  Free positions: the head [B_i, min(d_i b, B_{i+1})) and the tail
 // after the full blocks.  Bucket i first copies its overhang to LDS and
-// raises its flag; it writes only after bucket i-1 has raised its flag,
-// because bucket i-1's overhang sits in bucket i's head.
+// raises its flag; it writes only after every earlier bucket whose overhang
+// can reach its head has raised its flag (the overhang of a large bucket
+// can run across several empty or tiny buckets).
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
     using Elem = typename Traits<DT>::Elem;
@@ -808,9 +810,13 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_store(&c.flags[td.slot_begin + j], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (j > 0) {
+        // An overhang of bucket i lies in [B_{i+1}, d_{i+1} b): it can cover
+        // this bucket only if d_{i+1} == d_j, which holds for a run of
+        // predecessors (all but the first of them smaller than a block, and
+        // possibly empty).  Wait for each of them; their tickets are smaller.
+        for (uint32_t jj = j; jj >= 1 && dl[jj] == dl[j]; --jj) {
             uint32_t spins = 0;
-            while (__hip_atomic_load(&c.flags[td.slot_begin + j - 1], __ATOMIC_ACQUIRE,
+            while (__hip_atomic_load(&c.flags[td.slot_begin + jj - 1], __ATOMIC_ACQUIRE,
                                      __HIP_MEMORY_SCOPE_AGENT) == 0) {
                 if (++spins > c.spin_limit) { raise_err(c.err, ERR_SPIN); break; }
                 __builtin_amdgcn_s_sleep(1);
@@ -839,6 +845,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
         return;
     }
     const Elem* ovfp = c.ovf + (uint64_t)t * b;
+    if (threadIdx.x == 0) atomicAdd(&c.stats[2], (unsigned long long)nsrc);
     for (uint32_t x = threadIdx.x; x < nsrc; x += NT) {
         uint32_t q = upper_find(ns + 2, x, [&](uint32_t i) { return (uint64_t)pre[i]; });
         while (q + 1 < ns + 2 && pre[q + 1] <= x) ++q;

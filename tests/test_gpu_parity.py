@@ -194,6 +194,37 @@ def test_distribute_tiny(env, n):
         assert np.array_equal(ids, np.repeat(np.arange(counts.shape[0]), counts.astype(np.int64)))
 
 
+@pytest.mark.parametrize("trial", range(6))
+def test_distribute_overhang_across_empty_buckets(env, trial):
+    """Runs of equal splitters (no equality buckets) leave empty buckets right
+    after a large one: the large bucket's last full block spills across all
+    of them into the next bucket's head, which must not be overwritten before
+    that spill has been saved."""
+    torch, ips, h = env
+    n = 200003 + 977 * trial
+    inp = workloads.generate("uniform", "u64", n, 500 + trial)
+    srt = np.sort(inp)
+    rng = np.random.default_rng(trial)
+    picks = np.sort(rng.integers(0, n, 40))
+    sp = np.repeat(srt[picks], rng.integers(1, 6, picks.shape[0]))
+    counts, bounds = oracle.bucket_bounds(inp, sp, "u64", False)
+    d = to_dev(torch, inp)
+    gb = ips.ips4o_distribute(h, d, n, "u64", sp, False, {"workers": 256})
+    out = from_dev(d, inp)
+    assert np.array_equal(gb, bounds)
+    ids = oracle.classify(out, sp, "u64", False).astype(np.int64)
+    assert np.array_equal(ids, np.repeat(np.arange(counts.shape[0]), counts.astype(np.int64)))
+
+
+def test_sort_many_small_tasks_repeated(env):
+    """Deep recursion with tiny tasks (base capacity 1000), several times."""
+    n = 700001
+    for rep, dist in enumerate(["uniform", "twodup", "uniform", "eightdup"]):
+        inp = workloads.generate(dist, "u64", n, 31 + rep)
+        out = gpu_sort(env, inp, "u64", {"base_cap": 1000})
+        assert np.array_equal(out, np.sort(inp)), (rep, dist)
+
+
 # ------------------------------------------------------- classification
 @pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
 @pytest.mark.parametrize("eq", [False, True])

@@ -219,11 +219,19 @@ bool log_enabled() {
     return on == 1;
 }
 
-uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k) {
+// Oversampling factor.  The first level uses the paper's 0.2 log2 n (at
+// least 1).  Deeper levels feed the base case, whose capacity is fixed: a
+// bucket just above it costs a whole further level, while sampling costs
+// little on the GPU, so they oversample up to the LDS sample capacity
+// (at most 16).  An explicit alpha applies to every level.
+template <int DT>
+uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k, bool first) {
+    const uint32_t smax = (uint32_t)sample_max<typename Traits<DT>::Key>();
     uint32_t a;
     if (R.alpha_x100) a = std::max(1u, R.alpha_x100 / 100);
     else a = std::max<uint32_t>(1u, (uint32_t)std::floor(0.2 * std::log2((double)std::max<uint64_t>(m, 2))));
-    while (a > 1 && (uint64_t)a * k > (uint64_t)SAMPLE_MAX) --a;
+    if (!first && !R.alpha_x100) a = std::max(a, std::min(16u, smax / k));
+    while (a > 1 && (uint64_t)a * k > (uint64_t)smax) --a;
     return a;
 }
 
@@ -321,7 +329,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         else if (first) k = R.k;
         else k = std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * s.m + R.cap - 1) / R.cap)));
         t.k = k;
-        t.alpha = alpha_for(s.m, R, k);
+        t.alpha = alpha_for<DT>(s.m, R, k, first);
         t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
         const uint64_t nb = (s.m + b - 1) / b;
         // stripes: enough blocks per stripe to keep the partial buffers small
@@ -374,9 +382,7 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     add(L.total_tree * sizeof(Key));
     add((L.total_slots + T) * sizeof(uint64_t));
     add((L.total_slots + T) * sizeof(uint32_t));
-    add(L.total_slots * sizeof(uint64_t));
-    add(L.total_slots * sizeof(uint32_t));
-    add(L.total_slots * sizeof(uint32_t));
+    add(L.total_slots * sizeof(BucketSlot));
     add(S * (size_t)KMAX * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(L.total_buf * sizeof(Elem));
@@ -399,9 +405,7 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolve
     c.spl = cv.take<Key>(L.total_tree);
     c.bounds = cv.take<uint64_t>(L.total_slots + T);
     c.delim = cv.take<uint32_t>(L.total_slots + T);
-    c.wr = cv.take<uint64_t>(L.total_slots);
-    c.readers = cv.take<uint32_t>(L.total_slots);
-    c.flags = cv.take<uint32_t>(L.total_slots);
+    c.slots = cv.take<BucketSlot>(L.total_slots);
     c.counts = cv.take<uint32_t>(S * (size_t)KMAX);
     c.stripe_full = cv.take<uint32_t>(S);
     c.bufs = cv.take<Elem>(L.total_buf);

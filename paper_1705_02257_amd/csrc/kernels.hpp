@@ -29,7 +29,11 @@ namespace ips4o {
 
 constexpr int KT_MAX = 512;     // search tree leaves (power of two)
 constexpr int KMAX = 1024;      // logical buckets: up to 2*KT_MAX - 1
-constexpr int SAMPLE_MAX = 4096;
+// sample capacity in LDS: a power of two, at most 64 KiB of keys
+template <class Key>
+constexpr int sample_max() {
+    return sizeof(Key) <= 8 ? 8192 : (sizeof(Key) <= 16 ? 4096 : 2048);
+}
 constexpr int STRIPES_PER_TASK_MAX = 1024;
 constexpr uint32_t NO_BUCKET = 0xffffffffu;
 
@@ -62,6 +66,17 @@ struct TaskS {                  // device-written per task
     uint32_t pad0, pad1;
 };
 
+// Per-bucket permutation state, one 256-byte slot per bucket so that the
+// atomics of different buckets land on different cache lines and channels.
+struct alignas(256) BucketSlot {
+    uint64_t wr;        // (w << 32) | (r + 2^31), block indices in the segment
+    uint32_t readers;   // workers currently reading a block of this bucket
+    uint32_t flag;      // cleanup: overhang saved
+    uint32_t rinit;     // r at the start of the permutation (last full block)
+    uint32_t pad[59];
+};
+static_assert(sizeof(BucketSlot) == 256, "bucket slot size");
+
 template <int DT>
 struct Ctx {
     using T = Traits<DT>;
@@ -77,9 +92,7 @@ struct Ctx {
     Key* spl;                   // [sum k]: tree_begin + j, sorted splitters (padded)
     uint64_t* bounds;           // [sum (2k+1)]: slot_begin + task + i
     uint32_t* delim;            // same indexing as bounds
-    uint64_t* wr;               // [sum 2k]: packed (w << 32) | (r + 2^31)
-    uint32_t* readers;          // [sum 2k]
-    uint32_t* flags;            // [sum 2k] cleanup ordering flags
+    BucketSlot* slots;          // [sum 2k]: slot_begin + i
     uint32_t* counts;           // [stripes][KMAX]
     uint32_t* stripe_full;      // [stripes] full blocks after classification
     Elem* bufs;                 // stripe bucket buffers
@@ -99,6 +112,29 @@ enum ErrCode : uint32_t { ERR_SPIN = 1, ERR_CLEANUP_COUNT = 2, ERR_PERMUTE_RANGE
 
 __device__ inline void raise_err(uint32_t* err, uint32_t code) {
     __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Relaxed agent-scope atomics.  None of the kernels reads, within one
+// launch, data another workgroup wrote in that launch, so no acquire or
+// release (which would write back and invalidate the L2 of the issuing
+// XCD) is needed; where an atomic must follow earlier memory operations
+// the code waits for those to complete first (wait_vmem) and keeps the
+// compiler from reordering (compiler_fence).
+__device__ inline void compiler_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+__device__ inline uint64_t atom_add64(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t atom_add32(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t atom_load64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t atom_load32(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void atom_store32(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
@@ -219,7 +255,7 @@ template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
     using TR = Traits<DT>;
     using Key = typename TR::Key;
-    __shared__ Key smp[SAMPLE_MAX];
+    __shared__ Key smp[sample_max<Key>()];
     __shared__ uint32_t isnew[KT_MAX];
     __shared__ uint32_t scan_sh[NT / 64 + 1];
     const TaskD td = c.tasks[blockIdx.x];
@@ -463,8 +499,8 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
         dl[j] = (uint32_t)((B + c.b - 1) / c.b);
     }
     for (uint32_t j = threadIdx.x; j < K; j += NT) {
-        c.readers[td.slot_begin + j] = 0;
-        c.flags[td.slot_begin + j] = 0;
+        c.slots[td.slot_begin + j].readers = 0;
+        c.slots[td.slot_begin + j].flag = 0;
     }
     if (threadIdx.x == 0) {
         c.ts[t].ovf_bucket = NO_BUCKET;
@@ -563,7 +599,8 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
     }
     if (threadIdx.x == 0) {
         uint64_t w = d0, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
-        c.wr[td.slot_begin + j] = (w << 32) | (r & 0xffffffffull);
+        c.slots[td.slot_begin + j].wr = (w << 32) | (r & 0xffffffffull);
+        c.slots[td.slot_begin + j].rinit = d0 + occ;   // one past the last full block
     }
 }
 
@@ -601,8 +638,7 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
     const Key* gspl = trl.spl;
     if (gw >= c.total_workers || gw >= td.worker_begin + td.nworkers) return;
     const uint32_t lw = gw - td.worker_begin;
-    uint64_t* wr = c.wr + td.slot_begin;
-    uint32_t* readers = c.readers + td.slot_begin;
+    BucketSlot* sl = c.slots + td.slot_begin;
     const uint32_t* dl = c.delim + td.slot_begin + t;
     Elem* seg = c.data + td.off;
     constexpr uint32_t WPE = sizeof(Elem) / sizeof(Word);
@@ -665,7 +701,7 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             if (q >= K) q -= K;
             bool cand = false;
             if (scanned + lane < K) {
-                uint64_t v = __hip_atomic_load(&wr[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t v = atom_load64(&sl[q].wr);
                 int64_t w = (int64_t)(v >> 32), r = (int64_t)(v & 0xffffffffull) - 0x80000000ll;
                 cand = r >= w;
             }
@@ -681,33 +717,37 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             scanned += first;
             p += first;
             if (p >= K) p -= K;
-            // try to claim a block of bucket p
+            // try to claim a block of bucket p: announce the reader first and
+            // wait until that increment has been performed, so that a writer
+            // that sees the decremented r also sees the reader
             uint64_t old = 0;
             if (lane == 0) {
-                __hip_atomic_fetch_add(&readers[p], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                old = __hip_atomic_fetch_add(&wr[p], ~0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t rd = atom_add32(&sl[p].readers, 1u);
+                compiler_fence();
+                wait_vmem();
+                compiler_fence();
+                (void)rd;
+                old = atom_add64(&sl[p].wr, ~0ull);
             }
             old = bcast_u64(old);
             int64_t w0 = (int64_t)(old >> 32), r0 = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
             if (r0 >= w0) {
                 load_block((uint32_t)r0, A);
-                wait_vmem();
-                if (lane == 0)
-                    __hip_atomic_fetch_add(&readers[p], ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                compiler_fence();
+                wait_vmem();          // the block is in registers before the reader leaves
+                compiler_fence();
+                if (lane == 0) atom_add32(&sl[p].readers, ~0u);
                 destA = first_bucket(A);
                 got = true;
                 break;
             }
-            if (lane == 0)
-                __hip_atomic_fetch_add(&readers[p], ~0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) atom_add32(&sl[p].readers, ~0u);
         }
         if (!got) break;
         // ---- place the block, swapping along the way
         while (true) {
             uint64_t old = 0;
-            if (lane == 0)
-                old = __hip_atomic_fetch_add(&wr[destA], 1ull << 32, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0) old = atom_add64(&sl[destA].wr, 1ull << 32);
             old = bcast_u64(old);
             int64_t x = (int64_t)(old >> 32), r = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
             if (x >= (int64_t)dl[destA + 1] || x < 0) {   // cannot happen for consistent counts
@@ -734,11 +774,15 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
                 destA = destB;
                 continue;
             }
-            // empty block at x: wait for readers of dest, then write
+            // empty block at x.  If x was a full block when the permutation
+            // started, a reader took it and may still be loading it: wait
+            // until no reader of dest is active (this happens where w and r
+            // cross, at most once per bucket); blocks that were empty from
+            // the start were never read.
             uint32_t spins = 0;
-            while (true) {
+            while ((uint32_t)x < sl[destA].rinit) {
                 uint32_t rd = 0;
-                if (lane == 0) rd = __hip_atomic_load(&readers[destA], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0) rd = atom_load32(&sl[destA].readers);
                 rd = bcast_u32(rd);
                 if (rd == 0) break;
                 if (++spins > limit) {
@@ -747,6 +791,7 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
+            compiler_fence();
             store_block((uint32_t)x, A);
             ++moves;
             if (partial && (uint32_t)x == last_blk && lane == 0) c.ts[t].ovf_bucket = destA;
@@ -793,7 +838,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
     const uint32_t* dl = c.delim + td.slot_begin + t;
     const uint64_t B0 = bd[j], B1 = bd[j + 1];
     const uint64_t cs = (uint64_t)dl[j] * b;
-    const uint64_t w = c.wr[td.slot_begin + j] >> 32;
+    const uint64_t w = c.slots[td.slot_begin + j].wr >> 32;
     const bool ovf_case = st.ovf_bucket == j;
     // end of the correct full blocks (no blocks: the region is empty at cs;
     // with blocks the bucket holds at least b elements, so cs < B1)
@@ -809,19 +854,20 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
     for (uint32_t i = threadIdx.x; i < ohn; i += NT) oh[i] = seg[B1 + i];
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_store(&c.flags[td.slot_begin + j], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // the overhang is in LDS (the barrier above waited for its loads)
+        atom_store32(&c.slots[td.slot_begin + j].flag, 1u);
         // An overhang of bucket i lies in [B_{i+1}, d_{i+1} b): it can cover
         // this bucket only if d_{i+1} == d_j, which holds for a run of
         // predecessors (all but the first of them smaller than a block, and
         // possibly empty).  Wait for each of them; their tickets are smaller.
         for (uint32_t jj = j; jj >= 1 && dl[jj] == dl[j]; --jj) {
             uint32_t spins = 0;
-            while (__hip_atomic_load(&c.flags[td.slot_begin + jj - 1], __ATOMIC_ACQUIRE,
-                                     __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            while (atom_load32(&c.slots[td.slot_begin + jj - 1].flag) == 0) {
                 if (++spins > c.spin_limit) { raise_err(c.err, ERR_SPIN); break; }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
+        compiler_fence();
     }
     __syncthreads();
     // sources: [overhang | buffer of stripe 0 | ... | buffer of stripe ns-1 | overflow]

@@ -424,12 +424,15 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolve
 }
 
 // Kernel shapes per element type.
+// CNT/EPT: classification workgroup size and elements per thread per tile;
+// BNT/BVT: base-case workgroup size and items per thread (BNT*BVT is the
+// base-case capacity of the element type).
 template <int DT> struct Shape;
-template <> struct Shape<DT_U64> { static constexpr int CNT = 1024, EPT = 8, BNT = 512; };
-template <> struct Shape<DT_F64> { static constexpr int CNT = 1024, EPT = 8, BNT = 512; };
-template <> struct Shape<DT_PAIR> { static constexpr int CNT = 1024, EPT = 4, BNT = 512; };
-template <> struct Shape<DT_QUARTET> { static constexpr int CNT = 1024, EPT = 2, BNT = 512; };
-template <> struct Shape<DT_BYTES100> { static constexpr int CNT = 512, EPT = 1, BNT = 512; };
+template <> struct Shape<DT_U64> { static constexpr int CNT = 1024, EPT = 8, BNT = 1024, BVT = 16; };
+template <> struct Shape<DT_F64> { static constexpr int CNT = 1024, EPT = 8, BNT = 1024, BVT = 16; };
+template <> struct Shape<DT_PAIR> { static constexpr int CNT = 1024, EPT = 4, BNT = 1024, BVT = 8; };
+template <> struct Shape<DT_QUARTET> { static constexpr int CNT = 1024, EPT = 2, BNT = 512, BVT = 8; };
+template <> struct Shape<DT_BYTES100> { static constexpr int CNT = 512, EPT = 1, BNT = 512, BVT = 8; };
 
 template <int DT, int WPL>
 hipError_t launch_permute_wpl(const Ctx<DT>& c, hipStream_t st) {
@@ -541,6 +544,29 @@ int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>
     return check_device_error(h, st);
 }
 
+// Pack base-case segments into bins of at most `cap` consecutive elements.
+// A bin spans whole buckets in array order: the buckets of one partition
+// hold disjoint key ranges in ascending order, and whatever lies between two
+// listed segments is already final (equality buckets, buckets of at most one
+// element), so sorting the span sorts each bucket in place exactly as
+// sorting them one by one would.
+std::vector<SegD> pack_bins(std::vector<SegD> segs, uint32_t cap) {
+    std::sort(segs.begin(), segs.end(), [](const SegD& a, const SegD& b) { return a.off < b.off; });
+    std::vector<SegD> bins;
+    for (const SegD& s : segs) {
+        if (!bins.empty()) {
+            SegD& cur = bins.back();
+            const uint64_t end = s.off + s.len;
+            if (end - cur.off <= cap) {
+                cur.len = (uint32_t)(end - cur.off);
+                continue;
+            }
+        }
+        bins.push_back(s);
+    }
+    return bins;
+}
+
 template <int DT>
 int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, const Resolved& R,
                  hipStream_t st, Timer& tm) {
@@ -548,7 +574,8 @@ int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, c
     using Elem = typename TR::Elem;
     using Key = typename TR::Key;
     if (list.empty()) return IPS4O_OK;
-    constexpr int BNT = Shape<DT>::BNT;
+    constexpr int BNT = Shape<DT>::BNT, BVT = Shape<DT>::BVT;
+    static_assert(BNT * BVT == TR::kBaseCap, "base-case capacity");
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
     int rc = h->segs.ensure(list.size() * sizeof(SegD));
     if (rc) return rc;
@@ -562,12 +589,13 @@ int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, c
     HIP_TRY(hipMemcpyAsync(h->segs.p, list.data(), list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
     Ctx<DT> c{};
     c.data = (Elem*)d_data;
-    const size_t lds = plain ? (size_t)R.cap * sizeof(uint64_t) : (size_t)R.cap * sizeof(KeyIdx<Key>);
-    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    using It = typename BaseItem<DT>::T;
+    const size_t lds = (size_t)(R.cap + (R.cap + BVT - 1) / BVT) * sizeof(It);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
     int r = tm.begin(KK_BASE);
-    hipLaunchKernelGGL((k_basecase<DT, BNT>), dim3(grid), dim3(BNT), lds, st, c, (const SegD*)h->segs.p,
+    hipLaunchKernelGGL((k_basecase<DT, BNT, BVT>), dim3(grid), dim3(BNT), lds, st, c, (const SegD*)h->segs.p,
                        (uint32_t)list.size(), scr);
     HIP_TRY(hipGetLastError());
     tm.end(r, 2.0 * sizeof(Elem) * elems);
@@ -639,6 +667,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     }
     h->last.levels = level;
     for (const SegD& s : base) h->last.elements_base += s.len;
+    base = pack_bins(base, R.cap);
     rc = run_basecase<DT>(h, d_data, base, R, st, tm);
     if (rc) return rc;
     rc = check_device_error(h, st);

@@ -906,13 +906,14 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
 }
 
 // -------------------------------------------------------------- base case
-// Sorts each listed segment (<= the LDS capacity) inside one workgroup's
-// LDS.  Network: bitonic sort in its "mirror" form, where every
-// compare-exchange puts the smaller key at the lower index; positions at or
-// beyond the segment length act as +infinity and never move, so any length
-// is sorted without padding.  u64/f64 sort the keys themselves (f64 through
-// the bijective totalOrder image); records sort (key, index) pairs and then
-// gather whole records through the workgroup's scratch slot.
+// Sorts each listed segment (at most NT*VT elements) inside one workgroup's
+// LDS: every thread sorts VT consecutive items in registers with a bitonic
+// network, then log2(len / VT) merge passes double the sorted runs; in a pass
+// each thread finds where its VT outputs start in the merge of its two runs
+// by a binary search along the cross diagonal (merge path) and merges VT
+// items with a merging network.  u64/f64 sort the keys themselves (f64 through the
+// bijective totalOrder image); records sort (key, index) items and then
+// gather whole records from a per-workgroup scratch copy of the segment.
 struct SegD {
     uint64_t off;
     uint32_t len;
@@ -925,86 +926,147 @@ struct KeyIdx {
     uint32_t i;
 };
 
-template <int DT, int NT>
+template <int DT>
+struct BaseItem {                       // records: key and position
+    using Key = typename Traits<DT>::Key;
+    using T = KeyIdx<Key>;
+    __device__ static bool less(const T& a, const T& b) { return a.k < b.k; }
+    __device__ static T maxv() { return T{Traits<DT>::max_key(), 0xffffffffu}; }
+};
+template <>
+struct BaseItem<DT_U64> {
+    using T = uint64_t;
+    __device__ static bool less(T a, T b) { return a < b; }
+    __device__ static T maxv() { return ~0ull; }
+};
+template <>
+struct BaseItem<DT_F64> : BaseItem<DT_U64> {};
+
+template <class BI, int VT>
+__device__ inline void sort_network(typename BI::T (&x)[VT]) {
+#pragma unroll
+    for (int k = 2; k <= VT; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < VT; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    typename BI::T a = x[i], b = x[l];
+                    const bool sw = up ? BI::less(b, a) : BI::less(a, b);
+                    x[i] = sw ? b : a;
+                    x[l] = sw ? a : b;
+                }
+            }
+        }
+    }
+}
+
+// sorts a bitonic sequence ascending (log2 VT half-cleaner stages)
+template <class BI, int VT>
+__device__ inline void bitonic_merge(typename BI::T (&x)[VT]) {
+#pragma unroll
+    for (int j = VT >> 1; j > 0; j >>= 1) {
+#pragma unroll
+        for (int i = 0; i < VT; ++i) {
+            const int l = i ^ j;
+            if (l > i) {
+                typename BI::T a = x[i], b = x[l];
+                const bool sw = BI::less(b, a);
+                x[i] = sw ? b : a;
+                x[l] = sw ? a : b;
+            }
+        }
+    }
+}
+
+template <int DT, int NT, int VT>
 __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, uint32_t nseg,
                                                  typename Traits<DT>::Elem* scratch) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
-    using Key = typename TR::Key;
+    using BI = BaseItem<DT>;
+    using It = typename BI::T;
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    It* lds = reinterpret_cast<It*>(smem_raw);
+    auto pidx = [](uint32_t i) { return i + i / VT; };   // one pad item per VT: fewer bank conflicts
+    const uint32_t tid = threadIdx.x;
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
         const SegD sg = segs[si];
         const uint32_t len = sg.len;
         Elem* seg = c.data + sg.off;
-        uint32_t P = 1;
-        while (P < len) P <<= 1;
-        if constexpr (kPlain) {
-            uint64_t* keys = reinterpret_cast<uint64_t*>(smem_raw);
-            for (uint32_t i = threadIdx.x; i < len; i += NT) keys[i] = TR::key(seg[i]).v;
-            __syncthreads();
-            for (uint32_t size = 2; size <= P; size <<= 1) {
-                const uint32_t half = size >> 1;
-                for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
-                    uint32_t blk = x / half, o = x % half;
-                    uint32_t i = blk * size + o, jj = blk * size + size - 1 - o;
-                    if (jj < len) {
-                        uint64_t a = keys[i], bb = keys[jj];
-                        if (bb < a) { keys[i] = bb; keys[jj] = a; }
-                    }
-                }
-                __syncthreads();
-                for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
-                    for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
-                        uint32_t i = (x / stride) * 2 * stride + (x % stride), jj = i + stride;
-                        if (jj < len) {
-                            uint64_t a = keys[i], bb = keys[jj];
-                            if (bb < a) { keys[i] = bb; keys[jj] = a; }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (uint32_t i = threadIdx.x; i < len; i += NT) {
-                if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(keys[i]);
-                else seg[i] = keys[i];
-            }
-            __syncthreads();
-        } else {
-            KeyIdx<Key>* kv = reinterpret_cast<KeyIdx<Key>*>(smem_raw);
-            Elem* scr = scratch + (uint64_t)blockIdx.x * TR::kBaseCap;
-            for (uint32_t i = threadIdx.x; i < len; i += NT) {
-                Elem e = seg[i];
+        Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
+        for (uint32_t i = tid; i < len; i += NT) {
+            Elem e = seg[i];
+            if constexpr (kPlain) {
+                lds[pidx(i)] = TR::key(e).v;
+            } else {
                 scr[i] = e;
-                kv[i].k = TR::key(e);
-                kv[i].i = i;
+                lds[pidx(i)] = It{TR::key(e), i};
             }
-            __syncthreads();
-            for (uint32_t size = 2; size <= P; size <<= 1) {
-                const uint32_t half = size >> 1;
-                for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
-                    uint32_t blk = x / half, o = x % half;
-                    uint32_t i = blk * size + o, jj = blk * size + size - 1 - o;
-                    if (jj < len) {
-                        KeyIdx<Key> a = kv[i], bb = kv[jj];
-                        if (bb.k < a.k) { kv[i] = bb; kv[jj] = a; }
-                    }
-                }
-                __syncthreads();
-                for (uint32_t stride = half >> 1; stride > 0; stride >>= 1) {
-                    for (uint32_t x = threadIdx.x; x < P / 2; x += NT) {
-                        uint32_t i = (x / stride) * 2 * stride + (x % stride), jj = i + stride;
-                        if (jj < len) {
-                            KeyIdx<Key> a = kv[i], bb = kv[jj];
-                            if (bb.k < a.k) { kv[i] = bb; kv[jj] = a; }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            for (uint32_t i = threadIdx.x; i < len; i += NT) seg[i] = scr[kv[i].i];
-            __syncthreads();
         }
+        __syncthreads();
+        const uint32_t nthr = (len + VT - 1) / VT;
+        const uint32_t base = tid * VT;
+        It x[VT];
+        if (tid < nthr) {
+#pragma unroll
+            for (int v = 0; v < VT; ++v) x[v] = (base + v < len) ? lds[pidx(base + v)] : BI::maxv();
+            sort_network<BI, VT>(x);
+        }
+        for (uint32_t L = VT; L < len; L *= 2) {
+            __syncthreads();
+            if (tid < nthr) {
+#pragma unroll
+                for (int v = 0; v < VT; ++v)
+                    if (base + v < len) lds[pidx(base + v)] = x[v];
+            }
+            __syncthreads();
+            if (tid < nthr) {
+                const uint32_t a0 = (base / (2 * L)) * (2 * L);
+                const uint32_t aCount = (len - a0) < L ? (len - a0) : L;
+                const uint32_t b0 = a0 + L;
+                const uint32_t bCount = b0 >= len ? 0u : ((len - b0) < L ? (len - b0) : L);
+                const uint32_t diag = base - a0;
+                uint32_t lo = diag > bCount ? diag - bCount : 0u;
+                uint32_t hi = diag < aCount ? diag : aCount;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    const It a = lds[pidx(a0 + mid)];
+                    const It b = lds[pidx(b0 + diag - 1 - mid)];
+                    if (!BI::less(b, a)) lo = mid + 1; else hi = mid;
+                }
+                // the thread's VT outputs are the VT smallest of the next VT
+                // items of each run: load both (independent loads), keep the
+                // pairwise minima of a[v] and b[VT-1-v] (a bitonic sequence
+                // holding exactly those VT items) and sort it by bitonic merge
+                const uint32_t ai = lo, bi = diag - lo;
+                It av[VT], bv[VT];
+#pragma unroll
+                for (int v = 0; v < VT; ++v) {
+                    av[v] = (ai + v < aCount) ? lds[pidx(a0 + ai + v)] : BI::maxv();
+                    bv[v] = (bi + v < bCount) ? lds[pidx(b0 + bi + v)] : BI::maxv();
+                }
+#pragma unroll
+                for (int v = 0; v < VT; ++v) x[v] = BI::less(bv[VT - 1 - v], av[v]) ? bv[VT - 1 - v] : av[v];
+                bitonic_merge<BI, VT>(x);
+            }
+        }
+        __syncthreads();
+        if (tid < nthr) {
+#pragma unroll
+            for (int v = 0; v < VT; ++v)
+                if (base + v < len) lds[pidx(base + v)] = x[v];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < len; i += NT) {
+            if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(lds[pidx(i)]);
+            else if constexpr (DT == DT_U64) seg[i] = lds[pidx(i)];
+            else seg[i] = scr[lds[pidx(i)].i];
+        }
+        __syncthreads();
     }
 }
 

@@ -94,6 +94,8 @@ typedef struct {
 
 #define IPS4O_FLAG_NO_SKIP 1u   /* do not skip blocks already in place during the permutation */
 #define IPS4O_FLAG_TIMING  2u   /* time every kernel launch with HIP events on the call's stream */
+#define IPS4O_FLAG_CHECK   4u   /* debug: verify the phase invariants on the device after
+                                   classification and after the permutation (slow) */
 
 typedef struct ips4o_handle ips4o_handle;
 
@@ -176,7 +178,10 @@ const char *ips4o_status_string(int status);
  *   levels         distribution levels run
  *   fault_bits     device error bits of the last call (0 = none): 1 a wait
  *                  expired, 2 cleanup counts disagreed, 4 a permutation
- *                  pointer left its bucket, 8 empty-block fix counts disagreed
+ *                  pointer left its bucket, 8 empty-block fix counts
+ *                  disagreed; with IPS4O_FLAG_CHECK also 16 a full block
+ *                  mixed buckets, 32 recounted buckets differed, 64 a placed
+ *                  block held another bucket
  *   block_moves    blocks written by the permutations (all levels)
  *   block_skips    blocks found already in place and left there
  *   elements_base  elements sorted by the base case

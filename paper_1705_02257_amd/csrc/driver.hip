@@ -348,7 +348,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             sd.blk_begin = (uint32_t)(nb * q / ns);
             sd.blk_end = (uint32_t)(nb * (q + 1) / ns);
             sd.buf_off = bufoff;
-            bufoff += (uint64_t)2 * k * b;
+            bufoff += (uint64_t)4 * k * b;   // partial buffers (2k*b) and head copy (2k*b)
             L.stripes.push_back(sd);
         }
         uint64_t w = (uint64_t)std::llround((double)R.workers * (double)nb / (double)total_blocks);
@@ -458,7 +458,7 @@ struct LevelMarks {    // timer records whose byte counts are known after the le
 
 template <int DT>
 int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
-              LevelMarks& mk) {
+              LevelMarks& mk, bool check) {
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     constexpr int CNT = Shape<DT>::CNT, EPT = Shape<DT>::EPT;
@@ -485,6 +485,10 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     hipLaunchKernelGGL((k_classify<DT, CNT, EPT>), dim3(S), dim3(CNT), cls_lds, st, c);
     HIP_TRY(hipGetLastError());
     tm.end(r, 2.0 * sizeof(Elem) * (double)level_m);
+    if (check) {
+        hipLaunchKernelGGL((k_check_classify<DT, 256>), dim3(S), dim3(256), 0, st, c);
+        HIP_TRY(hipGetLastError());
+    }
     r = tm.begin(KK_SCAN);
     hipLaunchKernelGGL((k_scan<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
     HIP_TRY(hipGetLastError());
@@ -496,6 +500,12 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     mk.permute = tm.begin(KK_PERMUTE);
     HIP_TRY(launch_permute<DT>(c, st));
     tm.end(mk.permute, 0.0);
+    if (check) {
+        uint32_t kmax = 0;
+        for (const TaskD& t : L.tasks) kmax = std::max(kmax, 2 * t.k);
+        hipLaunchKernelGGL((k_check_permute<DT, 256>), dim3(kmax, T), dim3(256), 0, st, c);
+        HIP_TRY(hipGetLastError());
+    }
     const size_t cl_lds = (size_t)c.b * sizeof(Elem);
     HIP_TRY(hipFuncSetAttribute((const void*)k_cleanup<DT, 256>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)cl_lds));
@@ -517,11 +527,14 @@ void account_level(Timer& tm, const LevelMarks& mk, const unsigned long long* no
 }
 
 int check_device_error(ips4o_handle* h, hipStream_t st) {
-    uint32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, h->misc.p, sizeof(err), hipMemcpyDeviceToHost, st));
+    uint32_t err[53] = {0};
+    HIP_TRY(hipMemcpyAsync(err, h->misc.p, sizeof(err), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    h->last.fault_bits = err;
-    return err ? IPS4O_ERR_DEVICE_FAULT : IPS4O_OK;
+    h->last.fault_bits = err[0];
+    if (err[0] && log_enabled())
+        std::fprintf(stderr, "[ips4o] device fault bits %u, first: code %u (%u, %u, %u)\n", err[0], err[48],
+                     err[49], err[50], err[51]);
+    return err[0] ? IPS4O_ERR_DEVICE_FAULT : IPS4O_OK;
 }
 
 int reset_misc(ips4o_handle* h, hipStream_t st) {
@@ -629,7 +642,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         if (rc) return rc;
         carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
         LevelMarks mk;
-        rc = run_level<DT>(h, L, st, nullptr, tm, mk);
+        rc = run_level<DT>(h, L, st, nullptr, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
         if (rc) return rc;
         unsigned long long stats[4] = {0, 0, 0, 0};
         rc = read_level<DT>(h, L, st, ts, bounds, stats);
@@ -701,7 +714,7 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     LevelMarks mk;
-    rc = run_level<DT>(h, L, st, &ht, tm, mk);
+    rc = run_level<DT>(h, L, st, &ht, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
     if (rc) return rc;
     std::vector<TaskS> ts;
     std::vector<uint64_t> bounds;

@@ -108,10 +108,24 @@ struct Ctx {
     uint32_t pad;
 };
 
-enum ErrCode : uint32_t { ERR_SPIN = 1, ERR_CLEANUP_COUNT = 2, ERR_PERMUTE_RANGE = 4, ERR_FIX = 8 };
+enum ErrCode : uint32_t {
+    ERR_SPIN = 1, ERR_CLEANUP_COUNT = 2, ERR_PERMUTE_RANGE = 4, ERR_FIX = 8,
+    // phase invariant checks (debug flag)
+    ERR_CHECK_BLOCK = 16,   // a full block after classification mixes buckets
+    ERR_CHECK_COUNT = 32,   // recounted buckets differ from the stored counts
+    ERR_CHECK_PLACED = 64   // after the permutation a block in [d_i, w_i) is not of bucket i
+};
 
 __device__ inline void raise_err(uint32_t* err, uint32_t code) {
     __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// first failure details for diagnostics: err[48..52) = {code, a, b, c}
+__device__ inline void raise_err_at(uint32_t* err, uint32_t code, uint32_t a, uint32_t b, uint32_t c) {
+    raise_err(err, code);
+    if (__hip_atomic_fetch_add(err + 52, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        err[48] = code; err[49] = a; err[50] = b; err[51] = c;
+    }
 }
 
 // Relaxed agent-scope atomics.  None of the kernels reads, within one
@@ -344,130 +358,384 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
 }
 
 // ------------------------------------------------------ local classification
-// One workgroup per stripe.  The stripe is read in tiles of NT*EPT elements.
-// Each tile is classified in registers, counting-sorted by bucket in LDS,
-// and then merged with the workgroup's per-bucket buffer blocks (b elements
-// each, in global memory): a bucket whose buffer plus new elements reach b
-// or more emits full blocks to the stripe's write front, the rest stays
-// buffered.  The write front never passes the read front because a full
-// block is only emitted for b elements already read (Section 4.1).
+// One workgroup per stripe (Section 4.1).  The workgroup keeps one buffer
+// block of b elements per bucket; a full buffer block is a finished block of
+// the stripe.  To write every element only once, the buffer block a bucket is
+// filling ("open" block) lives inside the stripe at the write front, and a
+// full open block simply stays where it is.  Open blocks may be allocated
+// only where elements have already been read; the slack for the K open
+// blocks comes from first copying the stripe's first C = K*b elements to a
+// side area ("head"):
+//   phase 0  copy the head out;
+//   phase 1  tiles of NT*EPT elements after the head: classify in registers,
+//            counting-sort by bucket in LDS, write every element into its
+//            bucket's open block or into new blocks allocated at the write
+//            front (at most C + read elements are ever allocated);
+//   phase 2  move the content of every partly filled open block to the
+//            bucket's partial buffer (its slot becomes a hole), then run the
+//            head through the classic buffer scheme: buffer blocks that fill
+//            up become full blocks placed into the holes first and then at
+//            the write front;
+//   phase 3  if holes remain, move the last full blocks into them, so the
+//            stripe ends as [full blocks | empty blocks] with the partial
+//            buffers outside it, exactly as the paper's local classification
+//            leaves it.
 template <int DT, int NT, int EPT>
 struct ClassifyLds {
     using Elem = typename Traits<DT>::Elem;
     TreeLds<DT> tr;
     Elem tile[NT * EPT];
     uint16_t ids[NT * EPT];
-    uint32_t cnt[KMAX];
-    uint32_t off[KMAX];
-    uint32_t fill[KMAX];
-    uint32_t nblk[KMAX];
-    uint32_t bbase[KMAX];
-    uint32_t scan_sh[NT / 64 + 1];
-    uint32_t wf;
+    uint32_t cnt[KMAX];         // elements of the tile per bucket (atomic ranks)
+    uint32_t fill[KMAX];        // phase 1: fill of the open block (b: none or full);
+                                // phase 2: fill of the partial buffer
+    uint32_t open[KMAX];        // phase 1: slot of the open block
+    uint32_t nfull[KMAX];       // phase 1: blocks allocated; then full blocks
+    uint32_t off[KMAX];         // start of the bucket's run in the tile
+    int32_t lim[KMAX];          // phase 1: tile positions p < lim go to the open block
+    uint32_t abase[KMAX];       // phase 2: allocation index of the first new block
+    int64_t base0[KMAX];        // phase 1: stripe index of position p: base0 + p ...
+    int64_t base1[KMAX];        // ... or base1 + p at and beyond lim
+    uint32_t holes[KMAX];       // slots of evacuated open blocks
+    uint64_t scan_sh[NT / 64 + 1];
+    uint32_t wf;                // slots allocated in phase 1
+    uint32_t nholes;
+    uint32_t nalloc;            // full blocks allocated in phase 2
 };
+
+// Exclusive scan of one 64-bit value per thread over the workgroup.
+template <int NT>
+__device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* sh, uint64_t* total) {
+    constexpr int NW = NT / 64;
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t t = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += t;
+    }
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        uint64_t t = lane < NW ? sh[lane] : 0ull, ti = t;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            uint64_t u = __shfl_up(ti, d, 64);
+            if (lane >= (uint32_t)d) ti += u;
+        }
+        if (lane < NW) sh[lane] = ti - t;
+        if (lane == NW - 1) sh[NW] = ti;
+    }
+    __syncthreads();
+    uint64_t r = inc - v + sh[wid];
+    *total = sh[NW];
+    __syncthreads();
+    return r;
+}
+
+// Tree descent for EPT keys at once, level by level, so that the LDS loads
+// of the EPT descents are independent of each other.
+template <class Key, int EPT>
+__device__ inline void classify_batch(const Key (&k)[EPT], uint32_t (&out)[EPT], const Key* stree,
+                                      const Key* sspl, uint32_t log_kt, uint32_t nuniq, uint32_t eq) {
+    uint32_t j[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) j[e] = 1;
+    for (uint32_t l = 0; l < log_kt; ++l) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) j[e] = 2 * j[e] + (stree[j[e]] <= k[e] ? 1u : 0u);
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        uint32_t leaf = j[e] - (1u << log_kt);
+        leaf = leaf < nuniq ? leaf : nuniq;
+        uint32_t r = leaf;
+        if (eq) {
+            const uint32_t is_eq = (leaf >= 1 && sspl[leaf > 0 ? leaf - 1 : 0] == k[e]) ? 1u : 0u;
+            r = 2 * leaf - is_eq;
+        }
+        out[e] = r;
+    }
+}
+
+// Classify the tile held in x[] (tn valid elements) and rank every element
+// within its bucket: one LDS atomic per wavefront when all its lanes share a
+// bucket (skewed inputs), else one per element.
+template <int DT, int NT, int EPT>
+__device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename Traits<DT>::Elem (&x)[EPT],
+                                     uint32_t tn, uint32_t lkt, const TaskS& st, uint32_t (&bk)[EPT],
+                                     uint32_t (&rk)[EPT]) {
+    using TR = Traits<DT>;
+    typename TR::Key kk[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) kk[e] = TR::key(x[e]);
+    classify_batch<typename TR::Key, EPT>(kk, bk, L.tr.tree, L.tr.spl, lkt, st.nuniq, st.eq);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const uint32_t p = e * NT + threadIdx.x;
+        const bool valid = p < tn;
+        const uint64_t vmask = __ballot(valid);
+        const uint32_t b0 = __builtin_amdgcn_readfirstlane(bk[e]);
+        const uint64_t same = __ballot(valid && bk[e] == b0);
+        if (same == vmask) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+            uint32_t base = 0;
+            if (below == 0 && valid) base = atomicAdd(&L.cnt[b0], (uint32_t)__popcll(same));
+            base = __builtin_amdgcn_readfirstlane(base);
+            rk[e] = base + below;
+        } else if (valid) {
+            rk[e] = atomicAdd(&L.cnt[bk[e]], 1u);
+        }
+    }
+}
+
+template <int DT, int NT, int EPT>
+__device__ inline void scatter_tile(ClassifyLds<DT, NT, EPT>& L, const typename Traits<DT>::Elem (&x)[EPT],
+                                    uint32_t tn, const uint32_t (&bk)[EPT], const uint32_t (&rk)[EPT]) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const uint32_t p = e * NT + threadIdx.x;
+        if (p < tn) {
+            const uint32_t q = L.off[bk[e]] + rk[e];
+            L.tile[q] = x[e];
+            L.ids[q] = (uint16_t)bk[e];
+        }
+    }
+}
 
 template <int DT, int NT, int EPT>
 __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
+    using Word = typename TR::Word;
     constexpr uint32_t TILE = NT * EPT;
+    constexpr uint32_t PER = (KMAX + NT - 1) / NT;      // buckets per thread in the scans
+    constexpr uint32_t WPE = sizeof(Elem) / sizeof(Word);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     auto& L = *reinterpret_cast<ClassifyLds<DT, NT, EPT>*>(smem_raw);
 
     const StripeD sd = c.stripes[blockIdx.x];
     const TaskD td = c.tasks[sd.task];
     const TaskS st = c.ts[sd.task];
-    const uint32_t b = c.b, K = st.K, kt = st.kt, lkt = ilog2(kt);
-    load_tree<DT>(c, td, kt, st.nuniq, L.tr);
-    for (uint32_t j = threadIdx.x; j < K; j += NT) {
-        L.cnt[j] = 0; L.fill[j] = 0; L.nblk[j] = 0;
-    }
-    if (threadIdx.x == 0) L.wf = 0;
-    __syncthreads();
+    const uint32_t b = c.b, lb = ilog2(c.b), K = st.K, lkt = ilog2(st.kt);
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    load_tree<DT>(c, td, st.kt, st.nuniq, L.tr);
 
-    Elem* seg = c.data + td.off;
-    Elem* buf = c.bufs + sd.buf_off;
     const uint64_t s_begin = (uint64_t)sd.blk_begin * b;
     const uint64_t s_end = ((uint64_t)sd.blk_end * b < td.m) ? (uint64_t)sd.blk_end * b : td.m;
-    const uint64_t stripe_blk0 = sd.blk_begin;
+    const uint32_t E = (uint32_t)(s_end - s_begin);         // stripe elements
+    const uint32_t C = E < (K << lb) ? E : (K << lb);       // head size
+    Elem* sp = c.data + td.off + s_begin;                   // the stripe
+    Elem* buf = c.bufs + sd.buf_off;                        // partial buffers, bucket j at j*b
+    Elem* head = buf + ((uint64_t)(2 * td.k) << lb);        // copy of the head
 
-    for (uint64_t t0 = s_begin; t0 < s_end; t0 += TILE) {
-        const uint32_t tn = (uint32_t)((s_end - t0) < TILE ? (s_end - t0) : TILE);
-        Elem x[EPT];
+    for (uint32_t q = threadIdx.x; q < K; q += NT) {
+        L.cnt[q] = 0; L.fill[q] = b; L.open[q] = 0; L.nfull[q] = 0;
+    }
+    if (threadIdx.x == 0) { L.wf = 0; L.nholes = 0; L.nalloc = 0; }
+    // ---- phase 0: the head goes to the side area
+    for (uint32_t i = threadIdx.x; i < C; i += NT) head[i] = sp[i];
+    __syncthreads();
+
+    // ---- phase 1: the rest of the stripe, straight into open blocks
+    Elem x[EPT];
+    auto load_tile = [&](const Elem* src, uint32_t t0, uint32_t end) {
+        const uint32_t rem = end > t0 ? end - t0 : 0u;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const uint32_t p = e * NT + threadIdx.x;
+            if (p < rem) x[e] = src[t0 + p];
+        }
+    };
+    if (C < E) load_tile(sp, C, E);
+    for (uint32_t t0 = C; t0 < E; t0 += TILE) {
+        const uint32_t tn = (E - t0) < TILE ? (E - t0) : TILE;
         uint32_t bk[EPT], rk[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            uint32_t p = e * NT + threadIdx.x;
-            if (p < tn) x[e] = seg[t0 + p];
-        }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            uint32_t p = e * NT + threadIdx.x;
-            if (p < tn) {
-                bk[e] = classify_key(TR::key(x[e]), L.tr.tree, L.tr.spl, lkt, st.nuniq, st.eq);
-                rk[e] = atomicAdd(&L.cnt[bk[e]], 1u);
-            }
-        }
+        classify_rank<DT, NT, EPT>(L, x, tn, lkt, st, bk, rk);
         __syncthreads();
-        // per bucket: tile offsets and full blocks emitted
-        for (uint32_t j = threadIdx.x; j < K; j += NT) {
-            L.off[j] = L.cnt[j];
-            L.bbase[j] = (L.fill[j] + L.cnt[j]) / b;
-        }
-        __syncthreads();
-        lds_excl_scan<NT>(L.off, K, L.scan_sh);
-        uint32_t nfull = lds_excl_scan<NT>(L.bbase, K, L.scan_sh);
-        const uint32_t wf = L.wf;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            uint32_t p = e * NT + threadIdx.x;
-            if (p < tn) {
-                uint32_t q = L.off[bk[e]] + rk[e];
-                L.tile[q] = x[e];
-                L.ids[q] = (uint16_t)bk[e];
-            }
-        }
-        __syncthreads();
-        // phase A: buffered elements of buckets that complete a block go to
-        // the front of their first new block (one wavefront per bucket)
         {
-            const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-            for (uint32_t j = wid; j < K; j += NT / 64) {
-                uint32_t f = L.fill[j], nf = (f + L.cnt[j]) / b;
-                if (nf == 0 || f == 0) continue;
-                Elem* dst = seg + (stripe_blk0 + wf + L.bbase[j]) * (uint64_t)b;
-                const Elem* src = buf + (uint64_t)j * b;
-                for (uint32_t i = lane; i < f; i += 64) dst[i] = src[i];
+            // per bucket: run offset (low half) and new blocks (high half).
+            // Stream position pos = fill + rank lies in the open block while
+            // pos < b, else in new block (pos >> lb) - 1 counted from the
+            // first new slot.
+            const uint32_t wf = L.wf;
+            uint64_t v[PER], loc = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < PER; ++q) {
+                const uint32_t jb = threadIdx.x * PER + q;
+                v[q] = 0;
+                if (jb < K) {
+                    const uint32_t cn = L.cnt[jb];
+                    const uint32_t nn = cn ? ((L.fill[jb] + cn - 1) >> lb) : 0u;
+                    v[q] = ((uint64_t)nn << 32) | cn;
+                }
+                loc += v[q];
             }
+            uint64_t total;
+            uint64_t pre = block_excl_scan64<NT>(loc, L.scan_sh, &total);
+#pragma unroll
+            for (uint32_t q = 0; q < PER; ++q) {
+                const uint32_t jb = threadIdx.x * PER + q;
+                if (jb < K) {
+                    const uint32_t o = (uint32_t)pre, ns = wf + (uint32_t)(pre >> 32);
+                    const uint32_t f = L.fill[jb], cn = (uint32_t)v[q], nn = (uint32_t)(v[q] >> 32);
+                    L.off[jb] = o;
+                    L.lim[jb] = (int32_t)(o + b - f);
+                    L.base0[jb] = ((int64_t)L.open[jb] << lb) - (int64_t)o + (int64_t)f;
+                    L.base1[jb] = ((int64_t)ns - 1) * (int64_t)b - (int64_t)o + (int64_t)f;
+                    if (cn) L.fill[jb] = ((f + cn - 1) & (b - 1)) + 1;
+                    if (nn) { L.open[jb] = ns + nn - 1; L.nfull[jb] += nn; }
+                    pre += v[q];
+                }
+            }
+            if (threadIdx.x == 0) L.wf = wf + (uint32_t)(total >> 32);
         }
         __syncthreads();
-        // phase B: tile elements to full blocks or to the buffers
+        scatter_tile<DT, NT, EPT>(L, x, tn, bk, rk);
+        // the registers are free: start loading the next tile
+        if (t0 + TILE < E) load_tile(sp, t0 + TILE, E);
+        __syncthreads();
         for (uint32_t p = threadIdx.x; p < tn; p += NT) {
-            uint32_t j = L.ids[p];
-            uint32_t q = p - L.off[j];
-            uint32_t f = L.fill[j];
-            uint32_t pos = f + q;
-            uint32_t nf = (f + L.cnt[j]) / b;
-            if (pos < nf * b) {
-                uint64_t blk = stripe_blk0 + wf + L.bbase[j] + pos / b;
-                seg[blk * b + (pos % b)] = L.tile[p];
-            } else {
-                buf[(uint64_t)j * b + (pos - nf * b)] = L.tile[p];
-            }
+            const uint32_t jb = L.ids[p];
+            const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
+            sp[d] = L.tile[p];
         }
-        __syncthreads();
-        for (uint32_t j = threadIdx.x; j < K; j += NT) {
-            uint32_t tot = L.fill[j] + L.cnt[j];
-            L.nblk[j] += tot / b;
-            L.fill[j] = tot % b;
-            L.cnt[j] = 0;
-        }
-        if (threadIdx.x == 0) L.wf = wf + nfull;
+        for (uint32_t q = threadIdx.x; q < K; q += NT) L.cnt[q] = 0;
         __syncthreads();
     }
+
+    // ---- phase 2: evacuate partly filled open blocks, then the head
+    for (uint32_t jb = threadIdx.x; jb < K; jb += NT) {
+        const uint32_t f = L.fill[jb];
+        if (f < b) {
+            L.holes[atomicAdd(&L.nholes, 1u)] = L.open[jb];
+            L.nfull[jb] -= 1;               // that block is not full
+        } else {
+            L.fill[jb] = 0;                 // partial buffer starts empty
+        }
+    }
+    __syncthreads();
+    for (uint32_t jb = wid; jb < K; jb += NT / 64) {
+        const uint32_t f = L.fill[jb];
+        if (f == 0) continue;
+        const Elem* src = sp + ((uint64_t)L.open[jb] << lb);
+        Elem* dst = buf + ((uint64_t)jb << lb);
+        for (uint32_t r = lane; r < f; r += 64) dst[r] = src[r];
+    }
+    __syncthreads();
+    const uint32_t O = L.nholes, wf1 = L.wf;
+    auto slot_of = [&](uint32_t a) -> uint32_t { return a < O ? L.holes[a] : wf1 + (a - O); };
+    if (C > 0) load_tile(head, 0, C);
+    for (uint32_t t0 = 0; t0 < C; t0 += TILE) {
+        const uint32_t tn = (C - t0) < TILE ? (C - t0) : TILE;
+        uint32_t bk[EPT], rk[EPT];
+        classify_rank<DT, NT, EPT>(L, x, tn, lkt, st, bk, rk);
+        __syncthreads();
+        {
+            const uint32_t na = L.nalloc;
+            uint64_t v[PER], loc = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < PER; ++q) {
+                const uint32_t jb = threadIdx.x * PER + q;
+                v[q] = 0;
+                if (jb < K) {
+                    const uint32_t cn = L.cnt[jb];
+                    v[q] = ((uint64_t)((L.fill[jb] + cn) >> lb) << 32) | cn;
+                }
+                loc += v[q];
+            }
+            uint64_t total;
+            uint64_t pre = block_excl_scan64<NT>(loc, L.scan_sh, &total);
+#pragma unroll
+            for (uint32_t q = 0; q < PER; ++q) {
+                const uint32_t jb = threadIdx.x * PER + q;
+                if (jb < K) {
+                    L.off[jb] = (uint32_t)pre;
+                    L.abase[jb] = na + (uint32_t)(pre >> 32);
+                    pre += v[q];
+                }
+            }
+            if (threadIdx.x == 0) L.nalloc = na + (uint32_t)(total >> 32);
+        }
+        __syncthreads();
+        scatter_tile<DT, NT, EPT>(L, x, tn, bk, rk);
+        if (t0 + TILE < C) load_tile(head, t0 + TILE, C);
+        __syncthreads();
+        // buffered elements of buckets that complete a block go to the front
+        // of their first new block (one wavefront per bucket)
+        for (uint32_t jb = wid; jb < K; jb += NT / 64) {
+            const uint32_t f = L.fill[jb];
+            if (f == 0 || ((f + L.cnt[jb]) >> lb) == 0) continue;
+            Elem* dst = sp + ((uint64_t)slot_of(L.abase[jb]) << lb);
+            const Elem* src = buf + ((uint64_t)jb << lb);
+            for (uint32_t r = lane; r < f; r += 64) dst[r] = src[r];
+        }
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < tn; p += NT) {
+            const uint32_t jb = L.ids[p];
+            const uint32_t f = L.fill[jb];
+            const uint32_t pos = f + (p - L.off[jb]);
+            const uint32_t nf = (f + L.cnt[jb]) >> lb;
+            const uint32_t blk = pos >> lb;
+            if (blk < nf) sp[((uint64_t)slot_of(L.abase[jb] + blk) << lb) + (pos & (b - 1))] = L.tile[p];
+            else buf[((uint64_t)jb << lb) + (pos - (nf << lb))] = L.tile[p];
+        }
+        __syncthreads();          // the loop above reads fill and cnt
+        for (uint32_t q = threadIdx.x; q < K; q += NT) {
+            const uint32_t tot = L.fill[q] + L.cnt[q];
+            L.nfull[q] += tot >> lb;
+            L.fill[q] = tot & (b - 1);
+            L.cnt[q] = 0;
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 3: holes left over are filled with the last full blocks
+    const uint32_t na = L.nalloc;
+    uint32_t full_blocks;
+    if (na >= O) {
+        full_blocks = wf1 + (na - O);
+    } else {
+        const uint32_t R = O - na;                  // holes[na .. O) stay empty
+        full_blocks = wf1 - R;
+        // sort the remaining holes ascending (rank sort, at most K entries)
+        uint32_t* rest = L.cnt;                     // reuse: cnt is all zero here
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < R; i += NT) {
+            const uint32_t hv = L.holes[na + i];
+            uint32_t rank = 0;
+            for (uint32_t q = 0; q < R; ++q) rank += L.holes[na + q] < hv ? 1u : 0u;
+            rest[rank] = hv;
+        }
+        __syncthreads();
+        // slots [full_blocks, wf1) that are not holes hold full blocks; they
+        // move, in order, to the holes below full_blocks (rest[0 ..))
+        const uint32_t F = full_blocks;
+        for (uint32_t i = wid; i < R; i += NT / 64) {
+            const uint32_t s = F + i;
+            // position of s among the non-hole slots of [F, wf1)
+            uint32_t lo = 0, hi = R;                // holes in rest[] >= F start at hcut
+            while (lo < hi) { uint32_t mid = (lo + hi) / 2; if (rest[mid] < F) lo = mid + 1; else hi = mid; }
+            const uint32_t hcut = lo;
+            bool is_hole = false;
+            uint32_t holes_before = 0;              // holes in [F, s)
+            for (uint32_t q = hcut; q < R; ++q) {
+                if (rest[q] == s) is_hole = true;
+                if (rest[q] < s) ++holes_before;
+            }
+            if (is_hole) continue;
+            const uint32_t idx = (s - F) - holes_before;   // idx-th full block above F
+            const uint32_t dst = rest[idx];                // idx-th hole below F
+            const Word* sw = reinterpret_cast<const Word*>(sp + ((uint64_t)s << lb));
+            Word* dw = reinterpret_cast<Word*>(sp + ((uint64_t)dst << lb));
+            for (uint32_t w = lane; w < (b * WPE); w += 64) dw[w] = sw[w];
+        }
+    }
+    __syncthreads();
     uint32_t* cnt_out = c.counts + (uint64_t)blockIdx.x * KMAX;
-    for (uint32_t j = threadIdx.x; j < K; j += NT) cnt_out[j] = L.nblk[j] * b + L.fill[j];
-    if (threadIdx.x == 0) c.stripe_full[blockIdx.x] = L.wf;
+    for (uint32_t q = threadIdx.x; q < K; q += NT) cnt_out[q] = (L.nfull[q] << lb) + L.fill[q];
+    if (threadIdx.x == 0) c.stripe_full[blockIdx.x] = full_blocks;
 }
 
 // --------------------------------------------------------------- scan
@@ -1067,6 +1335,75 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
             else seg[i] = scr[lds[pidx(i)].i];
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------ phase invariant checks
+// Debug only.  After local classification (Section 4.1): every stripe is
+// [full blocks | empty blocks], each full block holds one bucket, and the
+// full blocks plus the partial buffers reproduce the stored counts.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_check_classify(Ctx<DT> c) {
+    using TR = Traits<DT>;
+    __shared__ TreeLds<DT> tr;
+    __shared__ uint32_t hist[KMAX];
+    const StripeD sd = c.stripes[blockIdx.x];
+    const TaskD td = c.tasks[sd.task];
+    const TaskS st = c.ts[sd.task];
+    const uint32_t b = c.b, K = st.K, lkt = ilog2(st.kt);
+    load_tree<DT>(c, td, st.kt, st.nuniq, tr);
+    for (uint32_t j = threadIdx.x; j < K; j += NT) hist[j] = 0;
+    __syncthreads();
+    const uint32_t F = c.stripe_full[blockIdx.x];
+    const typename TR::Elem* sp = c.data + td.off + (uint64_t)sd.blk_begin * b;
+    if ((uint64_t)(sd.blk_begin + F) * b > td.m || sd.blk_begin + F > sd.blk_end) {
+        if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
+        return;
+    }
+    for (uint64_t i = threadIdx.x; i < (uint64_t)F * b; i += NT) {
+        const uint32_t bj = classify_key(TR::key(sp[i]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
+        const uint32_t b0 = classify_key(TR::key(sp[(i / b) * b]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
+        if (bj != b0) raise_err_at(c.err, ERR_CHECK_BLOCK, (uint32_t)i, bj, b0);
+        atomicAdd(&hist[bj], 1u);
+    }
+    const uint32_t* cnt = c.counts + (uint64_t)blockIdx.x * KMAX;
+    for (uint32_t j = 0; j < K; ++j) {
+        const uint32_t f = cnt[j] % b;
+        for (uint32_t r = threadIdx.x; r < f; r += NT) {
+            const uint32_t bj = classify_key(TR::key(c.bufs[sd.buf_off + (uint64_t)j * b + r]), tr.tree, tr.spl,
+                                             lkt, st.nuniq, st.eq);
+            if (bj != j) raise_err_at(c.err, ERR_CHECK_COUNT, r, bj, j);
+            atomicAdd(&hist[bj], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < K; j += NT)
+        if (hist[j] != cnt[j]) raise_err_at(c.err, ERR_CHECK_COUNT, j, hist[j], cnt[j]);
+}
+
+// After the block permutation (Section 4.2 invariant at the end): every
+// block in [d_i, w_i) holds only elements of bucket i.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c) {
+    using TR = Traits<DT>;
+    __shared__ TreeLds<DT> tr;
+    const uint32_t t = blockIdx.y;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = blockIdx.x;
+    if (j >= st.K) return;
+    const uint32_t b = c.b, lkt = ilog2(st.kt);
+    load_tree<DT>(c, td, st.kt, st.nuniq, tr);
+    const uint32_t d0 = c.delim[td.slot_begin + t + j];
+    const uint32_t w = (uint32_t)(c.slots[td.slot_begin + j].wr >> 32);
+    const bool partial = (td.m % b) != 0;
+    const typename TR::Elem* seg = c.data + td.off;
+    for (uint32_t q = d0; q < w; ++q) {
+        const typename TR::Elem* blk = (partial && q == st.nblocks - 1) ? c.ovf + (uint64_t)t * b : seg + (uint64_t)q * b;
+        for (uint32_t r = threadIdx.x; r < b; r += NT) {
+            const uint32_t bj = classify_key(TR::key(blk[r]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
+            if (bj != j) raise_err_at(c.err, ERR_CHECK_PLACED, q, bj, j);
+        }
     }
 }
 

@@ -225,6 +225,26 @@ def test_sort_many_small_tasks_repeated(env):
         assert np.array_equal(out, np.sort(inp)), (rep, dist)
 
 
+@pytest.mark.parametrize("dist", ["uniform", "twodup", "sorted", "ones", "eightdup"])
+def test_phase_invariants_checked_on_device(env, dist):
+    """With the debug flag the library verifies, after classification, that
+    every stripe is [full blocks | empty blocks] with single-bucket full
+    blocks and exact counts, and after the permutation that every block in
+    [d_i, w_i) holds bucket i; any violation makes the call fail."""
+    torch, ips, h = env
+    for n, k in [(70001, 256), (300001, 16), (1 << 20, 256), (1 << 20, 512)]:
+        inp = workloads.generate(dist, "u64", n, 77 + n)
+        out = gpu_sort(env, inp, "u64", {"k": k, "flags": 4})
+        assert np.array_equal(out, np.sort(inp)), (dist, n, k)
+    for m in (3, 255, 511):
+        inp = workloads.generate(dist, "u64", 200003, m)
+        sp = _splitters(inp, "u64", m, m, dup=(dist != "uniform"))
+        d = to_dev(torch, inp)
+        gb = ips.ips4o_distribute(h, d, inp.shape[0], "u64", sp, dist != "uniform", {"flags": 4})
+        _, bounds = oracle.bucket_bounds(inp, sp, "u64", dist != "uniform")
+        assert np.array_equal(gb, bounds)
+
+
 # ------------------------------------------------------- classification
 @pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
 @pytest.mark.parametrize("eq", [False, True])

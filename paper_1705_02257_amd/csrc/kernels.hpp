@@ -23,6 +23,8 @@
 // Block indices are relative to the task's segment start; block q covers
 // elements [q*b, (q+1)*b) of the segment, the last block may be partial.
 #pragma once
+#include <type_traits>
+
 #include "traits.hpp"
 
 namespace ips4o {
@@ -172,7 +174,7 @@ __device__ inline uint32_t upper_find(uint32_t n, uint64_t x, F begin) {
 // ------------------------------------------------------------ block scan
 // Exclusive scan of one value per thread over the workgroup (NT threads).
 // `sh` needs NT/64 + 1 entries.  Returns the exclusive prefix; *total gets
-// the sum.  Contains barriers: call from every thread.
+// the sum.  Contains LDS-only barriers: call from every thread.
 template <int NT>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
     constexpr int NW = NT / 64;
@@ -184,7 +186,7 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
         if (lane >= (uint32_t)d) inc += t;
     }
     if (lane == 63) sh[wid] = inc;
-    __syncthreads();
+    lds_barrier();
     if (wid == 0) {
         uint32_t t = lane < NW ? sh[lane] : 0u, ti = t;
 #pragma unroll
@@ -195,10 +197,10 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* t
         if (lane < NW) sh[lane] = ti - t;
         if (lane == NW - 1) sh[NW] = ti;
     }
-    __syncthreads();
+    lds_barrier();
     uint32_t r = inc - v + sh[wid];
     *total = sh[NW];
-    __syncthreads();
+    lds_barrier();
     return r;
 }
 
@@ -218,7 +220,7 @@ __device__ inline uint32_t lds_excl_scan(uint32_t* arr, uint32_t n, uint32_t* sh
             arr[b0 + i] = pre;
             pre += v;
         }
-    __syncthreads();
+    lds_barrier();
     return total;
 }
 
@@ -415,7 +417,7 @@ __device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* sh, uint64_t*
         if (lane >= (uint32_t)d) inc += t;
     }
     if (lane == 63) sh[wid] = inc;
-    __syncthreads();
+    lds_barrier();
     if (wid == 0) {
         uint64_t t = lane < NW ? sh[lane] : 0ull, ti = t;
 #pragma unroll
@@ -426,10 +428,10 @@ __device__ inline uint64_t block_excl_scan64(uint64_t v, uint64_t* sh, uint64_t*
         if (lane < NW) sh[lane] = ti - t;
         if (lane == NW - 1) sh[NW] = ti;
     }
-    __syncthreads();
+    lds_barrier();
     uint64_t r = inc - v + sh[wid];
     *total = sh[NW];
-    __syncthreads();
+    lds_barrier();
     return r;
 }
 
@@ -461,7 +463,7 @@ __device__ inline void classify_batch(const Key (&k)[EPT], uint32_t (&out)[EPT],
 // Classify the tile held in x[] (tn valid elements) and rank every element
 // within its bucket: one LDS atomic per wavefront when all its lanes share a
 // bucket (skewed inputs), else one per element.
-template <int DT, int NT, int EPT>
+template <int DT, int NT, int EPT, bool FULL>
 __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename Traits<DT>::Elem (&x)[EPT],
                                      uint32_t tn, uint32_t lkt, const TaskS& st, uint32_t (&bk)[EPT],
                                      uint32_t (&rk)[EPT]) {
@@ -473,7 +475,7 @@ __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const uint32_t p = e * NT + threadIdx.x;
-        const bool valid = p < tn;
+        const bool valid = FULL || p < tn;
         const uint64_t vmask = __ballot(valid);
         const uint32_t b0 = __builtin_amdgcn_readfirstlane(bk[e]);
         const uint64_t same = __ballot(valid && bk[e] == b0);
@@ -490,13 +492,13 @@ __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename
     }
 }
 
-template <int DT, int NT, int EPT>
+template <int DT, int NT, int EPT, bool FULL>
 __device__ inline void scatter_tile(ClassifyLds<DT, NT, EPT>& L, const typename Traits<DT>::Elem (&x)[EPT],
                                     uint32_t tn, const uint32_t (&bk)[EPT], const uint32_t (&rk)[EPT]) {
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const uint32_t p = e * NT + threadIdx.x;
-        if (p < tn) {
+        if (FULL || p < tn) {
             const uint32_t q = L.off[bk[e]] + rk[e];
             L.tile[q] = x[e];
             L.ids[q] = (uint16_t)bk[e];
@@ -538,22 +540,29 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     for (uint32_t i = threadIdx.x; i < C; i += NT) head[i] = sp[i];
     __syncthreads();
 
-    // ---- phase 1: the rest of the stripe, straight into open blocks
+    // ---- phase 1: the rest of the stripe, straight into open blocks.
+    // Full tiles take a path without per-element guards: straight-line
+    // loads and stores let the compiler wait for exactly the loads it needs
+    // instead of every outstanding memory operation.
     Elem x[EPT];
     auto load_tile = [&](const Elem* src, uint32_t t0, uint32_t end) {
         const uint32_t rem = end > t0 ? end - t0 : 0u;
+        if (rem >= TILE) {
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const uint32_t p = e * NT + threadIdx.x;
-            if (p < rem) x[e] = src[t0 + p];
+            for (int e = 0; e < EPT; ++e) x[e] = src[t0 + e * NT + threadIdx.x];
+        } else {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t p = e * NT + threadIdx.x;
+                if (p < rem) x[e] = src[t0 + p];
+            }
         }
     };
-    if (C < E) load_tile(sp, C, E);
-    for (uint32_t t0 = C; t0 < E; t0 += TILE) {
-        const uint32_t tn = (E - t0) < TILE ? (E - t0) : TILE;
+    auto phase1_tile = [&](uint32_t t0, uint32_t tn, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
         uint32_t bk[EPT], rk[EPT];
-        classify_rank<DT, NT, EPT>(L, x, tn, lkt, st, bk, rk);
-        __syncthreads();
+        classify_rank<DT, NT, EPT, FULL>(L, x, tn, lkt, st, bk, rk);
+        lds_barrier();
         {
             // per bucket: run offset (low half) and new blocks (high half).
             // Stream position pos = fill + rank lies in the open block while
@@ -591,19 +600,50 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             }
             if (threadIdx.x == 0) L.wf = wf + (uint32_t)(total >> 32);
         }
-        __syncthreads();
-        scatter_tile<DT, NT, EPT>(L, x, tn, bk, rk);
-        // the registers are free: start loading the next tile
-        if (t0 + TILE < E) load_tile(sp, t0 + TILE, E);
-        __syncthreads();
-        for (uint32_t p = threadIdx.x; p < tn; p += NT) {
-            const uint32_t jb = L.ids[p];
-            const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
-            sp[d] = L.tile[p];
+        lds_barrier();
+        scatter_tile<DT, NT, EPT, FULL>(L, x, tn, bk, rk);
+        lds_barrier();
+        if constexpr (FULL) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t p = e * NT + threadIdx.x;
+                const uint32_t jb = L.ids[p];
+                const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
+                sp[d] = L.tile[p];
+            }
+        } else {
+            for (uint32_t p = threadIdx.x; p < tn; p += NT) {
+                const uint32_t jb = L.ids[p];
+                const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
+                sp[d] = L.tile[p];
+            }
         }
         for (uint32_t q = threadIdx.x; q < K; q += NT) L.cnt[q] = 0;
-        __syncthreads();
+        lds_barrier();
+    };
+    if (C < E) load_tile(sp, C, E);
+    uint32_t t0 = C;
+    {
+        // steady state: the next tile is full too.  Its loads go to a second
+        // register set at the start of the iteration; the body has no other
+        // loads and no data-dependent branches around memory operations, so
+        // waiting for those loads later does not wait for this tile's stores.
+        Elem xn[EPT];
+        for (; t0 + 2 * TILE <= E; t0 += TILE) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) xn[e] = sp[t0 + TILE + e * NT + threadIdx.x];
+            phase1_tile(t0, TILE, std::true_type{});
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) x[e] = xn[e];
+        }
     }
+    for (; t0 < E; t0 += TILE) {
+        const uint32_t tn = (E - t0) < TILE ? (E - t0) : TILE;
+        if (tn == TILE) phase1_tile(t0, TILE, std::true_type{});
+        else phase1_tile(t0, tn, std::false_type{});
+        if (t0 + TILE < E) load_tile(sp, t0 + TILE, E);
+    }
+    __syncthreads();        // phase 1's stores are read back in phase 2
 
     // ---- phase 2: evacuate partly filled open blocks, then the head
     for (uint32_t jb = threadIdx.x; jb < K; jb += NT) {
@@ -630,7 +670,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     for (uint32_t t0 = 0; t0 < C; t0 += TILE) {
         const uint32_t tn = (C - t0) < TILE ? (C - t0) : TILE;
         uint32_t bk[EPT], rk[EPT];
-        classify_rank<DT, NT, EPT>(L, x, tn, lkt, st, bk, rk);
+        classify_rank<DT, NT, EPT, false>(L, x, tn, lkt, st, bk, rk);
         __syncthreads();
         {
             const uint32_t na = L.nalloc;
@@ -659,7 +699,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             if (threadIdx.x == 0) L.nalloc = na + (uint32_t)(total >> 32);
         }
         __syncthreads();
-        scatter_tile<DT, NT, EPT>(L, x, tn, bk, rk);
+        scatter_tile<DT, NT, EPT, false>(L, x, tn, bk, rk);
         if (t0 + TILE < C) load_tile(head, t0 + TILE, C);
         __syncthreads();
         // buffered elements of buckets that complete a block go to the front

@@ -164,4 +164,15 @@ __device__ inline uint32_t read_lane(uint32_t v, uint32_t src) {
 // wait for every outstanding vector memory operation of this wave
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Workgroup barrier that orders LDS only: waits for this wave's LDS
+// operations (lgkmcnt 0) but not for its global loads and stores, so loads
+// issued ahead of time stay in flight across it.  Use __syncthreads() where
+// other waves must see this wave's global stores.
+__device__ inline void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0); vmcnt, expcnt unconstrained
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 }  // namespace ips4o

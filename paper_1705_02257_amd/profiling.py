@@ -1,0 +1,138 @@
+"""Turn rocprofv3 CSV output into the short summaries kept under profiles/.
+
+    python -m paper_1705_02257_amd.profiling stats  TRACE_DIR  OUT.md  --command "..."
+    python -m paper_1705_02257_amd.profiling traffic FETCH_DIR WRITE_DIR OUT_DIR \
+        --copy-bytes N --command "..."
+
+`stats` reads the kernel_stats.csv of a `rocprofv3 --kernel-trace --stats
+--output-format csv` run and writes a markdown table (calls, total and
+average duration per kernel) headed by the command that produced it.
+
+`traffic` reads the counter_collection.csv of two `rocprofv3 --pmc` runs of
+the same program, one with FETCH_SIZE and one with WRITE_SIZE (KiB per
+dispatch).  The program must contain one plain device-to-device copy of
+`copy-bytes` bytes (the largest copyBuffer dispatch): the ratio between its
+known size and what each counter reports for it is the calibration factor
+applied to every other dispatch.  For each library kernel it writes
+traffic_<kind>.json with the calibrated HBM bytes per launch, stamped with
+the hash of the kernel sources the counters were taken on.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "traits.hpp", "driver.hip")]
+
+# mangled-name fragment -> the kernel kinds the library reports timings under
+KINDS = [("k_sample", "sample"), ("k_classify", "classify"), ("k_scan", "scan"),
+         ("k_fix_empty", "fix_empty"), ("k_permute", "permute"), ("k_cleanup", "cleanup"),
+         ("k_basecase", "basecase")]
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kind_of(name: str):
+    for frag, kind in KINDS:
+        if re.search(r"\b" + frag + r"\b", name):
+            return kind
+    return None
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def stats_summary(trace_dir: str, command: str) -> str:
+    rows = list(csv.DictReader(open(_find(trace_dir, "kernel_stats.csv"))))
+    out = ["# Kernel time (rocprofv3 --kernel-trace --stats)", "", "Command:", "",
+           "```", command, "```", "",
+           "| kernel | calls | total ms | average us | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        name = r["Name"]
+        short = re.sub(r"\(.*", "", name).replace("void ", "")
+        out.append(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter(d: str, counter: str):
+    per = []
+    for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+        if r["Counter_Name"] == counter:
+            per.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return per
+
+
+def traffic(fetch_dir: str, write_dir: str, copy_bytes: int):
+    """Calibrated HBM bytes per launch of every library kernel kind."""
+    fetch = _counter(fetch_dir, "FETCH_SIZE")
+    write = _counter(write_dir, "WRITE_SIZE")
+    if len(fetch) != len(write):
+        raise ValueError("the FETCH_SIZE and WRITE_SIZE runs saw different dispatch lists")
+    cf = max(v for n, v in fetch if n.startswith(COPY)) * 1024.0
+    cw = max(v for n, v in write if n.startswith(COPY)) * 1024.0
+    sf, sw = copy_bytes / cf, copy_bytes / cw
+    acc = {}
+    for (nf, vf), (nw, vw) in zip(fetch, write):
+        if nf != nw:
+            raise ValueError("dispatch order differs between the two runs")
+        kind = kind_of(nf)
+        if kind is None:
+            continue
+        a = acc.setdefault(kind, {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0})
+        a["launches"] += 1
+        a["fetch_kib"] += vf
+        a["write_kib"] += vw
+    for a in acc.values():
+        a["hbm_bytes_per_launch"] = (a["fetch_kib"] * sf + a["write_kib"] * sw) * 1024.0 / a["launches"]
+    return acc, sf, sw
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("trace_dir")
+    s.add_argument("out")
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("out_dir")
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command", required=True)
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        with open(a.out, "w") as f:
+            f.write(stats_summary(a.trace_dir, a.command))
+        return 0
+    acc, sf, sw = traffic(a.fetch_dir, a.write_dir, a.copy_bytes)
+    sha = source_sha()
+    for kind, rec in acc.items():
+        rec.update({"kernel": kind, "source_sha": sha, "scale_fetch": sf, "scale_write": sw,
+                    "copy_bytes": a.copy_bytes, "command": a.command})
+        with open(os.path.join(a.out_dir, f"traffic_{kind}.json"), "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+    print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e9, 3) for k, v in acc.items()}), file=sys.stderr)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

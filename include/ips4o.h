@@ -70,8 +70,9 @@ typedef enum {
  *               block_bytes / s))) elements (default 2048, as in the paper).
  *   base_cap    largest subproblem (elements) sorted by the base case
  *               (default and maximum depend on the dtype).
- *   alpha_x100  oversampling factor times 100 (default 0.2 * log2 n, at
- *               least 1).
+ *   alpha_x100  oversampling factor times 100, used on every level (default:
+ *               0.2 * log2 m for a subproblem of m elements, raised to
+ *               min(32, sample capacity / k)).
  *   stripes     classification workgroups for the first level (default:
  *               chosen from n).
  *   workers     permutation workers (wavefronts) per level (default: chosen

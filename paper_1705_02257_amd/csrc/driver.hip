@@ -27,6 +27,7 @@ using namespace ips4o;
 namespace {
 
 constexpr uint32_t kDefaultK = 256;
+constexpr size_t kStatsOffset = 1024;        // misc: error word at 0, counters here
 constexpr uint32_t kDefaultBlockBytes = 2048;
 constexpr uint32_t kMaxBlockBytes = 8192;
 constexpr uint64_t kDefaultSeed = 0x1705022570ull;
@@ -102,7 +103,7 @@ struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
     Arena work;       // per-level workspace
-    Arena misc;       // error word, stats, ticket
+    Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
     ips4o_stats last{};
@@ -219,18 +220,21 @@ bool log_enabled() {
     return on == 1;
 }
 
-// Oversampling factor.  The first level uses the paper's 0.2 log2 n (at
-// least 1).  Deeper levels feed the base case, whose capacity is fixed: a
-// bucket just above it costs a whole further level, while sampling costs
-// little on the GPU, so they oversample up to the LDS sample capacity
-// (at most 16).  An explicit alpha applies to every level.
+// Oversampling factor: the paper's 0.2 log2 n (at least 1), raised to the
+// LDS sample capacity (at most 32 per bucket).  Every level ends in the base
+// case, whose capacity is fixed: the relative spread of bucket sizes falls
+// as 1/sqrt(alpha), a bucket just above the capacity costs a whole further
+// level, and sampling costs little on the GPU.  An explicit alpha applies
+// to every level as given.
 template <int DT>
-uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k, bool first) {
+uint32_t alpha_for(uint64_t m, const Resolved& R, uint32_t k) {
     const uint32_t smax = (uint32_t)sample_max<typename Traits<DT>::Key>();
     uint32_t a;
     if (R.alpha_x100) a = std::max(1u, R.alpha_x100 / 100);
-    else a = std::max<uint32_t>(1u, (uint32_t)std::floor(0.2 * std::log2((double)std::max<uint64_t>(m, 2))));
-    if (!first && !R.alpha_x100) a = std::max(a, std::min(16u, smax / k));
+    else {
+        a = std::max<uint32_t>(1u, (uint32_t)std::floor(0.2 * std::log2((double)std::max<uint64_t>(m, 2))));
+        a = std::max(a, std::min(32u, smax / k));
+    }
     while (a > 1 && (uint64_t)a * k > (uint64_t)smax) --a;
     return a;
 }
@@ -301,6 +305,7 @@ struct Level {
     using Elem = typename TR::Elem;
     std::vector<TaskD> tasks;
     std::vector<StripeD> stripes;
+    std::vector<uint32_t> order;     // classification launch order
     uint32_t total_slots = 0, total_tree = 0, total_workers = 0;
     uint64_t total_buf = 0;
     Ctx<DT> c{};
@@ -317,6 +322,22 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     }
     L.tasks.clear();
     L.stripes.clear();
+    // Stripes per task: kLevelStripes shared out in proportion to the task
+    // sizes (largest remainders, at least one each), so that a level that
+    // fits in one round of workgroups per CU leaves no partial last round.
+    std::vector<uint64_t> share(segs.size(), 1);
+    if (segs.size() < kLevelStripes) {
+        std::vector<std::pair<double, size_t>> rem;
+        uint64_t given = 0;
+        for (size_t i = 0; i < segs.size(); ++i) {
+            const double q = (double)kLevelStripes * (double)segs[i].m / (double)total_m;
+            share[i] = std::max<uint64_t>(1, (uint64_t)q);
+            given += share[i];
+            rem.push_back({q - std::floor(q), i});
+        }
+        std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (size_t r = 0; given < kLevelStripes && r < rem.size(); ++r, ++given) share[rem[r].second] += 1;
+    }
     uint32_t slot = 0, treeb = 0, wk = 0;
     uint64_t bufoff = 0;
     for (size_t i = 0; i < segs.size(); ++i) {
@@ -329,15 +350,13 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         else if (first) k = R.k;
         else k = std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * s.m + R.cap - 1) / R.cap)));
         t.k = k;
-        t.alpha = alpha_for<DT>(s.m, R, k, first);
+        t.alpha = alpha_for<DT>(s.m, R, k);
         t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
         const uint64_t nb = (s.m + b - 1) / b;
-        // stripes: enough blocks per stripe to keep the partial buffers small
-        // (at least 8 buffer sets of k blocks each), and about kLevelStripes
-        // stripes over the whole level
+        // stripes: the task's share, but enough blocks per stripe to keep
+        // the partial buffers small (at least 8 buffer sets of k blocks each)
         uint64_t by_size = nb / (8ull * k);
-        uint64_t by_share = (uint64_t)std::ceil((double)kLevelStripes * (double)s.m / (double)total_m);
-        uint64_t ns = std::max<uint64_t>(1, std::min(by_size, by_share));
+        uint64_t ns = std::max<uint64_t>(1, std::min(by_size, share[i]));
         if (first && R.stripes) ns = R.stripes;
         ns = std::min<uint64_t>(ns, std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
         t.stripe_begin = (uint32_t)L.stripes.size();
@@ -362,6 +381,18 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         treeb += k;
         L.tasks.push_back(t);
     }
+    // classification launch order: largest stripes first, so that the
+    // workgroups dispatched last are the short ones (longest processing
+    // time first)
+    L.order.resize(L.stripes.size());
+    for (size_t q = 0; q < L.order.size(); ++q) L.order[q] = (uint32_t)q;
+    auto stripe_len = [&](uint32_t q) {
+        const StripeD& sd = L.stripes[q];
+        const uint64_t e = std::min<uint64_t>((uint64_t)sd.blk_end * b, L.tasks[sd.task].m);
+        return e - (uint64_t)sd.blk_begin * b;
+    };
+    std::stable_sort(L.order.begin(), L.order.end(),
+                     [&](uint32_t x, uint32_t y) { return stripe_len(x) > stripe_len(y); });
     L.total_slots = slot;
     L.total_tree = treeb;
     L.total_workers = wk;
@@ -384,6 +415,7 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     add((L.total_slots + T) * sizeof(uint32_t));
     add(L.total_slots * sizeof(BucketSlot));
     add(S * (size_t)KMAX * sizeof(uint32_t));
+    add(S * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(L.total_buf * sizeof(Elem));
     add(T * (size_t)b * sizeof(Elem));
@@ -408,14 +440,14 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolve
     c.slots = cv.take<BucketSlot>(L.total_slots);
     c.counts = cv.take<uint32_t>(S * (size_t)KMAX);
     c.stripe_full = cv.take<uint32_t>(S);
+    c.order = cv.take<uint32_t>(S);
     c.bufs = cv.take<Elem>(L.total_buf);
     c.ovf = cv.take<Elem>(T * (size_t)R.b);
     c.ntasks = (uint32_t)T;
     c.nstripes = (uint32_t)S;
     char* m = (char*)misc;
     c.err = (uint32_t*)m;
-    c.ticket = (uint32_t*)(m + 64);
-    c.stats = (unsigned long long*)(m + 128);
+    c.stats = (unsigned long long*)(m + kStatsOffset);
     c.b = R.b;
     c.spin_limit = R.spin;
     c.total_workers = L.total_workers;
@@ -466,6 +498,7 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     const size_t T = L.tasks.size(), S = L.stripes.size();
     HIP_TRY(hipMemcpyAsync((void*)c.tasks, L.tasks.data(), T * sizeof(TaskD), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync((void*)c.stripes, L.stripes.data(), S * sizeof(StripeD), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)c.order, L.order.data(), S * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (given) {
         HIP_TRY(hipMemcpyAsync(c.tree, given->tree.data(), given->tree.size() * sizeof(Key), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
@@ -506,12 +539,29 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
         hipLaunchKernelGGL((k_check_permute<DT, 256>), dim3(kmax, T), dim3(256), 0, st, c);
         HIP_TRY(hipGetLastError());
     }
-    const size_t cl_lds = (size_t)c.b * sizeof(Elem);
-    HIP_TRY(hipFuncSetAttribute((const void*)k_cleanup<DT, 256>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)cl_lds));
+    // cleanup: a bucket has a source (under a block) per stripe, plus the
+    // overhang and the overflow block; with many stripes the sources are
+    // split over several workgroups
+    uint32_t kmax = 0, nsmax = 1;
+    for (const TaskD& t : L.tasks) {
+        kmax = std::max(kmax, 2 * t.k);
+        nsmax = std::max(nsmax, t.nstripes);
+    }
+    const uint32_t parts = std::min<uint32_t>(32, std::max<uint32_t>(1, (nsmax + 2) / 16));
     mk.cleanup = tm.begin(KK_CLEANUP);
-    hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(L.total_slots), dim3(256), cl_lds, st, c);
-    HIP_TRY(hipGetLastError());
+    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+        hipLaunchKernelGGL((k_overhang<DT, 256>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
+        HIP_TRY(hipGetLastError());
+    }
+    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+        if (nsmax + 2 <= 64)
+            hipLaunchKernelGGL((k_cleanup_narrow<DT>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
+        else
+            hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(kmax * parts, nt), dim3(256), 0, st, c, parts, t0);
+        HIP_TRY(hipGetLastError());
+    }
     tm.end(mk.cleanup, 0.0);
     return IPS4O_OK;
 }
@@ -540,7 +590,7 @@ int check_device_error(ips4o_handle* h, hipStream_t st) {
 int reset_misc(ips4o_handle* h, hipStream_t st) {
     int rc = h->misc.ensure(4096);
     if (rc) return rc;
-    HIP_TRY(hipMemsetAsync(h->misc.p, 0, 256, st));
+    HIP_TRY(hipMemsetAsync(h->misc.p, 0, kStatsOffset + STAT_SPREAD * 64, st));
     return IPS4O_OK;
 }
 
@@ -553,31 +603,34 @@ int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>
     bounds.resize(L.total_slots + T);
     HIP_TRY(hipMemcpyAsync(ts.data(), L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(bounds.data(), L.c.bounds, bounds.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(stats, L.c.stats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    return check_device_error(h, st);
+    unsigned long long spread[STAT_SPREAD * 8];
+    HIP_TRY(hipMemcpyAsync(spread, L.c.stats, sizeof(spread), hipMemcpyDeviceToHost, st));
+    const int rc = check_device_error(h, st);
+    for (int q = 0; q < 4; ++q) {
+        stats[q] = 0;
+        for (int r = 0; r < STAT_SPREAD; ++r) stats[q] += spread[r * 8 + q];
+    }
+    return rc;
 }
 
-// Pack base-case segments into bins of at most `cap` consecutive elements.
-// A bin spans whole buckets in array order: the buckets of one partition
-// hold disjoint key ranges in ascending order, and whatever lies between two
-// listed segments is already final (equality buckets, buckets of at most one
-// element), so sorting the span sorts each bucket in place exactly as
-// sorting them one by one would.
-std::vector<SegD> pack_bins(std::vector<SegD> segs, uint32_t cap) {
-    std::sort(segs.begin(), segs.end(), [](const SegD& a, const SegD& b) { return a.off < b.off; });
-    std::vector<SegD> bins;
-    for (const SegD& s : segs) {
-        if (!bins.empty()) {
-            SegD& cur = bins.back();
-            const uint64_t end = s.off + s.len;
-            if (end - cur.off <= cap) {
-                cur.len = (uint32_t)(end - cur.off);
-                continue;
-            }
+// Base-case segments are packed into bins of at most `cap` consecutive
+// elements as a level lists them (in array order).  A bin spans whole
+// buckets of one level: the buckets of one partition hold disjoint key
+// ranges in ascending order, and whatever lies between two listed segments
+// of a level is already final (equality buckets, buckets of at most one
+// element) or is a bucket larger than `cap` (which no bin can span), so
+// sorting the span sorts each bucket in place exactly as sorting them one
+// by one would.  `first` is the index of the level's first bin.
+void add_to_bins(std::vector<SegD>& bins, size_t first, uint64_t off, uint64_t len, uint32_t cap) {
+    if (bins.size() > first) {
+        SegD& cur = bins.back();
+        const uint64_t end = off + len;
+        if (end - cur.off <= cap) {
+            cur.len = (uint32_t)(end - cur.off);
+            return;
         }
-        bins.push_back(s);
     }
-    return bins;
+    bins.push_back(SegD{off, (uint32_t)len, 0});
 }
 
 template <int DT>
@@ -603,7 +656,8 @@ int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, c
     Ctx<DT> c{};
     c.data = (Elem*)d_data;
     using It = typename BaseItem<DT>::T;
-    const size_t lds = (size_t)(R.cap + (R.cap + BVT - 1) / BVT) * sizeof(It);
+    const size_t lds = ((BNT * sizeof(uint32_t) + 15) & ~size_t(15)) +
+                       (size_t)(R.cap + (R.cap + BVT - 1) / BVT + BVT) * sizeof(It);
     HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
@@ -627,7 +681,10 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     if (rc) return rc;
     std::vector<SegD> base;
     std::vector<Seg> cur;
-    if (n <= R.cap) base.push_back(SegD{0, (uint32_t)n, 0});
+    if (n <= R.cap) {
+        base.push_back(SegD{0, (uint32_t)n, 0});
+        h->last.elements_base = n;
+    }
     else cur.push_back(Seg{0, n});
     uint32_t level = 0;
     Level<DT> L;
@@ -663,6 +720,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         h->last.block_skips = stats[1];
         for (const Seg& s : cur) h->last.elements_distributed += s.m;
         std::vector<Seg> next;
+        const size_t first_bin = base.size();
         for (size_t t = 0; t < L.tasks.size(); ++t) {
             const TaskD& td = L.tasks[t];
             const uint64_t* bd = bounds.data() + td.slot_begin + t;
@@ -671,7 +729,10 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
                 if (sz <= 1) continue;
                 if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
                 uint64_t off = td.off + bd[i];
-                if (sz <= R.cap) base.push_back(SegD{off, (uint32_t)sz, 0});
+                if (sz <= R.cap) {
+                    add_to_bins(base, first_bin, off, sz, R.cap);
+                    h->last.elements_base += sz;
+                }
                 else next.push_back(Seg{off, sz});
             }
         }
@@ -679,8 +740,6 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         ++level;
     }
     h->last.levels = level;
-    for (const SegD& s : base) h->last.elements_base += s.len;
-    base = pack_bins(base, R.cap);
     rc = run_basecase<DT>(h, d_data, base, R, st, tm);
     if (rc) return rc;
     rc = check_device_error(h, st);

@@ -73,7 +73,7 @@ struct TaskS {                  // device-written per task
 struct alignas(256) BucketSlot {
     uint64_t wr;        // (w << 32) | (r + 2^31), block indices in the segment
     uint32_t readers;   // workers currently reading a block of this bucket
-    uint32_t flag;      // cleanup: overhang saved
+    uint32_t flag;      // unused
     uint32_t rinit;     // r at the start of the permutation (last full block)
     uint32_t pad[59];
 };
@@ -97,11 +97,11 @@ struct Ctx {
     BucketSlot* slots;          // [sum 2k]: slot_begin + i
     uint32_t* counts;           // [stripes][KMAX]
     uint32_t* stripe_full;      // [stripes] full blocks after classification
+    const uint32_t* order;      // [stripes] classification launch order (largest first)
     Elem* bufs;                 // stripe bucket buffers
     Elem* ovf;                  // [tasks][b]
     uint32_t* err;              // device error word (0 = ok)
     unsigned long long* stats;  // [0] block moves, [1] skips, [2] cleanup placements, [3] fix moves
-    uint32_t* ticket;           // cleanup workgroup ticket
     uint32_t b;                 // elements per block
     uint32_t spin_limit;
     uint32_t total_workers;
@@ -120,6 +120,15 @@ enum ErrCode : uint32_t {
 
 __device__ inline void raise_err(uint32_t* err, uint32_t code) {
     __hip_atomic_fetch_or(err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Per-level counters (0 block moves, 1 skipped in-place blocks, 2 elements
+// placed by the cleanup, 3 empty-block fix moves), each kept in STAT_SPREAD
+// copies on separate cache lines: per-bucket updates from many workgroups
+// would otherwise serialize on one address.  The host sums the copies.
+constexpr int STAT_SPREAD = 32;
+__device__ inline void stat_add(unsigned long long* stats, int which, unsigned long long v, uint32_t key) {
+    atomicAdd(&stats[(key % STAT_SPREAD) * 8 + which], v);
 }
 
 // first failure details for diagnostics: err[48..52) = {code, a, b, c}
@@ -517,7 +526,8 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     auto& L = *reinterpret_cast<ClassifyLds<DT, NT, EPT>*>(smem_raw);
 
-    const StripeD sd = c.stripes[blockIdx.x];
+    const uint32_t sid = c.order[blockIdx.x];
+    const StripeD sd = c.stripes[sid];
     const TaskD td = c.tasks[sd.task];
     const TaskS st = c.ts[sd.task];
     const uint32_t b = c.b, lb = ilog2(c.b), K = st.K, lkt = ilog2(st.kt);
@@ -773,26 +783,43 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
         }
     }
     __syncthreads();
-    uint32_t* cnt_out = c.counts + (uint64_t)blockIdx.x * KMAX;
+    uint32_t* cnt_out = c.counts + (uint64_t)sid * KMAX;
     for (uint32_t q = threadIdx.x; q < K; q += NT) cnt_out[q] = (L.nfull[q] << lb) + L.fill[q];
-    if (threadIdx.x == 0) c.stripe_full[blockIdx.x] = full_blocks;
+    if (threadIdx.x == 0) c.stripe_full[sid] = full_blocks;
 }
 
 // --------------------------------------------------------------- scan
 // One workgroup per task: C_i = sum over stripes, bounds B_i (exclusive
 // prefix), delimiters d_i = ceil(B_i / b) (Section 4.2).  Also resets the
-// reader counts, the cleanup flags and the overflow owner of the task.
+// reader counts and the overflow owner of the task.  With few buckets the
+// stripes are summed by NT / K thread groups side by side.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
     __shared__ uint32_t tot[KMAX];
+    __shared__ uint32_t part[NT];
     __shared__ uint32_t sh[NT / 64 + 1];
     const uint32_t t = blockIdx.x;
     const TaskD td = c.tasks[t];
     const uint32_t K = c.ts[t].K;
-    for (uint32_t j = threadIdx.x; j < K; j += NT) {
+    const uint32_t P = K <= NT / 2 ? NT / K : 1u;
+    if (P > 1) {
+        const uint32_t j = threadIdx.x % K, p = threadIdx.x / K;
         uint32_t s = 0;
-        for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
-        tot[j] = s;
+        if (p < P)
+            for (uint32_t q = p; q < td.nstripes; q += P) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x < K) {
+            uint32_t v = 0;
+            for (uint32_t q = 0; q < P; ++q) v += part[q * K + threadIdx.x];
+            tot[threadIdx.x] = v;
+        }
+    } else {
+        for (uint32_t j = threadIdx.x; j < K; j += NT) {
+            uint32_t s = 0;
+            for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
+            tot[j] = s;
+        }
     }
     __syncthreads();
     // 64-bit prefix: per-thread chunk sums fit 32 bits only if m < 2^32;
@@ -808,12 +835,8 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
     }
     for (uint32_t j = threadIdx.x; j < K; j += NT) {
         c.slots[td.slot_begin + j].readers = 0;
-        c.slots[td.slot_begin + j].flag = 0;
     }
-    if (threadIdx.x == 0) {
-        c.ts[t].ovf_bucket = NO_BUCKET;
-        if (t == 0) *c.ticket = 0;
-    }
+    if (threadIdx.x == 0) c.ts[t].ovf_bucket = NO_BUCKET;
 }
 
 // ------------------------------------------------------ empty-block fix
@@ -876,7 +899,7 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
     if (nh != nsg && threadIdx.x == 0) raise_err(c.err, ERR_FIX);
     hpre[ns] = nh;
     spre[ns] = nsg;
-    if (threadIdx.x == 0 && nh) atomicAdd(&c.stats[3], (unsigned long long)nh);
+    if (threadIdx.x == 0 && nh) stat_add(c.stats, 3, nh, blockIdx.x);
     __syncthreads();
     // moves: the x-th hole receives the x-th straggler; one wavefront per move
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1107,121 +1130,234 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
         }
     }
     if (lane == 0) {
-        atomicAdd(&c.stats[0], moves);
-        atomicAdd(&c.stats[1], skips);
+        stat_add(c.stats, 0, moves, blockIdx.x);
+        stat_add(c.stats, 1, skips, blockIdx.x);
     }
 }
 
 // ---------------------------------------------------------------- cleanup
-// One workgroup per bucket slot, in ticket order (Section 4.3).  Bucket i
-// owns [B_i, B_{i+1}).  After the permutation its full blocks fill
-// [d_i b, w_i b), except that a block written to the partial last block went
-// to the overflow block.  Elements still to place: the overhang
-// [B_{i+1}, w_i b) (bucket-i data inside bucket i+1's head), the partial
-// buffers of every stripe of the task, and the overflow block if bucket i
-// wrote it.  Free positions: the head [B_i, min(d_i b, B_{i+1})) and the tail
-// after the full blocks.  Bucket i first copies its overhang to LDS and
-// raises its flag; it writes only after every earlier bucket whose overhang
-// can reach its head has raised its flag (the overhang of a large bucket
-// can run across several empty or tiny buckets).
-template <int DT, int NT>
-__global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c) {
-    using Elem = typename Traits<DT>::Elem;
-    __shared__ uint32_t gsh;
-    __shared__ uint32_t pre[STRIPES_PER_TASK_MAX + 3];
-    __shared__ uint32_t sh[NT / 64 + 1];
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Elem* oh = reinterpret_cast<Elem*>(smem_raw);   // overhang, < b elements
-    if (threadIdx.x == 0) gsh = atomicAdd(c.ticket, 1u);
-    __syncthreads();
-    const uint32_t g = gsh;
-    if (g >= c.total_slots) return;
-    const uint32_t t = upper_find(c.ntasks, g, [&](uint32_t i) { return (uint64_t)c.tasks[i].slot_begin; });
-    const TaskD td = c.tasks[t];
-    const TaskS st = c.ts[t];
-    const uint32_t j = g - td.slot_begin;
-    if (j >= st.K) return;
+// Section 4.3.  Bucket j owns [B_j, B_{j+1}).  After the permutation its
+// full blocks fill [d_j b, w_j b), except that a block written to the
+// partial last block went to the overflow block.  Elements still to place:
+// the overhang [B_{j+1}, w_j b) (bucket-j data inside the head of bucket
+// j+1, and of further buckets when those are smaller than a block), the
+// partial buffers of every stripe of the task, and the overflow block if
+// bucket j wrote it.  Free positions: the head [B_j, min(d_j b, B_{j+1}))
+// and the tail after the full blocks.
+//
+// The paper's threads clean their buckets one after another.  Here every
+// bucket is cleaned at once in two launches: k_overhang copies each
+// overhang to a side slot (the task's first stripe's head-copy area, free
+// once classification is over), so that k_cleanup can then fill every
+// bucket's free positions with no ordering between buckets.
+struct BucketGeom {
+    uint64_t B0, B1;    // bucket bounds (segment-relative)
+    uint64_t cs, ce;    // start and end of the correct full blocks
+    uint64_t ohn;       // overhang elements at [B1, B1 + ohn)
+    bool ovf_case;      // this bucket wrote the overflow block
+};
+
+template <int DT>
+__device__ inline BucketGeom bucket_geom(const Ctx<DT>& c, uint32_t t, const TaskD& td, const TaskS& st,
+                                         uint32_t j, bool* bad) {
     const uint32_t b = c.b;
     const uint64_t* bd = c.bounds + td.slot_begin + t;
     const uint32_t* dl = c.delim + td.slot_begin + t;
-    const uint64_t B0 = bd[j], B1 = bd[j + 1];
-    const uint64_t cs = (uint64_t)dl[j] * b;
+    BucketGeom g;
+    g.B0 = bd[j];
+    g.B1 = bd[j + 1];
+    g.cs = (uint64_t)dl[j] * b;
     const uint64_t w = c.slots[td.slot_begin + j].wr >> 32;
-    const bool ovf_case = st.ovf_bucket == j;
-    // end of the correct full blocks (no blocks: the region is empty at cs;
-    // with blocks the bucket holds at least b elements, so cs < B1)
+    g.ovf_case = st.ovf_bucket == j;
+    // with blocks the bucket holds at least b elements, so cs < B1; without
+    // them the block region is empty at cs
     const bool has_blocks = w > dl[j];
-    const uint64_t ce = !has_blocks ? cs : (ovf_case ? (uint64_t)(st.nblocks - 1) * b : w * b);
-    Elem* seg = c.data + td.off;
-    // overhang: bucket-j elements of the last full block beyond B1
-    uint64_t ohn = (has_blocks && !ovf_case && ce > B1) ? ce - B1 : 0;
-    if (B1 + ohn > td.m || ohn >= b) {   // cannot happen for consistent state
-        if (threadIdx.x == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
-        ohn = 0;
+    g.ce = !has_blocks ? g.cs : (g.ovf_case ? (uint64_t)(st.nblocks - 1) * b : w * b);
+    g.ohn = (has_blocks && !g.ovf_case && g.ce > g.B1) ? g.ce - g.B1 : 0;
+    *bad = g.B1 + g.ohn > td.m || g.ohn >= b;      // cannot happen for consistent state
+    if (*bad) g.ohn = 0;
+    return g;
+}
+
+// Overhang to the side slot of the task's first stripe: one wave per
+// bucket; grid (bucket groups, tasks from task0).
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_overhang(Ctx<DT> c, uint32_t task0) {
+    using Elem = typename Traits<DT>::Elem;
+    const uint32_t t = task0 + blockIdx.y;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = blockIdx.x * (NT / 64) + threadIdx.x / 64, lane = threadIdx.x & 63;
+    if (j >= st.K) return;
+    bool bad;
+    const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
+    if (bad) {
+        if (lane == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        return;
     }
-    for (uint32_t i = threadIdx.x; i < ohn; i += NT) oh[i] = seg[B1 + i];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // the overhang is in LDS (the barrier above waited for its loads)
-        atom_store32(&c.slots[td.slot_begin + j].flag, 1u);
-        // An overhang of bucket i lies in [B_{i+1}, d_{i+1} b): it can cover
-        // this bucket only if d_{i+1} == d_j, which holds for a run of
-        // predecessors (all but the first of them smaller than a block, and
-        // possibly empty).  Wait for each of them; their tickets are smaller.
-        for (uint32_t jj = j; jj >= 1 && dl[jj] == dl[j]; --jj) {
-            uint32_t spins = 0;
-            while (atom_load32(&c.slots[td.slot_begin + jj - 1].flag) == 0) {
-                if (++spins > c.spin_limit) { raise_err(c.err, ERR_SPIN); break; }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        compiler_fence();
-    }
-    __syncthreads();
-    // sources: [overhang | buffer of stripe 0 | ... | buffer of stripe ns-1 | overflow]
-    const uint32_t ns = td.nstripes;
-    for (uint32_t q = threadIdx.x; q < ns + 2; q += NT) {
-        uint32_t v;
-        if (q == 0) v = (uint32_t)ohn;
-        else if (q <= ns) v = c.counts[(uint64_t)(td.stripe_begin + q - 1) * KMAX + j] % b;
-        else v = ovf_case ? b : 0;
-        pre[q] = v;
-    }
-    __syncthreads();
-    const uint32_t nsrc = lds_excl_scan<NT>(pre, ns + 2, sh);
-    // free positions: head [B0, he) and tail [tb, B1)
-    const uint64_t he = cs < B1 ? cs : B1;
-    const uint64_t tb0 = ce > cs ? ce : cs;
-    const uint64_t tb = tb0 < B1 ? tb0 : B1;
-    const uint64_t nhead = he - B0, nfree = nhead + (B1 - tb);
-    if (nfree != nsrc) {
+    const Elem* src = c.data + td.off + g.B1;
+    Elem* side = c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * c.b;
+    for (uint32_t i = lane; i < g.ohn; i += 64) side[i] = src[i];
+}
+
+// Where source element x of a bucket goes: the head first, then the tail.
+struct FreeMap {
+    uint64_t B0, tb, nhead;
+    __device__ uint64_t operator()(uint64_t x) const { return x < nhead ? B0 + x : tb + (x - nhead); }
+};
+
+// Fill the free positions of buckets whose task has many stripes: grid
+// (bucket * parts + part, tasks from task0), one workgroup per part; the
+// bucket's sources [overhang | buffer of stripe 0 | ... | buffer of stripe
+// ns-1 | overflow] are split into `parts` ranges of whole sources.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint32_t task0) {
+    using Elem = typename Traits<DT>::Elem;
+    __shared__ uint32_t pre[STRIPES_PER_TASK_MAX + 3];
+    __shared__ uint32_t sh[NT / 64 + 1];
+    const uint32_t t = task0 + blockIdx.y;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = blockIdx.x / parts, part = blockIdx.x % parts;
+    if (j >= st.K) return;
+    const uint32_t b = c.b;
+    bool bad;
+    const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
+    if (bad) {
         if (threadIdx.x == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
         return;
     }
+    const uint32_t ns = td.nstripes, nq = ns + 2;
+    for (uint32_t q = threadIdx.x; q < nq; q += NT) {
+        uint32_t v;
+        if (q == 0) v = (uint32_t)g.ohn;
+        else if (q <= ns) v = c.counts[(uint64_t)(td.stripe_begin + q - 1) * KMAX + j] % b;
+        else v = g.ovf_case ? b : 0;
+        pre[q] = v;
+    }
+    __syncthreads();
+    const uint32_t nsrc = lds_excl_scan<NT>(pre, nq, sh);
+    pre[nq] = nsrc;     // every thread writes the same value
+    __syncthreads();
+    // free positions: head [B0, he) and tail [tb, B1)
+    const uint64_t he = g.cs < g.B1 ? g.cs : g.B1;
+    const uint64_t tb0 = g.ce > g.cs ? g.ce : g.cs;
+    const uint64_t tb = tb0 < g.B1 ? tb0 : g.B1;
+    const uint64_t nhead = he - g.B0, nfree = nhead + (g.B1 - tb);
+    if (nfree != nsrc) {
+        if (threadIdx.x == 0 && part == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        return;
+    }
+    if (threadIdx.x == 0 && part == 0) stat_add(c.stats, 2, nsrc, blockIdx.x + blockIdx.y);
+    const FreeMap fm{g.B0, tb, nhead};
+    Elem* seg = c.data + td.off;
+    const uint32_t q0 = (uint32_t)((uint64_t)nq * part / parts), q1 = (uint32_t)((uint64_t)nq * (part + 1) / parts);
+    for (uint32_t q = q0; q < q1; ++q) {
+        const uint32_t x0 = pre[q], n = pre[q + 1] - x0;
+        if (n == 0) continue;
+        const Elem* src = q == 0 ? c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * b
+                        : q <= ns ? c.bufs + c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b
+                                  : c.ovf + (uint64_t)t * b;
+        for (uint32_t o = threadIdx.x; o < n; o += NT) seg[fm(x0 + o)] = src[o];
+    }
+}
+
+// The same for tasks with at most 62 stripes: one wave per bucket, four
+// buckets per workgroup; grid (bucket groups, tasks from task0).
+template <int DT>
+__global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task0) {
+    using Elem = typename Traits<DT>::Elem;
+    const uint32_t t = task0 + blockIdx.y;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x & 63;
+    if (j >= st.K) return;
+    const uint32_t b = c.b;
+    bool bad;
+    const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
+    if (bad) {
+        if (lane == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        return;
+    }
+    const uint32_t ns = td.nstripes, nq = ns + 2;
+    // lane q holds source q's size and start
+    uint32_t v = 0;
+    uint64_t src_off = 0;                       // element offset in bufs (q <= ns)
+    if (lane == 0) {
+        v = (uint32_t)g.ohn;
+        src_off = c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * b;
+    } else if (lane <= ns) {
+        v = c.counts[(uint64_t)(td.stripe_begin + lane - 1) * KMAX + j] % b;
+        src_off = c.stripes[td.stripe_begin + lane - 1].buf_off + (uint64_t)j * b;
+    } else if (lane == ns + 1) {
+        v = g.ovf_case ? b : 0;
+    }
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(inc, d, 64);
+        if (lane >= (uint32_t)d) inc += u;
+    }
+    const uint32_t nsrc = read_lane(inc, 63);
+    const uint32_t x_lane = inc - v;
+    const uint64_t he = g.cs < g.B1 ? g.cs : g.B1;
+    const uint64_t tb0 = g.ce > g.cs ? g.ce : g.cs;
+    const uint64_t tb = tb0 < g.B1 ? tb0 : g.B1;
+    const uint64_t nhead = he - g.B0, nfree = nhead + (g.B1 - tb);
+    if (nfree != nsrc) {
+        if (lane == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+        return;
+    }
+    if (lane == 0) stat_add(c.stats, 2, nsrc, threadIdx.x / 64 + blockIdx.x + blockIdx.y);
+    const FreeMap fm{g.B0, tb, nhead};
+    Elem* seg = c.data + td.off;
     const Elem* ovfp = c.ovf + (uint64_t)t * b;
-    if (threadIdx.x == 0) atomicAdd(&c.stats[2], (unsigned long long)nsrc);
-    for (uint32_t x = threadIdx.x; x < nsrc; x += NT) {
-        uint32_t q = upper_find(ns + 2, x, [&](uint32_t i) { return (uint64_t)pre[i]; });
-        while (q + 1 < ns + 2 && pre[q + 1] <= x) ++q;
-        uint32_t o = x - pre[q];
-        Elem e;
-        if (q == 0) e = oh[o];
-        else if (q <= ns) e = c.bufs[c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b + o];
-        else e = ovfp[o];
-        uint64_t dst = x < nhead ? B0 + x : tb + (x - nhead);
-        seg[dst] = e;
+    // U elements per lane per round: all loads of a round are issued before
+    // its stores, so a round costs one memory latency, not U
+    constexpr int U = 8;
+    for (uint32_t base = 0; base < nsrc; base += 64 * U) {
+        uint32_t qs[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) qs[u] = 0;
+        for (uint32_t q = 1; q < nq; ++q) {
+            const uint32_t xq = read_lane(x_lane, q);
+#pragma unroll
+            for (int u = 0; u < U; ++u) qs[u] = (base + lane + 64u * u >= xq) ? q : qs[u];
+        }
+        Elem r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = base + lane + 64u * u;
+            const uint32_t q = qs[u];
+            const uint32_t o = x - (uint32_t)__shfl(x_lane, q, 64);
+            const uint64_t so = ((uint64_t)(uint32_t)__shfl((uint32_t)(src_off >> 32), q, 64) << 32) |
+                                (uint32_t)__shfl((uint32_t)src_off, q, 64);
+            if (x < nsrc) r[u] = q == ns + 1 ? ovfp[o] : c.bufs[so + o];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = base + lane + 64u * u;
+            if (x < nsrc) seg[fm(x)] = r[u];
+        }
     }
 }
 
 // -------------------------------------------------------------- base case
 // Sorts each listed segment (at most NT*VT elements) inside one workgroup's
-// LDS: every thread sorts VT consecutive items in registers with a bitonic
-// network, then log2(len / VT) merge passes double the sorted runs; in a pass
-// each thread finds where its VT outputs start in the merge of its two runs
-// by a binary search along the cross diagonal (merge path) and merges VT
-// items with a merging network.  u64/f64 sort the keys themselves (f64 through the
-// bijective totalOrder image); records sort (key, index) items and then
-// gather whole records from a per-workgroup scratch copy of the segment.
+// LDS.  The segment is padded with maximal sentinels to a multiple of VT, so
+// every thread owns exactly VT items and no access needs a bounds check.
+// Every thread sorts its VT items in registers with a bitonic network; then
+// log2(len / VT) merge passes double the sorted runs.  In a pass each thread
+// finds where its VT outputs start in the merge of its two runs by a binary
+// search along its cross diagonal (merge path); the next thread's start,
+// exchanged through LDS, says how many of the VT outputs come from each run,
+// na from the first and VT - na from the second.  The thread loads those na
+// items ascending followed by the VT - na items descending (a bitonic
+// sequence holding exactly its outputs, one load per output) and sorts them
+// with a bitonic merge.  u64/f64 sort the keys themselves (f64 through the
+// bijective totalOrder image); records sort (key, index) items, ties broken
+// by index so that the sentinels (index 2^32 - 1) stay last, and then gather
+// whole records from a per-workgroup scratch copy of the segment.
 struct SegD {
     uint64_t off;
     uint32_t len;
@@ -1238,7 +1374,7 @@ template <int DT>
 struct BaseItem {                       // records: key and position
     using Key = typename Traits<DT>::Key;
     using T = KeyIdx<Key>;
-    __device__ static bool less(const T& a, const T& b) { return a.k < b.k; }
+    __device__ static bool less(const T& a, const T& b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
     __device__ static T maxv() { return T{Traits<DT>::max_key(), 0xffffffffu}; }
 };
 template <>
@@ -1298,75 +1434,81 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
     using It = typename BI::T;
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    It* lds = reinterpret_cast<It*>(smem_raw);
+    uint32_t* xchg = reinterpret_cast<uint32_t*>(smem_raw);                  // NT merge-path starts
+    It* lds = reinterpret_cast<It*>(smem_raw + ((NT * sizeof(uint32_t) + 15) & ~size_t(15)));
     auto pidx = [](uint32_t i) { return i + i / VT; };   // one pad item per VT: fewer bank conflicts
     const uint32_t tid = threadIdx.x;
+    const uint32_t base = tid * VT;
+    It* const mine = lds + pidx(base);                    // this thread's VT items, contiguous
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
         const SegD sg = segs[si];
         const uint32_t len = sg.len;
+        const uint32_t lenP = (len + VT - 1) / VT * VT;
         Elem* seg = c.data + sg.off;
         Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
-        for (uint32_t i = tid; i < len; i += NT) {
-            Elem e = seg[i];
-            if constexpr (kPlain) {
-                lds[pidx(i)] = TR::key(e).v;
-            } else {
-                scr[i] = e;
-                lds[pidx(i)] = It{TR::key(e), i};
+        for (uint32_t i = tid; i < lenP; i += NT) {
+            It v = BI::maxv();
+            if (i < len) {
+                const Elem e = seg[i];
+                if constexpr (kPlain) {
+                    v = TR::key(e).v;
+                } else {
+                    scr[i] = e;
+                    v = It{TR::key(e), i};
+                }
             }
+            lds[pidx(i)] = v;
         }
         __syncthreads();
-        const uint32_t nthr = (len + VT - 1) / VT;
-        const uint32_t base = tid * VT;
+        const uint32_t nthr = lenP / VT;
         It x[VT];
         if (tid < nthr) {
 #pragma unroll
-            for (int v = 0; v < VT; ++v) x[v] = (base + v < len) ? lds[pidx(base + v)] : BI::maxv();
+            for (int v = 0; v < VT; ++v) x[v] = mine[v];
             sort_network<BI, VT>(x);
         }
-        for (uint32_t L = VT; L < len; L *= 2) {
+        for (uint32_t L = VT; L < lenP; L *= 2) {
             __syncthreads();
             if (tid < nthr) {
 #pragma unroll
-                for (int v = 0; v < VT; ++v)
-                    if (base + v < len) lds[pidx(base + v)] = x[v];
+                for (int v = 0; v < VT; ++v) mine[v] = x[v];
             }
             __syncthreads();
+            uint32_t lo = 0, a0 = 0, aCount = 0, b0 = 0, diag = 0;
             if (tid < nthr) {
-                const uint32_t a0 = (base / (2 * L)) * (2 * L);
-                const uint32_t aCount = (len - a0) < L ? (len - a0) : L;
-                const uint32_t b0 = a0 + L;
-                const uint32_t bCount = b0 >= len ? 0u : ((len - b0) < L ? (len - b0) : L);
-                const uint32_t diag = base - a0;
-                uint32_t lo = diag > bCount ? diag - bCount : 0u;
+                a0 = base & ~(2 * L - 1);
+                aCount = min(L, lenP - a0);
+                b0 = a0 + L;
+                const uint32_t bCount = b0 >= lenP ? 0u : min(L, lenP - b0);
+                diag = base - a0;
+                lo = diag > bCount ? diag - bCount : 0u;
                 uint32_t hi = diag < aCount ? diag : aCount;
                 while (lo < hi) {
                     const uint32_t mid = (lo + hi) >> 1;
-                    const It a = lds[pidx(a0 + mid)];
-                    const It b = lds[pidx(b0 + diag - 1 - mid)];
-                    if (!BI::less(b, a)) lo = mid + 1; else hi = mid;
+                    const It av = lds[pidx(a0 + mid)];
+                    const It bv = lds[pidx(b0 + diag - 1 - mid)];
+                    if (!BI::less(bv, av)) lo = mid + 1; else hi = mid;
                 }
-                // the thread's VT outputs are the VT smallest of the next VT
-                // items of each run: load both (independent loads), keep the
-                // pairwise minima of a[v] and b[VT-1-v] (a bitonic sequence
-                // holding exactly those VT items) and sort it by bitonic merge
-                const uint32_t ai = lo, bi = diag - lo;
-                It av[VT], bv[VT];
+                xchg[tid] = lo;
+            }
+            lds_barrier();
+            if (tid < nthr) {
+                // the next thread continues this merge unless this thread
+                // ends it (end of both runs or of the padded segment)
+                const uint32_t end = min(a0 + 2 * L, lenP);
+                const uint32_t lo_next = base + VT < end ? xchg[tid + 1] : aCount;
+                const uint32_t na = lo_next - lo;
+                const uint32_t ai = a0 + lo, bi_last = b0 + (diag - lo) + VT - 1;
 #pragma unroll
-                for (int v = 0; v < VT; ++v) {
-                    av[v] = (ai + v < aCount) ? lds[pidx(a0 + ai + v)] : BI::maxv();
-                    bv[v] = (bi + v < bCount) ? lds[pidx(b0 + bi + v)] : BI::maxv();
-                }
-#pragma unroll
-                for (int v = 0; v < VT; ++v) x[v] = BI::less(bv[VT - 1 - v], av[v]) ? bv[VT - 1 - v] : av[v];
+                for (int v = 0; v < VT; ++v)
+                    x[v] = lds[pidx((uint32_t)v < na ? ai + v : bi_last - v)];
                 bitonic_merge<BI, VT>(x);
             }
         }
         __syncthreads();
         if (tid < nthr) {
 #pragma unroll
-            for (int v = 0; v < VT; ++v)
-                if (base + v < len) lds[pidx(base + v)] = x[v];
+            for (int v = 0; v < VT; ++v) mine[v] = x[v];
         }
         __syncthreads();
         for (uint32_t i = tid; i < len; i += NT) {

@@ -274,7 +274,8 @@ def test_select_splitters_parity(env, dtype, dist):
         seed = 0xABCDEF + k
         want, weq = oracle.select_splitters(inp, dtype, k, alpha, seed)
         d = to_dev(torch, inp)
-        got, geq = ips.ips4o_select_splitters(h, d, n, dtype, {"k": k, "seed": seed}, like=inp)
+        got, geq = ips.ips4o_select_splitters(h, d, n, dtype, {"k": k, "seed": seed, "alpha_x100": 100 * alpha},
+                                              like=inp)
         assert geq == weq
         assert np.array_equal(keys_of(got, dtype), keys_of(want, dtype)), (k, dist)
 

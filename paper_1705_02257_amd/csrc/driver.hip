@@ -260,7 +260,7 @@ int build_host_tree(const void* h_split, uint32_t m, int eq, uint64_t nseg, uint
     using TR = Traits<DT>;
     using Key = typename TR::Key;
     using Elem = typename TR::Elem;
-    if (m < 1 || m > (uint32_t)KT_MAX - 1 || !h_split) return IPS4O_ERR_INVALID_ARG;
+    if (m < 1 || m > (uint32_t)KGIVEN_MAX || !h_split) return IPS4O_ERR_INVALID_ARG;
     std::vector<Key> keys(m);
     const char* src = (const char*)h_split;
     for (uint32_t i = 0; i < m; ++i) {
@@ -633,38 +633,67 @@ void add_to_bins(std::vector<SegD>& bins, size_t first, uint64_t off, uint64_t l
     bins.push_back(SegD{off, (uint32_t)len, 0});
 }
 
+// Base-case bins larger than half the capacity are sorted by one
+// workgroup of BNT threads per CU; the others by workgroups of BNT/2
+// threads holding half the LDS, two per CU, so that one workgroup's
+// barriers and LDS latencies overlap the other's work.
 template <int DT>
-int run_basecase(ips4o_handle* h, void* d_data, const std::vector<SegD>& list, const Resolved& R,
+constexpr uint32_t small_bin_cap() {
+    return (uint32_t)(Shape<DT>::BNT / 2) * Shape<DT>::BVT;
+}
+
+template <int DT, int NT>
+int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t cap,
+                    uint32_t grid, typename Traits<DT>::Elem* scr, hipStream_t st) {
+    constexpr int BVT = Shape<DT>::BVT;
+    using It = typename BaseItem<DT>::T;
+    const size_t lds = ((NT * sizeof(uint32_t) + 15) & ~size_t(15)) +
+                       (size_t)(cap + (cap + BVT - 1) / BVT + BVT) * sizeof(It);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, NT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL((k_basecase<DT, NT, BVT>), dim3(grid), dim3(NT), lds, st, c, segs, (uint32_t)nseg, scr);
+    HIP_TRY(hipGetLastError());
+    return IPS4O_OK;
+}
+
+template <int DT>
+int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const Resolved& R,
                  hipStream_t st, Timer& tm) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
-    using Key = typename TR::Key;
     if (list.empty()) return IPS4O_OK;
     constexpr int BNT = Shape<DT>::BNT, BVT = Shape<DT>::BVT;
     static_assert(BNT * BVT == TR::kBaseCap, "base-case capacity");
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
+    const uint32_t half = small_bin_cap<DT>();
+    // small bins first, then the large ones
+    auto mid = std::stable_partition(list.begin(), list.end(), [&](const SegD& sg) { return sg.len <= half; });
+    const size_t nsmall = (size_t)(mid - list.begin()), nlarge = list.size() - nsmall;
     int rc = h->segs.ensure(list.size() * sizeof(SegD));
     if (rc) return rc;
-    const uint32_t grid = (uint32_t)std::min<size_t>(list.size(), kBaseGrid);
+    const uint32_t g_small = (uint32_t)std::min<size_t>(nsmall, 2 * kBaseGrid);
+    const uint32_t g_large = (uint32_t)std::min<size_t>(nlarge, kBaseGrid);
     Elem* scr = nullptr;
     if (!plain) {
-        rc = h->scratch.ensure((size_t)grid * TR::kBaseCap * sizeof(Elem));
+        rc = h->scratch.ensure(std::max((size_t)g_small * half, (size_t)g_large * TR::kBaseCap) * sizeof(Elem));
         if (rc) return rc;
         scr = (Elem*)h->scratch.p;
     }
     HIP_TRY(hipMemcpyAsync(h->segs.p, list.data(), list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
     Ctx<DT> c{};
     c.data = (Elem*)d_data;
-    using It = typename BaseItem<DT>::T;
-    const size_t lds = ((BNT * sizeof(uint32_t) + 15) & ~size_t(15)) +
-                       (size_t)(R.cap + (R.cap + BVT - 1) / BVT + BVT) * sizeof(It);
-    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, BNT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
+    const SegD* d_segs = (const SegD*)h->segs.p;
     int r = tm.begin(KK_BASE);
-    hipLaunchKernelGGL((k_basecase<DT, BNT, BVT>), dim3(grid), dim3(BNT), lds, st, c, (const SegD*)h->segs.p,
-                       (uint32_t)list.size(), scr);
-    HIP_TRY(hipGetLastError());
+    if (nsmall) {
+        rc = launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, std::min(R.cap, half), g_small, scr, st);
+        if (rc) return rc;
+    }
+    if (nlarge) {
+        rc = launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, R.cap, g_large, scr, st);
+        if (rc) return rc;
+    }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
     HIP_TRY(hipStreamSynchronize(st));   // the host list must outlive the copy
     return IPS4O_OK;
@@ -730,7 +759,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
                 if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
                 uint64_t off = td.off + bd[i];
                 if (sz <= R.cap) {
-                    add_to_bins(base, first_bin, off, sz, R.cap);
+                    add_to_bins(base, first_bin, off, sz, std::min(R.cap, small_bin_cap<DT>()));
                     h->last.elements_base += sz;
                 }
                 else next.push_back(Seg{off, sz});
@@ -1035,7 +1064,7 @@ int ips4o_check_args(const void* d_data, uint64_t n, int dtype, const ips4o_para
 
 int ips4o_check_splitters(const void* h_splitters, uint32_t num_splitters, int dtype, int equality_buckets) {
     if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
-    if (!h_splitters || num_splitters < 1 || num_splitters > (uint32_t)KT_MAX - 1) return IPS4O_ERR_INVALID_ARG;
+    if (!h_splitters || num_splitters < 1 || num_splitters > (uint32_t)KGIVEN_MAX) return IPS4O_ERR_INVALID_ARG;
     if (equality_buckets != 0 && equality_buckets != 1) return IPS4O_ERR_INVALID_ARG;
     DISPATCH(dtype, check_splitter_order<D>(h_splitters, num_splitters));
 }

@@ -29,12 +29,13 @@
 
 namespace ips4o {
 
-constexpr int KT_MAX = 512;     // search tree leaves (power of two)
-constexpr int KMAX = 1024;      // logical buckets: up to 2*KT_MAX - 1
-// sample capacity in LDS: a power of two, at most 64 KiB of keys
+constexpr int KT_MAX = 1024;    // search tree leaves (power of two)
+constexpr int KMAX = 1024;      // logical buckets (with equality buckets 2 nuniq + 1)
+constexpr int KGIVEN_MAX = 511; // caller-given splitters: 2*511 + 1 buckets fit KMAX
+// sample capacity in LDS: a power of two, at most 128 KiB of keys
 template <class Key>
 constexpr int sample_max() {
-    return sizeof(Key) <= 8 ? 8192 : (sizeof(Key) <= 16 ? 4096 : 2048);
+    return sizeof(Key) <= 8 ? 16384 : (sizeof(Key) <= 16 ? 8192 : 4096);
 }
 constexpr int STRIPES_PER_TASK_MAX = 1024;
 constexpr uint32_t NO_BUCKET = 0xffffffffu;
@@ -312,26 +313,37 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
             __syncthreads();
         }
     }
-    // picks and duplicate removal
-    for (uint32_t i = threadIdx.x; i < KT_MAX; i += NT) {
-        uint32_t f = 0;
-        if (i >= 1 && i < k) {
-            f = (i == 1) ? 1u : (smp[(i - 1) * alpha - 1] == smp[i * alpha - 1] ? 0u : 1u);
+    // picks s_i = sample[i*step - 1], i = 1..kp-1, and duplicate removal;
+    // returns the number of unique picks (isnew[i]: index among them)
+    auto pick_unique = [&](uint32_t kp, uint32_t step) {
+        for (uint32_t i = threadIdx.x; i < KT_MAX; i += NT) {
+            uint32_t f = 0;
+            if (i >= 1 && i < kp) f = (i == 1) ? 1u : (smp[(i - 1) * step - 1] == smp[i * step - 1] ? 0u : 1u);
+            isnew[i] = f;
         }
-        isnew[i] = f;
+        __syncthreads();
+        return lds_excl_scan<NT>(isnew, KT_MAX, scan_sh);
+    };
+    uint32_t kp = k, step = alpha;
+    uint32_t nuniq = pick_unique(kp, step);
+    // equality buckets double the bucket count: when 2 nuniq + 1 would
+    // exceed KMAX, every second pick is used instead (k/2 buckets, twice
+    // the oversampling)
+    if (nuniq < kp - 1 && 2 * nuniq + 1 > (uint32_t)KMAX) {
+        kp = k / 2;
+        step = 2 * alpha;
+        __syncthreads();
+        nuniq = pick_unique(kp, step);
     }
-    __syncthreads();
-    // position of each new pick among the unique ones
-    uint32_t nuniq = lds_excl_scan<NT>(isnew, KT_MAX, scan_sh);
     Key* spl = c.spl + td.tree_begin;
     Key* tree = c.tree + td.tree_begin;
-    for (uint32_t i = 1 + threadIdx.x; i < k; i += NT) {
-        Key pick = smp[i * alpha - 1];
-        bool nw = (i == 1) || !(smp[(i - 1) * alpha - 1] == pick);
+    for (uint32_t i = 1 + threadIdx.x; i < kp; i += NT) {
+        Key pick = smp[i * step - 1];
+        bool nw = (i == 1) || !(smp[(i - 1) * step - 1] == pick);
         if (nw) spl[isnew[i]] = pick;
     }
-    const uint32_t eq = nuniq < k - 1 ? 1u : 0u;
-    uint32_t kt = k;
+    const uint32_t eq = nuniq < kp - 1 ? 1u : 0u;
+    uint32_t kt = kp;
     if (eq) {
         kt = 2;
         while (kt < nuniq + 1) kt <<= 1;
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
     Key last = smp[0];
     {
         // the largest pick is the last one
-        last = smp[(k - 1) * alpha - 1];
+        last = smp[(kp - 1) * step - 1];
     }
     for (uint32_t j = nuniq + threadIdx.x; j < kt; j += NT) spl[j] = last;
     __syncthreads();
@@ -365,6 +377,103 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
         s.ovf_bucket = NO_BUCKET;
         s.pad0 = s.pad1 = 0;
         c.ts[blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------- lookup-table classification
+// The same bucket as the tree descent, #{i < nuniq : s_i <= e} (and the
+// equality rule on top), found with fewer LDS reads.  A table of LUT_N
+// cells splits the range of the splitters' leading 64-bit words into equal
+// parts: cell c holds the first splitter index lo_c whose leading word
+// lies at or beyond the cell's start and the number n_c of splitters whose
+// leading word lies inside the cell.  A key's cell follows from its leading
+// word; the splitters before lo_c are all below the key and those from
+// lo_c + n_c on all above it, so a binary search over the n_c candidates
+// finishes the count.  Its step count is the same for every key of the
+// workgroup (log2 of the largest n_c + 1): about two for spread-out
+// splitters, log2 k when they crowd into one cell.
+constexpr int LUT_BITS = 12;
+constexpr uint32_t LUT_N = 1u << LUT_BITS;
+
+__device__ inline uint64_t lead_word(const Key1& k) { return k.v; }
+__device__ inline uint64_t lead_word(const Key3& k) { return k.a; }
+__device__ inline uint64_t lead_word(const Key10& k) { return k.hi; }
+
+struct LutParams {
+    uint64_t w_lo;      // leading word of the smallest splitter
+    uint32_t sh;        // cell = (w - w_lo) >> sh, clamped to [0, LUT_N)
+    uint32_t steps;     // binary-search steps
+};
+
+// Builds lut[] from the sorted splitters spl[0..nuniq) in LDS; every thread
+// of the workgroup calls it.  `red` is NT/64 + 1 words of LDS scratch.
+template <class Key, int NT>
+__device__ inline LutParams build_lut(const Key* spl, uint32_t nuniq, uint32_t* lut, uint32_t* red) {
+    LutParams P;
+    P.w_lo = nuniq ? lead_word(spl[0]) : 0;
+    const uint64_t span = nuniq ? lead_word(spl[nuniq - 1]) - P.w_lo : 0;
+    const uint32_t bits = span ? 64u - (uint32_t)__clzll(span) : 0u;
+    P.sh = bits > (uint32_t)LUT_BITS ? bits - LUT_BITS : 0u;
+    // first splitter index whose leading word is at or beyond w_lo + off
+    auto first_at = [&](uint64_t off) {
+        uint32_t lo = 0, hi = nuniq;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (lead_word(spl[mid]) - P.w_lo < off) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    uint32_t nmax = 0;
+    for (uint32_t cidx = threadIdx.x; cidx < LUT_N; cidx += NT) {
+        const uint32_t lo = cidx == 0 ? 0u : first_at((uint64_t)cidx << P.sh);
+        const uint32_t hi = cidx + 1 == LUT_N ? nuniq : first_at((uint64_t)(cidx + 1) << P.sh);
+        lut[cidx] = lo | ((hi - lo) << 16);
+        nmax = max(nmax, hi - lo);
+    }
+    // workgroup maximum of n_c
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor(nmax, d, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nmax;
+    __syncthreads();
+    uint32_t m = 0;
+    for (int w = 0; w < NT / 64; ++w) m = max(m, red[w]);
+    P.steps = m ? 32u - (uint32_t)__clz(m) : 0u;     // ceil(log2(m + 1))
+    __syncthreads();
+    return P;
+}
+
+template <class Key, int EPT>
+__device__ inline void classify_lut_batch(const Key (&k)[EPT], uint32_t (&out)[EPT], const Key* spl,
+                                          const uint32_t* lut, const LutParams& P, uint32_t nuniq, uint32_t eq) {
+    uint32_t base[EPT], len[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const uint64_t w = lead_word(k[e]);
+        const uint64_t off = w > P.w_lo ? w - P.w_lo : 0;
+        const uint64_t cl = off >> P.sh;
+        const uint32_t cell = cl < LUT_N ? (uint32_t)cl : LUT_N - 1;
+        const uint32_t v = lut[cell];
+        base[e] = v & 0xffffu;
+        len[e] = v >> 16;
+    }
+    for (uint32_t s = 0; s < P.steps; ++s) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const uint32_t half = len[e] >> 1;
+            const bool go = len[e] > 0 && spl[base[e] + half] <= k[e];
+            base[e] = go ? base[e] + half + 1 : base[e];
+            len[e] = go ? len[e] - half - 1 : half;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const uint32_t leaf = base[e];
+        uint32_t r = leaf;
+        if (eq) {
+            const uint32_t is_eq = (leaf >= 1 && spl[leaf > 0 ? leaf - 1 : 0] == k[e]) ? 1u : 0u;
+            r = 2 * leaf - is_eq;
+        }
+        out[e] = r;
     }
 }
 
@@ -394,7 +503,9 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
 template <int DT, int NT, int EPT>
 struct ClassifyLds {
     using Elem = typename Traits<DT>::Elem;
-    TreeLds<DT> tr;
+    typename Traits<DT>::Key spl[KT_MAX];   // sorted unique splitters
+    uint32_t lut[LUT_N];                    // lo_c | n_c << 16
+    LutParams lp;
     Elem tile[NT * EPT];
     uint16_t ids[NT * EPT];
     uint32_t cnt[KMAX];         // elements of the tile per bucket (atomic ranks)
@@ -480,7 +591,7 @@ __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename
     typename TR::Key kk[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) kk[e] = TR::key(x[e]);
-    classify_batch<typename TR::Key, EPT>(kk, bk, L.tr.tree, L.tr.spl, lkt, st.nuniq, st.eq);
+    classify_lut_batch<typename TR::Key, EPT>(kk, bk, L.spl, L.lut, L.lp, st.nuniq, st.eq);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const uint32_t p = e * NT + threadIdx.x;
@@ -532,7 +643,12 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     const TaskS st = c.ts[sd.task];
     const uint32_t b = c.b, lb = ilog2(c.b), K = st.K, lkt = ilog2(st.kt);
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    load_tree<DT>(c, td, st.kt, st.nuniq, L.tr);
+    for (uint32_t i = threadIdx.x; i < st.nuniq; i += NT) L.spl[i] = c.spl[td.tree_begin + i];
+    __syncthreads();
+    {
+        const LutParams P = build_lut<typename TR::Key, NT>(L.spl, st.nuniq, L.lut, L.holes);
+        if (threadIdx.x == 0) L.lp = P;
+    }
 
     const uint64_t s_begin = (uint64_t)sd.blk_begin * b;
     const uint64_t s_end = ((uint64_t)sd.blk_end * b < td.m) ? (uint64_t)sd.blk_end * b : td.m;
@@ -1386,43 +1502,58 @@ struct BaseItem<DT_U64> {
 template <>
 struct BaseItem<DT_F64> : BaseItem<DT_U64> {};
 
+// One stage of compare-exchanges between x[i] and x[i ^ j] (i < i ^ j),
+// ascending where `up(i)`.  For 64-bit integer items one operand of the
+// selects passes through an empty asm statement: the selects then no longer
+// match the min/max idiom, which the compiler would expand into two 64-bit
+// comparisons per exchange; one comparison feeds all four 32-bit selects.
+template <class BI, int VT, int J, class Up>
+__device__ inline void cx_stage(typename BI::T (&x)[VT], Up up) {
+    using T = typename BI::T;
+#pragma unroll
+    for (int i = 0; i < VT; ++i) {
+        const int l = i ^ J;
+        if (l > i) {
+            const T a = x[i], b = x[l];
+            const bool w = up(i) ? BI::less(b, a) : BI::less(a, b);
+            T a2 = a;
+            if constexpr (std::is_same<T, uint64_t>::value) asm volatile("" : "+v"(a2));
+            x[i] = w ? b : a2;
+            x[l] = w ? a2 : b;
+        }
+    }
+}
+
+template <class BI, int VT, int K, int J>
+__device__ inline void sort_network_stages(typename BI::T (&x)[VT]) {
+    if constexpr (K <= VT) {
+        if constexpr (J > 0) {
+            cx_stage<BI, VT, J>(x, [](int i) { return (i & K) == 0; });
+            sort_network_stages<BI, VT, K, J / 2>(x);
+        } else {
+            sort_network_stages<BI, VT, K * 2, K>(x);
+        }
+    }
+}
+
+// bitonic sort of VT items in registers, ascending
 template <class BI, int VT>
 __device__ inline void sort_network(typename BI::T (&x)[VT]) {
-#pragma unroll
-    for (int k = 2; k <= VT; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < VT; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool up = (i & k) == 0;
-                    typename BI::T a = x[i], b = x[l];
-                    const bool sw = up ? BI::less(b, a) : BI::less(a, b);
-                    x[i] = sw ? b : a;
-                    x[l] = sw ? a : b;
-                }
-            }
-        }
+    sort_network_stages<BI, VT, 2, 1>(x);
+}
+
+template <class BI, int VT, int J>
+__device__ inline void bitonic_merge_stages(typename BI::T (&x)[VT]) {
+    if constexpr (J > 0) {
+        cx_stage<BI, VT, J>(x, [](int) { return true; });
+        bitonic_merge_stages<BI, VT, J / 2>(x);
     }
 }
 
 // sorts a bitonic sequence ascending (log2 VT half-cleaner stages)
 template <class BI, int VT>
 __device__ inline void bitonic_merge(typename BI::T (&x)[VT]) {
-#pragma unroll
-    for (int j = VT >> 1; j > 0; j >>= 1) {
-#pragma unroll
-        for (int i = 0; i < VT; ++i) {
-            const int l = i ^ j;
-            if (l > i) {
-                typename BI::T a = x[i], b = x[l];
-                const bool sw = BI::less(b, a);
-                x[i] = sw ? b : a;
-                x[l] = sw ? a : b;
-            }
-        }
-    }
+    bitonic_merge_stages<BI, VT, VT / 2>(x);
 }
 
 template <int DT, int NT, int VT>

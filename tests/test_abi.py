@@ -68,8 +68,8 @@ def test_check_args(ips):
     assert _check(ips, 0x1000, 5, 7) == bad                     # unknown dtype
     assert _check(ips, 0x1000, 1 << 32, ips.U64) == unsup
     assert _check(ips, 0x1000, 100, ips.U64, k=3) == bad        # not a power of two
-    assert _check(ips, 0x1000, 100, ips.U64, k=1024) == bad     # above 512
-    assert _check(ips, 0x1000, 100, ips.U64, k=512) == ok
+    assert _check(ips, 0x1000, 100, ips.U64, k=2048) == bad     # above 1024
+    assert _check(ips, 0x1000, 100, ips.U64, k=1024) == ok
     assert _check(ips, 0x1000, 100, ips.U64, block_bytes=4) == bad
     assert _check(ips, 0x1000, 100, ips.U64, block_bytes=1 << 14) == bad
     assert _check(ips, 0x1000, 100, ips.U64, base_cap=1) == bad

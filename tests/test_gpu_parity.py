@@ -138,12 +138,30 @@ def test_sort_robust_to_parameters(env):
     n = 700001
     inp = workloads.generate("twodup", "u64", n, 31)
     ref = oracle.sort(inp, "u64")
-    for params in [{"k": 2}, {"k": 16}, {"k": 512}, {"block_bytes": 512}, {"block_bytes": 8192},
+    for params in [{"k": 2}, {"k": 16}, {"k": 512}, {"k": 1024}, {"block_bytes": 512}, {"block_bytes": 8192},
                    {"stripes": 1}, {"stripes": 7}, {"workers": 4}, {"workers": 64},
                    {"flags": 1}, {"alpha_x100": 100}, {"base_cap": 1000}, {"seed": 12345}]:
         print(f"[gpu] sort u64 twodup n={n} params={params}", flush=True)
         out = gpu_sort(env, inp, "u64", params)
         assert np.array_equal(out, ref), params
+
+
+def test_sort_equality_buckets_thinned(env):
+    """k = 1024 on an input with about 700 distinct values: the 1023 picks
+    hold duplicates but more than 511 unique values, so equality buckets
+    would exceed the bucket limit and every second pick is used instead."""
+    rng = np.random.default_rng(5)
+    n = 1 << 20
+    vals = np.sort(rng.integers(0, 2**64, 700, dtype=np.uint64))
+    for dtype in ("u64", "f64"):
+        inp = vals[rng.integers(0, 700, n)].copy()
+        if dtype == "f64":
+            inp = inp.view(np.float64)
+            inp = np.where(np.isnan(inp), 1.5, inp)
+        ref = oracle.sort(inp, dtype)
+        print(f"[gpu] sort {dtype} 700 distinct values n={n} k=1024", flush=True)
+        out = gpu_sort(env, inp, dtype, {"k": 1024})
+        assert np.array_equal(out.view(np.uint64), ref.view(np.uint64)), dtype
 
 
 # ---------------------------------------------------- one distribution step

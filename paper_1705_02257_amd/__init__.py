@@ -27,6 +27,7 @@ DTYPES = {"u64": U64, "f64": F64, "pair": PAIR, "quartet": QUARTET, "bytes100": 
 ELEM_BYTES = {U64: 8, F64: 8, PAIR: 16, QUARTET: 32, BYTES100: 100}
 FLAG_NO_SKIP = 1
 DEFAULT_K = 256          # first-level buckets when params leave k at 0
+DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -27,7 +28,7 @@ using namespace ips4o;
 namespace {
 
 constexpr uint32_t kDefaultK = 256;
-constexpr size_t kStatsOffset = 1024;        // misc: error word at 0, counters here
+constexpr size_t kStatsOffset = 1024;        // misc: error word at 0, level counters here
 constexpr uint32_t kDefaultBlockBytes = 2048;
 constexpr uint32_t kMaxBlockBytes = 8192;
 constexpr uint64_t kDefaultSeed = 0x1705022570ull;
@@ -106,6 +107,8 @@ struct ips4o_handle {
     Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
+    Arena rflag;      // permutation read marks, one word per block of the array
+    uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
     std::vector<hipEvent_t> events;   // pool for IPS4O_FLAG_TIMING
@@ -594,6 +597,26 @@ int reset_misc(ips4o_handle* h, hipStream_t st) {
     return IPS4O_OK;
 }
 
+// Read marks for the permutation of one level: one word per block of the
+// n-element array (block index floor(off / b) + local block, plus the
+// partial blocks at segment ends).  A fresh buffer is zeroed and every level
+// takes the next epoch, so a mark equals the level's epoch only once that
+// level has read the block.
+template <int DT>
+int prepare_rflag(ips4o_handle* h, Level<DT>& L, uint64_t n, uint32_t b, hipStream_t st) {
+    const size_t need = (size_t)(n / b + 2) * sizeof(uint32_t);
+    const void* before = h->rflag.p;
+    int rc = h->rflag.ensure(need);
+    if (rc) return rc;
+    if (h->rflag.p != before || h->epoch == 0xffffffffu) {
+        HIP_TRY(hipMemsetAsync(h->rflag.p, 0, h->rflag.bytes, st));
+        h->epoch = 0;
+    }
+    L.c.rflag = (uint32_t*)h->rflag.p;
+    L.c.epoch = ++h->epoch;
+    return IPS4O_OK;
+}
+
 // Read back the per-task state and bounds of a finished level.
 template <int DT>
 int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>& ts,
@@ -636,22 +659,32 @@ void add_to_bins(std::vector<SegD>& bins, size_t first, uint64_t off, uint64_t l
 // Base-case bins larger than half the capacity are sorted by one
 // workgroup of BNT threads per CU; the others by workgroups of BNT/2
 // threads holding half the LDS, two per CU, so that one workgroup's
-// barriers and LDS latencies overlap the other's work.
+// barriers and LDS latencies overlap the other's work.  Each size class
+// runs the counting sort first; the bins it hands back (items crowded into
+// a few digits) are merge-sorted by a second launch that reads their count
+// from device memory.
 template <int DT>
 constexpr uint32_t small_bin_cap() {
     return (uint32_t)(Shape<DT>::BNT / 2) * Shape<DT>::BVT;
 }
 
+constexpr size_t kFailCounts = 256;     // misc: two base-case fallback counters
+
 template <int DT, int NT>
-int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t cap,
-                    uint32_t grid, typename Traits<DT>::Elem* scr, hipStream_t st) {
+int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t grid,
+                    typename Traits<DT>::Elem* scr, SegD* fail, uint32_t* nfail, hipStream_t st) {
     constexpr int BVT = Shape<DT>::BVT;
-    using It = typename BaseItem<DT>::T;
-    const size_t lds = ((NT * sizeof(uint32_t) + 15) & ~size_t(15)) +
-                       (size_t)(cap + (cap + BVT - 1) / BVT + BVT) * sizeof(It);
+    using LB = BaseLds<DT, NT, BVT>;
+    const size_t lds_count = LB::bytes(), lds_merge = LB::xchg_at + NT * sizeof(uint32_t);
+    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase_count<DT, NT, BVT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_count));
     HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, NT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    hipLaunchKernelGGL((k_basecase<DT, NT, BVT>), dim3(grid), dim3(NT), lds, st, c, segs, (uint32_t)nseg, scr);
+                                (int)lds_merge));
+    hipLaunchKernelGGL((k_basecase_count<DT, NT, BVT>), dim3(grid), dim3(NT), lds_count, st, c, segs, (uint32_t)nseg,
+                       scr, fail, nfail);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((k_basecase<DT, NT, BVT>), dim3(grid), dim3(NT), lds_merge, st, c, (const SegD*)fail, 0u, scr,
+                       (const uint32_t*)nfail);
     HIP_TRY(hipGetLastError());
     return IPS4O_OK;
 }
@@ -669,7 +702,8 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     // small bins first, then the large ones
     auto mid = std::stable_partition(list.begin(), list.end(), [&](const SegD& sg) { return sg.len <= half; });
     const size_t nsmall = (size_t)(mid - list.begin()), nlarge = list.size() - nsmall;
-    int rc = h->segs.ensure(list.size() * sizeof(SegD));
+    // the list, then room for the bins each size class hands back
+    int rc = h->segs.ensure(2 * list.size() * sizeof(SegD));
     if (rc) return rc;
     const uint32_t g_small = (uint32_t)std::min<size_t>(nsmall, 2 * kBaseGrid);
     const uint32_t g_large = (uint32_t)std::min<size_t>(nlarge, kBaseGrid);
@@ -684,14 +718,16 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     c.data = (Elem*)d_data;
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
-    const SegD* d_segs = (const SegD*)h->segs.p;
+    SegD* d_segs = (SegD*)h->segs.p;
+    SegD* fail = d_segs + list.size();
+    uint32_t* nfail = (uint32_t*)((char*)h->misc.p + kFailCounts);
     int r = tm.begin(KK_BASE);
     if (nsmall) {
-        rc = launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, std::min(R.cap, half), g_small, scr, st);
+        rc = launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, g_small, scr, fail, nfail, st);
         if (rc) return rc;
     }
     if (nlarge) {
-        rc = launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, R.cap, g_large, scr, st);
+        rc = launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, g_large, scr, fail + nsmall, nfail + 1, st);
         if (rc) return rc;
     }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
@@ -727,11 +763,18 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         rc = h->work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
         carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+        rc = prepare_rflag<DT>(h, L, n, R.b, st);
+        if (rc) return rc;
         LevelMarks mk;
         rc = run_level<DT>(h, L, st, nullptr, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
         if (rc) return rc;
         unsigned long long stats[4] = {0, 0, 0, 0};
+        const auto hr0 = std::chrono::steady_clock::now();
         rc = read_level<DT>(h, L, st, ts, bounds, stats);
+        const auto hr1 = std::chrono::steady_clock::now();
+        if (log_enabled())
+            std::fprintf(stderr, "[ips4o] level %u readback %.3f ms\n", level,
+                         std::chrono::duration<double, std::milli>(hr1 - hr0).count());
         if (rc) return rc;
         account_level<DT>(tm, mk, stats, before, R.b);
         for (int q = 0; q < 4; ++q) before[q] = stats[q];
@@ -765,11 +808,18 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
                 else next.push_back(Seg{off, sz});
             }
         }
+        if (log_enabled())
+            std::fprintf(stderr, "[ips4o] level %u host planning %.3f ms\n", level,
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - hr1).count());
         cur.swap(next);
         ++level;
     }
     h->last.levels = level;
+    const auto hb0 = std::chrono::steady_clock::now();
     rc = run_basecase<DT>(h, d_data, base, R, st, tm);
+    if (log_enabled())
+        std::fprintf(stderr, "[ips4o] base case: %zu bins, %.3f ms including the kernels\n", base.size(),
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - hb0).count());
     if (rc) return rc;
     rc = check_device_error(h, st);
     tm.finish();
@@ -800,6 +850,8 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
     carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+    rc = prepare_rflag<DT>(h, L, n, R.b, st);
+    if (rc) return rc;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     LevelMarks mk;
     rc = run_level<DT>(h, L, st, &ht, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
@@ -984,6 +1036,7 @@ void ips4o_destroy(ips4o_handle* h) {
     h->misc.release();
     h->segs.release();
     h->scratch.release();
+    h->rflag.release();
     delete h;
 }
 

@@ -73,7 +73,7 @@ struct TaskS {                  // device-written per task
 // atomics of different buckets land on different cache lines and channels.
 struct alignas(256) BucketSlot {
     uint64_t wr;        // (w << 32) | (r + 2^31), block indices in the segment
-    uint32_t readers;   // workers currently reading a block of this bucket
+    uint32_t unused;
     uint32_t flag;      // unused
     uint32_t rinit;     // r at the start of the permutation (last full block)
     uint32_t pad[59];
@@ -99,6 +99,8 @@ struct Ctx {
     uint32_t* counts;           // [stripes][KMAX]
     uint32_t* stripe_full;      // [stripes] full blocks after classification
     const uint32_t* order;      // [stripes] classification launch order (largest first)
+    uint32_t* rflag;            // per block of the array: epoch of the level that read it
+    uint32_t epoch;             // this level's mark in rflag (never reused while rflag lives)
     Elem* bufs;                 // stripe bucket buffers
     Elem* ovf;                  // [tasks][b]
     uint32_t* err;              // device error word (0 = ok)
@@ -950,7 +952,6 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
         dl[j] = (uint32_t)((B + c.b - 1) / c.b);
     }
     for (uint32_t j = threadIdx.x; j < K; j += NT) {
-        c.slots[td.slot_begin + j].readers = 0;
     }
     if (threadIdx.x == 0) c.ts[t].ovf_bucket = NO_BUCKET;
 }
@@ -1045,7 +1046,12 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
         for (uint32_t i = lane; i < words; i += 64) dw[i] = sw[i];
     }
     if (threadIdx.x == 0) {
-        uint64_t w = d0, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
+        // a bucket that holds the whole task (all keys equal, for example)
+        // has every full block in place already: it starts with w past r,
+        // so that no worker reads or moves its blocks
+        const uint64_t* bd = c.bounds + td.slot_begin + t;
+        const bool whole = bd[j + 1] - bd[j] == td.m;
+        uint64_t w = whole ? d0 + occ : d0, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
         c.slots[td.slot_begin + j].wr = (w << 32) | (r & 0xffffffffull);
         c.slots[td.slot_begin + j].rinit = d0 + occ;   // one past the last full block
     }
@@ -1053,14 +1059,15 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
 
 // ------------------------------------------------------ block permutation
 // Wavefront workers (Section 4.2).  A worker takes an unprocessed block from
-// its primary bucket by decrementing r_p (announcing itself in the bucket's
-// reader count first), classifies the block's first element to get its
-// destination bucket, and increments w_dest: if the block at the old w_dest
-// is unprocessed it swaps (reads that block, writes its own) and continues
-// with the block it read, unless that block already belongs to dest, in
-// which case it is left in place; if the old w_dest is empty it waits until
-// no worker is still reading from dest, writes its block there and goes back
-// to the primary bucket.  (w_i, r_i) live in one 64-bit word so that every
+// its primary bucket by decrementing r_p, loads it, and then marks the block
+// as read (rflag[block] = this level's epoch); it classifies the block's
+// first element to get its destination bucket and increments w_dest: if the
+// block at the old w_dest is unprocessed it swaps (reads that block, writes
+// its own) and continues with the block it read, unless that block already
+// belongs to dest, in which case it is left in place; if the old w_dest is
+// empty it writes its block there (after the block's reader has marked it,
+// when the position held a full block at the start) and goes back to the
+// primary bucket, where it first tries to claim again directly.  (w_i, r_i) live in one 64-bit word so that every
 // update sees a consistent pair.  A worker stops after a full cycle over the
 // buckets finds no unprocessed block.  The partial last block of a segment is
 // never written in place: the overflow block stands in for it.
@@ -1138,11 +1145,31 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
     uint32_t p = (uint32_t)(((uint64_t)lw * K) / td.nworkers);
     unsigned long long moves = 0, skips = 0;
     const uint32_t limit = c.spin_limit;
+    const uint64_t fbase = td.off / b;          // rflag index of the segment's block 0
+    const uint32_t epoch = c.epoch;
+    // claim block r_q of bucket q; on success the block is in A and marked
+    auto try_claim = [&](uint32_t q, uint32_t& dest) -> bool {
+        uint64_t old = 0;
+        if (lane == 0) old = atom_add64(&sl[q].wr, ~0ull);
+        old = bcast_u64(old);
+        const int64_t w0 = (int64_t)(old >> 32), r0 = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
+        if (r0 < w0) return false;
+        load_block((uint32_t)r0, A);
+        compiler_fence();
+        wait_vmem();          // the block is in registers before it is marked read
+        compiler_fence();
+        if (lane == 0) atom_store32(&c.rflag[fbase + (uint64_t)r0], epoch);
+        dest = first_bucket(A);
+        return true;
+    };
+    bool last_ok = false;
     while (true) {
-        // ---- fetch an unprocessed block from the primary bucket (or the next ones)
+        // ---- fetch an unprocessed block: the primary bucket directly after a
+        // success there, else a scan over the buckets for a candidate
         bool got = false;
         uint32_t destA = 0;
-        for (uint32_t scanned = 0; scanned < K;) {
+        if (last_ok) got = try_claim(p, destA);
+        for (uint32_t scanned = 0; !got && scanned < K;) {
             // look at 64 buckets at once, starting at p
             uint32_t q = p + lane;
             if (q >= K) q -= K;
@@ -1164,32 +1191,9 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             scanned += first;
             p += first;
             if (p >= K) p -= K;
-            // try to claim a block of bucket p: announce the reader first and
-            // wait until that increment has been performed, so that a writer
-            // that sees the decremented r also sees the reader
-            uint64_t old = 0;
-            if (lane == 0) {
-                uint32_t rd = atom_add32(&sl[p].readers, 1u);
-                compiler_fence();
-                wait_vmem();
-                compiler_fence();
-                (void)rd;
-                old = atom_add64(&sl[p].wr, ~0ull);
-            }
-            old = bcast_u64(old);
-            int64_t w0 = (int64_t)(old >> 32), r0 = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
-            if (r0 >= w0) {
-                load_block((uint32_t)r0, A);
-                compiler_fence();
-                wait_vmem();          // the block is in registers before the reader leaves
-                compiler_fence();
-                if (lane == 0) atom_add32(&sl[p].readers, ~0u);
-                destA = first_bucket(A);
-                got = true;
-                break;
-            }
-            if (lane == 0) atom_add32(&sl[p].readers, ~0u);
+            got = try_claim(p, destA);
         }
+        last_ok = got;
         if (!got) break;
         // ---- place the block, swapping along the way
         while (true) {
@@ -1223,15 +1227,15 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             }
             // empty block at x.  If x was a full block when the permutation
             // started, a reader took it and may still be loading it: wait
-            // until no reader of dest is active (this happens where w and r
+            // until that reader has marked it (this happens where w and r
             // cross, at most once per bucket); blocks that were empty from
             // the start were never read.
             uint32_t spins = 0;
             while ((uint32_t)x < sl[destA].rinit) {
-                uint32_t rd = 0;
-                if (lane == 0) rd = atom_load32(&sl[destA].readers);
-                rd = bcast_u32(rd);
-                if (rd == 0) break;
+                uint32_t f = 0;
+                if (lane == 0) f = atom_load32(&c.rflag[fbase + (uint64_t)x]);
+                f = bcast_u32(f);
+                if (f == epoch) break;
                 if (++spins > limit) {
                     if (lane == 0) raise_err(c.err, ERR_SPIN);
                     break;
@@ -1459,21 +1463,10 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
 }
 
 // -------------------------------------------------------------- base case
-// Sorts each listed segment (at most NT*VT elements) inside one workgroup's
-// LDS.  The segment is padded with maximal sentinels to a multiple of VT, so
-// every thread owns exactly VT items and no access needs a bounds check.
-// Every thread sorts its VT items in registers with a bitonic network; then
-// log2(len / VT) merge passes double the sorted runs.  In a pass each thread
-// finds where its VT outputs start in the merge of its two runs by a binary
-// search along its cross diagonal (merge path); the next thread's start,
-// exchanged through LDS, says how many of the VT outputs come from each run,
-// na from the first and VT - na from the second.  The thread loads those na
-// items ascending followed by the VT - na items descending (a bitonic
-// sequence holding exactly its outputs, one load per output) and sorts them
-// with a bitonic merge.  u64/f64 sort the keys themselves (f64 through the
-// bijective totalOrder image); records sort (key, index) items, ties broken
-// by index so that the sentinels (index 2^32 - 1) stay last, and then gather
-// whole records from a per-workgroup scratch copy of the segment.
+// Subproblems of at most the base-case capacity are sorted inside one
+// workgroup's LDS (u64/f64 sort the keys themselves, f64 through the
+// bijective totalOrder image; records sort (key, index) items and then
+// gather whole records from a per-workgroup scratch copy of the segment).
 struct SegD {
     uint64_t off;
     uint32_t len;
@@ -1556,21 +1549,213 @@ __device__ inline void bitonic_merge(typename BI::T (&x)[VT]) {
     bitonic_merge_stages<BI, VT, VT / 2>(x);
 }
 
+// Leading 64-bit word of a base-case item (the key itself for u64/f64).
+__device__ inline uint64_t item_lead(uint64_t k) { return k; }
+template <class Key>
+__device__ inline uint64_t item_lead(const KeyIdx<Key>& it) { return lead_word(it.k); }
+
+// LDS layout of the base case: the items first (CAP of them for the
+// counting sort; CAP + CAP/VT + VT padded slots for the merge sort), then
+// either the 2^(log2 CAP - 1) digit counters or the merge-path starts.
 template <int DT, int NT, int VT>
-__global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, uint32_t nseg,
-                                                 typename Traits<DT>::Elem* scratch) {
+struct BaseLds {
+    using It = typename BaseItem<DT>::T;
+    static constexpr uint32_t CAP = NT * VT;
+    static constexpr uint32_t LOG_CAP = CAP >= 16384 ? 14 : CAP >= 8192 ? 13 : CAP >= 4096 ? 12 : CAP >= 2048 ? 11 : 10;
+    static constexpr uint32_t RADIX = 1u << (LOG_CAP - 1);
+    static constexpr size_t merge_items = CAP + CAP / VT + VT;
+    static constexpr size_t counters_at = CAP * sizeof(It);
+    static constexpr size_t xchg_at = (merge_items * sizeof(It) + 15) & ~size_t(15);
+    static constexpr size_t bytes() {
+        const size_t r = counters_at + RADIX * sizeof(uint32_t);
+        const size_t m = xchg_at + NT * sizeof(uint32_t);
+        return r > m ? r : m;
+    }
+};
+
+// Counting sort of each listed segment (at most NT*VT elements) inside one
+// workgroup's LDS, on the top bits of the leading word: every thread holds
+// VT items in registers; the span [lo, hi] of their leading words is split
+// into 2^(log2 CAP - 1) equal digit ranges, an LDS atomic per item counts
+// its digit (and returns its rank in it), and after an exclusive scan each
+// item goes to its digit's group.  Groups hold about two items; each item's
+// final place is the group start plus the number of group members that
+// precede it (smaller, or equal and placed earlier).  A segment whose keys
+// are all equal is left as it is.  Segments whose items crowd into a few
+// digits (a group of more than 32, or records with one leading word) are
+// left untouched and appended to `fail` for k_basecase (merge sort).
+template <int DT, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
+                                                       typename Traits<DT>::Elem* scratch, SegD* fail,
+                                                       uint32_t* nfail) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     using BI = BaseItem<DT>;
     using It = typename BI::T;
+    using LB = BaseLds<DT, NT, VT>;
+    constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
+    constexpr uint32_t RADIX = LB::RADIX, GMAX = 32, NW = NT / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    It* items = reinterpret_cast<It*>(smem_raw);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);
+    uint64_t* red = reinterpret_cast<uint64_t*>(smem_raw + LB::counters_at);     // before cnt is used
+    // scan and maximum scratch of the counting sort: the start of the item
+    // array, which is free until the items are scattered into it
+    uint32_t* scan_sh = reinterpret_cast<uint32_t*>(smem_raw);
+    uint32_t* gmax_sh = scan_sh + 32;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
+        const SegD sg = segs[si];
+        const uint32_t len = sg.len;
+        Elem* seg = c.data + sg.off;
+        Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
+        It x[VT];
+        uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+        for (int v = 0; v < VT; ++v) {
+            const uint32_t i = v * NT + tid;
+            x[v] = BI::maxv();
+            if (i < len) {
+                const Elem e = seg[i];
+                if constexpr (kPlain) {
+                    x[v] = TR::key(e).v;
+                } else {
+                    scr[i] = e;
+                    x[v] = It{TR::key(e), i};
+                }
+                const uint64_t w = item_lead(x[v]);
+                lo = w < lo ? w : lo;
+                hi = w > hi ? w : hi;
+            }
+        }
+        // span of the leading words over the segment
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint64_t l2 = __shfl_xor(lo, d, 64), h2 = __shfl_xor(hi, d, 64);
+            lo = l2 < lo ? l2 : lo;
+            hi = h2 > hi ? h2 : hi;
+        }
+        if (lane == 0) { red[2 * wid] = lo; red[2 * wid + 1] = hi; }
+        __syncthreads();
+        lo = red[0];
+        hi = red[1];
+        for (uint32_t w = 1; w < NW; ++w) {
+            lo = red[2 * w] < lo ? red[2 * w] : lo;
+            hi = red[2 * w + 1] > hi ? red[2 * w + 1] : hi;
+        }
+        __syncthreads();
+        if (kPlain && lo == hi) continue;           // all keys equal: already sorted
+        bool radix = lo != hi;
+        uint32_t dr[VT];                            // digit | rank << 16
+        if (radix) {
+            const uint64_t span = hi - lo;
+            const uint32_t bits = 64u - (uint32_t)__clzll(span);
+            const uint32_t sh = bits > LB::LOG_CAP - 1 ? bits - (LB::LOG_CAP - 1) : 0u;
+            for (uint32_t q = tid; q < RADIX; q += NT) cnt[q] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VT; ++v) {
+                if (v * NT + tid < len) {
+                    const uint32_t d = (uint32_t)((item_lead(x[v]) - lo) >> sh);
+                    dr[v] = d | (atomicAdd(&cnt[d], 1u) << 16);
+                }
+            }
+            __syncthreads();
+            // exclusive scan of the counters; largest group
+            constexpr uint32_t PERC = RADIX / NT;
+            uint32_t cv[PERC], loc = 0, gm = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < PERC; ++q) {
+                cv[q] = cnt[tid * PERC + q];
+                loc += cv[q];
+                gm = cv[q] > gm ? cv[q] : gm;
+            }
+            uint32_t total;
+            uint32_t pre = block_excl_scan<NT>(loc, scan_sh, &total);
+#pragma unroll
+            for (uint32_t q = 0; q < PERC; ++q) {
+                cnt[tid * PERC + q] = pre;
+                pre += cv[q];
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint32_t o = __shfl_xor(gm, d, 64);
+                gm = o > gm ? o : gm;
+            }
+            if (lane == 0) gmax_sh[wid] = gm;
+            __syncthreads();
+            gm = 0;
+            for (uint32_t w = 0; w < NW; ++w) gm = gmax_sh[w] > gm ? gmax_sh[w] : gm;
+            radix = gm <= GMAX;
+            __syncthreads();                        // scan_sh and gmax_sh are read
+        }
+        if (radix) {
+            // each item to its group; then to its place inside the group
+#pragma unroll
+            for (int v = 0; v < VT; ++v)
+                if (v * NT + tid < len) items[cnt[dr[v] & 0xffffu] + (dr[v] >> 16)] = x[v];
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VT; ++v) {
+                if (v * NT + tid < len) {
+                    const uint32_t d = dr[v] & 0xffffu;
+                    const uint32_t g0 = cnt[d], g1 = d + 1 < RADIX ? cnt[d + 1] : len;
+                    const uint32_t pos = g0 + (dr[v] >> 16);
+                    uint32_t rank = 0;
+                    for (uint32_t j = g0; j < g1; ++j) {
+                        const It y = items[j];
+                        rank += (BI::less(y, x[v]) || (j < pos && !BI::less(x[v], y))) ? 1u : 0u;
+                    }
+                    dr[v] = g0 + rank;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < VT; ++v)
+                if (v * NT + tid < len) items[dr[v]] = x[v];
+            __syncthreads();
+            for (uint32_t i = tid; i < len; i += NT) {
+                if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(items[i]);
+                else if constexpr (DT == DT_U64) seg[i] = items[i];
+                else seg[i] = scr[items[i].i];
+            }
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0) fail[atomicAdd(nfail, 1u)] = sg;
+    }
+}
+
+// Merge sort of each listed segment (at most NT*VT elements; the count is
+// read from `dev_nseg` when given) inside one workgroup's LDS.  The segment
+// is padded to lenP (a multiple of VT) with maximal sentinels, so every
+// thread owns exactly VT items and no access needs a bounds check.  Every
+// thread sorts its VT items in registers with a bitonic network; then
+// log2(len / VT) merge passes double the sorted runs.  In a pass each thread
+// finds where its VT outputs start in the merge of its two runs by a binary
+// search along its cross diagonal (merge path); the next thread's start,
+// exchanged through LDS, says how many of the VT outputs come from each run,
+// na from the first and VT - na from the second.  The thread loads those na
+// items ascending followed by the VT - na items descending (a bitonic
+// sequence holding exactly its outputs) and sorts them with a bitonic merge.
+// Records break ties by index, so the sentinels (index 2^32 - 1) stay last.
+template <int DT, int NT, int VT>
+__global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, uint32_t nseg,
+                                                 typename Traits<DT>::Elem* scratch, const uint32_t* dev_nseg) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    using BI = BaseItem<DT>;
+    using It = typename BI::T;
+    using LB = BaseLds<DT, NT, VT>;
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    uint32_t* xchg = reinterpret_cast<uint32_t*>(smem_raw);                  // NT merge-path starts
-    It* lds = reinterpret_cast<It*>(smem_raw + ((NT * sizeof(uint32_t) + 15) & ~size_t(15)));
+    It* items = reinterpret_cast<It*>(smem_raw);
+    uint32_t* xchg = reinterpret_cast<uint32_t*>(smem_raw + LB::xchg_at);
     auto pidx = [](uint32_t i) { return i + i / VT; };   // one pad item per VT: fewer bank conflicts
     const uint32_t tid = threadIdx.x;
     const uint32_t base = tid * VT;
-    It* const mine = lds + pidx(base);                    // this thread's VT items, contiguous
+    It* const mine = items + pidx(base);
+    if (dev_nseg) nseg = *dev_nseg;
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
         const SegD sg = segs[si];
         const uint32_t len = sg.len;
@@ -1588,7 +1773,7 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
                     v = It{TR::key(e), i};
                 }
             }
-            lds[pidx(i)] = v;
+            items[pidx(i)] = v;
         }
         __syncthreads();
         const uint32_t nthr = lenP / VT;
@@ -1605,22 +1790,22 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
                 for (int v = 0; v < VT; ++v) mine[v] = x[v];
             }
             __syncthreads();
-            uint32_t lo = 0, a0 = 0, aCount = 0, b0 = 0, diag = 0;
+            uint32_t lo2 = 0, a0 = 0, aCount = 0, b0 = 0, diag = 0;
             if (tid < nthr) {
                 a0 = base & ~(2 * L - 1);
                 aCount = min(L, lenP - a0);
                 b0 = a0 + L;
                 const uint32_t bCount = b0 >= lenP ? 0u : min(L, lenP - b0);
                 diag = base - a0;
-                lo = diag > bCount ? diag - bCount : 0u;
-                uint32_t hi = diag < aCount ? diag : aCount;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    const It av = lds[pidx(a0 + mid)];
-                    const It bv = lds[pidx(b0 + diag - 1 - mid)];
-                    if (!BI::less(bv, av)) lo = mid + 1; else hi = mid;
+                lo2 = diag > bCount ? diag - bCount : 0u;
+                uint32_t hi2 = diag < aCount ? diag : aCount;
+                while (lo2 < hi2) {
+                    const uint32_t mid = (lo2 + hi2) >> 1;
+                    const It av = items[pidx(a0 + mid)];
+                    const It bv = items[pidx(b0 + diag - 1 - mid)];
+                    if (!BI::less(bv, av)) lo2 = mid + 1; else hi2 = mid;
                 }
-                xchg[tid] = lo;
+                xchg[tid] = lo2;
             }
             lds_barrier();
             if (tid < nthr) {
@@ -1628,11 +1813,11 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
                 // ends it (end of both runs or of the padded segment)
                 const uint32_t end = min(a0 + 2 * L, lenP);
                 const uint32_t lo_next = base + VT < end ? xchg[tid + 1] : aCount;
-                const uint32_t na = lo_next - lo;
-                const uint32_t ai = a0 + lo, bi_last = b0 + (diag - lo) + VT - 1;
+                const uint32_t na = lo_next - lo2;
+                const uint32_t ai = a0 + lo2, bi_last = b0 + (diag - lo2) + VT - 1;
 #pragma unroll
                 for (int v = 0; v < VT; ++v)
-                    x[v] = lds[pidx((uint32_t)v < na ? ai + v : bi_last - v)];
+                    x[v] = items[pidx((uint32_t)v < na ? ai + v : bi_last - v)];
                 bitonic_merge<BI, VT>(x);
             }
         }
@@ -1643,9 +1828,9 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
         }
         __syncthreads();
         for (uint32_t i = tid; i < len; i += NT) {
-            if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(lds[pidx(i)]);
-            else if constexpr (DT == DT_U64) seg[i] = lds[pidx(i)];
-            else seg[i] = scr[lds[pidx(i)].i];
+            if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(items[pidx(i)]);
+            else if constexpr (DT == DT_U64) seg[i] = items[pidx(i)];
+            else seg[i] = scr[items[pidx(i)].i];
         }
         __syncthreads();
     }

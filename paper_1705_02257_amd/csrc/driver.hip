@@ -78,6 +78,29 @@ struct Arena {  // grow-only device buffer
     }
 };
 
+struct HostArena {  // grow-only pinned host buffer (fast, asynchronous copies)
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need) {
+        if (need <= bytes) return IPS4O_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        size_t want = need + need / 4;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return IPS4O_ERR_OUT_OF_MEMORY;
+        }
+        bytes = want;
+        return IPS4O_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
 struct Carve {  // sequential sub-allocation with 256-byte alignment
     char* base;
     size_t off = 0;
@@ -108,6 +131,7 @@ struct ips4o_handle {
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
     Arena rflag;      // permutation read marks, one word per block of the array
+    HostArena hbounds;    // pinned copy of a level's bucket bounds
     uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
@@ -620,12 +644,15 @@ int prepare_rflag(ips4o_handle* h, Level<DT>& L, uint64_t n, uint32_t b, hipStre
 // Read back the per-task state and bounds of a finished level.
 template <int DT>
 int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>& ts,
-               std::vector<uint64_t>& bounds, unsigned long long* stats) {
+               const uint64_t*& bounds, unsigned long long* stats) {
     const size_t T = L.tasks.size();
     ts.resize(T);
-    bounds.resize(L.total_slots + T);
+    const size_t nb = L.total_slots + T;
+    int rc0 = h->hbounds.ensure(nb * sizeof(uint64_t));
+    if (rc0) return rc0;
     HIP_TRY(hipMemcpyAsync(ts.data(), L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(bounds.data(), L.c.bounds, bounds.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h->hbounds.p, L.c.bounds, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    bounds = (const uint64_t*)h->hbounds.p;
     unsigned long long spread[STAT_SPREAD * 8];
     HIP_TRY(hipMemcpyAsync(spread, L.c.stats, sizeof(spread), hipMemcpyDeviceToHost, st));
     const int rc = check_device_error(h, st);
@@ -732,6 +759,12 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
     HIP_TRY(hipStreamSynchronize(st));   // the host list must outlive the copy
+    if (log_enabled()) {
+        uint32_t nf[2] = {0, 0};
+        HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "[ips4o] base case: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted)\n",
+                     nsmall, nf[0], nlarge, nf[1]);
+    }
     return IPS4O_OK;
 }
 
@@ -754,7 +787,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     uint32_t level = 0;
     Level<DT> L;
     std::vector<TaskS> ts;
-    std::vector<uint64_t> bounds;
+    const uint64_t* bounds = nullptr;     // pinned, valid until the next level's readback
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     unsigned long long before[4] = {0, 0, 0, 0};
     while (!cur.empty()) {
@@ -793,9 +826,10 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         for (const Seg& s : cur) h->last.elements_distributed += s.m;
         std::vector<Seg> next;
         const size_t first_bin = base.size();
+        base.reserve(base.size() + L.total_slots);
         for (size_t t = 0; t < L.tasks.size(); ++t) {
             const TaskD& td = L.tasks[t];
-            const uint64_t* bd = bounds.data() + td.slot_begin + t;
+            const uint64_t* bd = bounds + td.slot_begin + t;
             for (uint32_t i = 0; i < ts[t].K; ++i) {
                 uint64_t sz = bd[i + 1] - bd[i];
                 if (sz <= 1) continue;
@@ -857,7 +891,7 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     rc = run_level<DT>(h, L, st, &ht, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
     if (rc) return rc;
     std::vector<TaskS> ts;
-    std::vector<uint64_t> bounds;
+    const uint64_t* bounds = nullptr;     // pinned, valid until the next level's readback
     unsigned long long stats[4] = {0, 0, 0, 0}, zero[4] = {0, 0, 0, 0};
     rc = read_level<DT>(h, L, st, ts, bounds, stats);
     account_level<DT>(tm, mk, stats, zero, R.b);
@@ -1037,6 +1071,7 @@ void ips4o_destroy(ips4o_handle* h) {
     h->segs.release();
     h->scratch.release();
     h->rflag.release();
+    h->hbounds.release();
     delete h;
 }
 

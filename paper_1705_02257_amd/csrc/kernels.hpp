@@ -1045,13 +1045,43 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
         const Word* sw = reinterpret_cast<const Word*>(seg + (uint64_t)src_blk * b);
         for (uint32_t i = lane; i < words; i += 64) dw[i] = sw[i];
     }
+    // In-place prefix: the first full blocks of the range may hold bucket j
+    // already (presorted inputs; a bucket that holds the whole task).  They
+    // count as processed: w starts after them, so that no worker reads or
+    // moves them.  A full block holds one bucket, so its first element
+    // decides.
+    __shared__ uint32_t first_foreign;
+    const uint64_t* bd = c.bounds + td.slot_begin + t;
+    const bool whole = bd[j + 1] - bd[j] == td.m;       // every block holds bucket j
+    if (threadIdx.x == 0) first_foreign = c.skip_inplace ? occ : 0u;
+    if (c.skip_inplace && occ > 0 && !whole) {
+        __syncthreads();                        // this workgroup's moves above are visible
+        using Key = typename Traits<DT>::Key;
+        const TaskS st = c.ts[t];
+        const Key* spl = c.spl + td.tree_begin;
+        // bucket j is [lower, upper) of the keys, or one splitter value
+        const uint32_t leaf = st.eq ? (j + 1) / 2 : j;
+        const bool eq_bucket = st.eq && (j & 1);
+        const bool has_lo = leaf >= 1, has_hi = leaf < st.nuniq;
+        const Key klo = has_lo ? spl[leaf - 1] : Key{}, khi = has_hi ? spl[leaf] : Key{};
+        auto in_bucket = [&](const Key& e) {
+            if (eq_bucket) return e == klo;
+            if (has_lo && (st.eq ? !(klo < e) : e < klo)) return false;
+            return !has_hi || e < khi;
+        };
+        // the first block alone first: on unsorted inputs it decides
+        for (uint32_t i0 = 0, step = 1; i0 < occ; i0 += step, step = NT) {
+            const uint32_t i = i0 + threadIdx.x;
+            if (threadIdx.x < step && i < occ && !in_bucket(Traits<DT>::key(seg[(uint64_t)(d0 + i) * b])))
+                atomicMin(&first_foreign, i);
+            __syncthreads();
+            if (first_foreign < occ) break;
+        }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        // a bucket that holds the whole task (all keys equal, for example)
-        // has every full block in place already: it starts with w past r,
-        // so that no worker reads or moves its blocks
-        const uint64_t* bd = c.bounds + td.slot_begin + t;
-        const bool whole = bd[j + 1] - bd[j] == td.m;
-        uint64_t w = whole ? d0 + occ : d0, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
+        const uint32_t prefix = first_foreign;
+        uint64_t w = d0 + prefix, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
         c.slots[td.slot_begin + j].wr = (w << 32) | (r & 0xffffffffull);
         c.slots[td.slot_begin + j].rinit = d0 + occ;   // one past the last full block
     }
@@ -1067,7 +1097,7 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
 // belongs to dest, in which case it is left in place; if the old w_dest is
 // empty it writes its block there (after the block's reader has marked it,
 // when the position held a full block at the start) and goes back to the
-// primary bucket, where it first tries to claim again directly.  (w_i, r_i) live in one 64-bit word so that every
+// primary bucket.  (w_i, r_i) live in one 64-bit word so that every
 // update sees a consistent pair.  A worker stops after a full cycle over the
 // buckets finds no unprocessed block.  The partial last block of a segment is
 // never written in place: the overflow block stands in for it.
@@ -1162,13 +1192,13 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
         dest = first_bucket(A);
         return true;
     };
-    bool last_ok = false;
     while (true) {
-        // ---- fetch an unprocessed block: the primary bucket directly after a
-        // success there, else a scan over the buckets for a candidate
+        // ---- fetch an unprocessed block: scan the buckets from the primary
+        // one for a candidate and claim there.  (Claiming again directly
+        // where the last claim succeeded saves the scan, but on presorted
+        // inputs it piles every worker onto the same few buckets.)
         bool got = false;
         uint32_t destA = 0;
-        if (last_ok) got = try_claim(p, destA);
         for (uint32_t scanned = 0; !got && scanned < K;) {
             // look at 64 buckets at once, starting at p
             uint32_t q = p + lane;
@@ -1193,7 +1223,6 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             if (p >= K) p -= K;
             got = try_claim(p, destA);
         }
-        last_ok = got;
         if (!got) break;
         // ---- place the block, swapping along the way
         while (true) {
@@ -1582,7 +1611,7 @@ struct BaseLds {
 // final place is the group start plus the number of group members that
 // precede it (smaller, or equal and placed earlier).  A segment whose keys
 // are all equal is left as it is.  Segments whose items crowd into a few
-// digits (a group of more than 32, or records with one leading word) are
+// digits (a group of more than 64, or records with one leading word) are
 // left untouched and appended to `fail` for k_basecase (merge sort).
 template <int DT, int NT, int VT>
 __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
@@ -1594,7 +1623,7 @@ __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* se
     using It = typename BI::T;
     using LB = BaseLds<DT, NT, VT>;
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
-    constexpr uint32_t RADIX = LB::RADIX, GMAX = 32, NW = NT / 64;
+    constexpr uint32_t RADIX = LB::RADIX, GMAX = 64, NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     It* items = reinterpret_cast<It*>(smem_raw);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);

@@ -1614,7 +1614,7 @@ struct BaseLds {
 // digits (a group of more than 64, or records with one leading word) are
 // left untouched and appended to `fail` for k_basecase (merge sort).
 template <int DT, int NT, int VT>
-__global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
                                                        typename Traits<DT>::Elem* scratch, SegD* fail,
                                                        uint32_t* nfail) {
     using TR = Traits<DT>;
@@ -1633,11 +1633,26 @@ __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* se
     uint32_t* scan_sh = reinterpret_cast<uint32_t*>(smem_raw);
     uint32_t* gmax_sh = scan_sh + 32;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
+    // u64/f64: the next bin's keys are loaded before this bin is written
+    // out, with loads and stores free of guards (indexes clamped to the
+    // bin), so the wait for the loads does not include those stores
+    Elem raw[kPlain ? VT : 1];
+    SegD sg{};
+    auto fetch = [&](uint32_t s2) {
+        if constexpr (kPlain) {
+            sg = segs[s2];
+            const Elem* src = c.data + sg.off;
+#pragma unroll
+            for (int v = 0; v < VT; ++v) raw[v] = src[min((uint32_t)(v * NT) + tid, sg.len - 1)];
+        } else {
+            sg = segs[s2];
+        }
+    };
+    if (blockIdx.x < nseg) fetch(blockIdx.x);
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
-        const SegD sg = segs[si];
         const uint32_t len = sg.len;
         Elem* seg = c.data + sg.off;
-        Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
         It x[VT];
         uint64_t lo = ~0ull, hi = 0;
 #pragma unroll
@@ -1645,10 +1660,10 @@ __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* se
             const uint32_t i = v * NT + tid;
             x[v] = BI::maxv();
             if (i < len) {
-                const Elem e = seg[i];
                 if constexpr (kPlain) {
-                    x[v] = TR::key(e).v;
+                    x[v] = TR::key(raw[v]).v;
                 } else {
+                    const Elem e = seg[i];
                     scr[i] = e;
                     x[v] = It{TR::key(e), i};
                 }
@@ -1673,8 +1688,9 @@ __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* se
             hi = red[2 * w + 1] > hi ? red[2 * w + 1] : hi;
         }
         __syncthreads();
-        if (kPlain && lo == hi) continue;           // all keys equal: already sorted
+        // all keys equal: already sorted; records with one leading word: merge sort
         bool radix = lo != hi;
+        bool sorted = false;
         uint32_t dr[VT];                            // digit | rank << 16
         if (radix) {
             const uint64_t span = hi - lo;
@@ -1742,16 +1758,32 @@ __global__ __launch_bounds__(NT) void k_basecase_count(Ctx<DT> c, const SegD* se
 #pragma unroll
             for (int v = 0; v < VT; ++v)
                 if (v * NT + tid < len) items[dr[v]] = x[v];
-            __syncthreads();
-            for (uint32_t i = tid; i < len; i += NT) {
-                if constexpr (DT == DT_F64) seg[i] = Traits<DT_F64>::unkey(items[i]);
-                else if constexpr (DT == DT_U64) seg[i] = items[i];
-                else seg[i] = scr[items[i].i];
-            }
-            __syncthreads();
-            continue;
+            sorted = true;
+        } else if (!(kPlain && lo == hi)) {
+            if (tid == 0) fail[atomicAdd(nfail, 1u)] = sg;
         }
-        if (tid == 0) fail[atomicAdd(nfail, 1u)] = sg;
+        __syncthreads();
+        const SegD cur = sg;
+        if (si + gridDim.x < nseg) fetch(si + gridDim.x);
+        if (sorted) {
+            Elem* out = c.data + cur.off;
+            if constexpr (kPlain) {
+                // four at a time: the next bin's keys already occupy registers
+#pragma unroll
+                for (int v0 = 0; v0 < VT; v0 += 4) {
+#pragma unroll
+                    for (int v = v0; v < v0 + 4; ++v) {
+                        const uint32_t i = min((uint32_t)(v * NT) + tid, cur.len - 1);
+                        if constexpr (DT == DT_F64) out[i] = Traits<DT_F64>::unkey(items[i]);
+                        else out[i] = items[i];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                for (uint32_t i = tid; i < cur.len; i += NT) out[i] = scr[items[i].i];
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -10,12 +10,14 @@ average duration per kernel) headed by the command that produced it.
 
 `traffic` reads the counter_collection.csv of two `rocprofv3 --pmc` runs of
 the same program, one with FETCH_SIZE and one with WRITE_SIZE (KiB per
-dispatch).  The program must contain one plain device-to-device copy of
-`copy-bytes` bytes (the largest copyBuffer dispatch): the ratio between its
+dispatch).  The program must sort exactly once and contain one plain
+device-to-device copy of `copy-bytes` bytes (the largest copyBuffer
+dispatch): the ratio between its
 known size and what each counter reports for it is the calibration factor
-applied to every other dispatch.  For each library kernel it writes
-traffic_<kind>.json with the calibrated HBM bytes per launch, stamped with
-the hash of the kernel sources the counters were taken on.
+applied to every other dispatch.  For each kernel kind it writes
+traffic_<kind>.json with the calibrated HBM bytes of all its dispatches in
+the sort (hbm_bytes), stamped with the hash of the kernel sources the
+counters were taken on.
 """
 import argparse
 import csv
@@ -29,10 +31,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "traits.hpp", "driver.hip")]
 
-# mangled-name fragment -> the kernel kinds the library reports timings under
+# kernel-name prefix -> the kernel kind the library reports timings under
+# (one timing record may span several launches: the overhang copy and the
+# cleanup; the counting sort and its merge-sort fallback)
 KINDS = [("k_sample", "sample"), ("k_classify", "classify"), ("k_scan", "scan"),
-         ("k_fix_empty", "fix_empty"), ("k_permute", "permute"), ("k_cleanup", "cleanup"),
-         ("k_basecase", "basecase")]
+         ("k_fix_empty", "fix_empty"), ("k_permute", "permute"), ("k_overhang", "cleanup"),
+         ("k_cleanup", "cleanup"), ("k_basecase", "basecase")]
 COPY = "__amd_rocclr_copyBuffer"
 
 
@@ -45,8 +49,8 @@ def source_sha() -> str:
 
 
 def kind_of(name: str):
-    for frag, kind in KINDS:
-        if re.search(r"\b" + frag + r"\b", name):
+    for prefix, kind in KINDS:
+        if re.search(r"\b" + prefix, name):
             return kind
     return None
 
@@ -80,7 +84,7 @@ def _counter(d: str, counter: str):
 
 
 def traffic(fetch_dir: str, write_dir: str, copy_bytes: int):
-    """Calibrated HBM bytes per launch of every library kernel kind."""
+    """Calibrated HBM bytes of every library kernel kind over the run."""
     fetch = _counter(fetch_dir, "FETCH_SIZE")
     write = _counter(write_dir, "WRITE_SIZE")
     if len(fetch) != len(write):
@@ -100,7 +104,7 @@ def traffic(fetch_dir: str, write_dir: str, copy_bytes: int):
         a["fetch_kib"] += vf
         a["write_kib"] += vw
     for a in acc.values():
-        a["hbm_bytes_per_launch"] = (a["fetch_kib"] * sf + a["write_kib"] * sw) * 1024.0 / a["launches"]
+        a["hbm_bytes"] = (a["fetch_kib"] * sf + a["write_kib"] * sw) * 1024.0
     return acc, sf, sw
 
 
@@ -130,7 +134,7 @@ def main(argv=None) -> int:
         with open(os.path.join(a.out_dir, f"traffic_{kind}.json"), "w") as f:
             json.dump(rec, f, indent=1)
             f.write("\n")
-    print(json.dumps({k: round(v["hbm_bytes_per_launch"] / 1e9, 3) for k, v in acc.items()}), file=sys.stderr)
+    print(json.dumps({k: round(v["hbm_bytes"] / 1e9, 3) for k, v in acc.items()}), file=sys.stderr)
     return 0
 
 

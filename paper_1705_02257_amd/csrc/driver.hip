@@ -132,6 +132,7 @@ struct ips4o_handle {
     Arena scratch;    // base-case record scratch
     Arena rflag;      // permutation read marks, one word per block of the array
     HostArena hbounds;    // pinned copy of a level's bucket bounds
+    HostArena hsegs;      // pinned staging of the base-case bin list
     uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
@@ -554,7 +555,23 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     HIP_TRY(hipGetLastError());
     tm.end(r, 0.0);
     mk.fix = tm.begin(KK_FIX);
-    hipLaunchKernelGGL((k_fix_empty<DT, 256>), dim3(L.total_slots), dim3(256), 0, st, c);
+    {
+        // one workgroup per bucket: 16 waves when tasks have many stripes
+        // (many holes per bucket), else one wave
+        uint32_t nsmax = 1, kmax = 0;
+        for (const TaskD& t : L.tasks) {
+            nsmax = std::max(nsmax, t.nstripes);
+            kmax = std::max(kmax, 2 * t.k);
+        }
+        for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+            const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+            if (nsmax > 64)
+                hipLaunchKernelGGL((k_fix_empty<DT, 1024, STRIPES_PER_TASK_MAX>), dim3(kmax, nt), dim3(1024), 0, st, c, t0);
+            else
+                hipLaunchKernelGGL((k_fix_empty<DT, 64, 64>), dim3(kmax, nt), dim3(64), 0, st, c, t0);
+            HIP_TRY(hipGetLastError());
+        }
+    }
     HIP_TRY(hipGetLastError());
     tm.end(mk.fix, 0.0);
     mk.permute = tm.begin(KK_PERMUTE);
@@ -726,11 +743,19 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     static_assert(BNT * BVT == TR::kBaseCap, "base-case capacity");
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
     const uint32_t half = small_bin_cap<DT>();
-    // small bins first, then the large ones
-    auto mid = std::stable_partition(list.begin(), list.end(), [&](const SegD& sg) { return sg.len <= half; });
-    const size_t nsmall = (size_t)(mid - list.begin()), nlarge = list.size() - nsmall;
+    // small bins first, then the large ones, staged in pinned memory
+    size_t nsmall = 0;
+    for (const SegD& sg : list) nsmall += sg.len <= half ? 1 : 0;
+    const size_t nlarge = list.size() - nsmall;
+    int rc = h->hsegs.ensure(list.size() * sizeof(SegD));
+    if (rc) return rc;
+    {
+        SegD* hs = (SegD*)h->hsegs.p;
+        size_t a = 0, bl = nsmall;
+        for (const SegD& sg : list) hs[sg.len <= half ? a++ : bl++] = sg;
+    }
     // the list, then room for the bins each size class hands back
-    int rc = h->segs.ensure(2 * list.size() * sizeof(SegD));
+    rc = h->segs.ensure(2 * list.size() * sizeof(SegD));
     if (rc) return rc;
     const uint32_t g_small = (uint32_t)std::min<size_t>(nsmall, 2 * kBaseGrid);
     const uint32_t g_large = (uint32_t)std::min<size_t>(nlarge, kBaseGrid);
@@ -740,7 +765,7 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
         if (rc) return rc;
         scr = (Elem*)h->scratch.p;
     }
-    HIP_TRY(hipMemcpyAsync(h->segs.p, list.data(), list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->segs.p, h->hsegs.p, list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
     Ctx<DT> c{};
     c.data = (Elem*)d_data;
     double elems = 0;
@@ -758,7 +783,7 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
         if (rc) return rc;
     }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
-    HIP_TRY(hipStreamSynchronize(st));   // the host list must outlive the copy
+    HIP_TRY(hipStreamSynchronize(st));   // the staged list must outlive the copy
     if (log_enabled()) {
         uint32_t nf[2] = {0, 0};
         HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
@@ -1072,6 +1097,7 @@ void ips4o_destroy(ips4o_handle* h) {
     h->scratch.release();
     h->rflag.release();
     h->hbounds.release();
+    h->hsegs.release();
     delete h;
 }
 

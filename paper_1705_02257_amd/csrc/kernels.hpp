@@ -957,26 +957,30 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
 }
 
 // ------------------------------------------------------ empty-block fix
-// One workgroup per bucket slot.  Within the bucket's block range
+// One workgroup per bucket (grid: bucket, task from task0; NSMAX bounds the
+// stripes of a task).  Within the bucket's block range
 // [d_i, d_{i+1}) the stripes contribute runs "full, then empty".  Count the
 // full blocks occ; the first occ positions must all be full: the empty ones
 // among them ("holes") receive, in order, the full blocks found at or after
 // d_i + occ ("stragglers"), as in Appendix A.  Then w_i = d_i and
 // r_i = d_i + occ - 1.
-template <int DT, int NT>
-__global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
+template <int DT, int NT, int NSMAX>
+__global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c, uint32_t task0) {
     using Elem = typename Traits<DT>::Elem;
     using Word = typename Traits<DT>::Word;
-    __shared__ uint32_t hpre[STRIPES_PER_TASK_MAX + 1];
-    __shared__ uint32_t spre[STRIPES_PER_TASK_MAX + 1];
-    __shared__ uint32_t occpre[STRIPES_PER_TASK_MAX + 1];
+    __shared__ uint32_t hpre[NSMAX + 1];
+    __shared__ uint32_t spre[NSMAX + 1];
+    __shared__ uint32_t occpre[NSMAX + 1];
     __shared__ uint32_t sh[NT / 64 + 1];
-    const uint32_t g = blockIdx.x;
-    const uint32_t t = upper_find(c.ntasks, g, [&](uint32_t i) { return (uint64_t)c.tasks[i].slot_begin; });
+    const uint32_t t = task0 + blockIdx.y;
     const TaskD td = c.tasks[t];
-    const uint32_t j = g - td.slot_begin;
+    const uint32_t j = blockIdx.x;
     const uint32_t K = c.ts[t].K;
     if (j >= K) return;
+    if (td.nstripes > NSMAX) {                  // the launch chose the wrong variant
+        if (threadIdx.x == 0) raise_err(c.err, ERR_FIX);
+        return;
+    }
     const uint32_t b = c.b;
     const uint32_t* dl = c.delim + td.slot_begin + t;
     const uint32_t d0 = dl[j], d1 = dl[j + 1];
@@ -1043,7 +1047,20 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c) {
         }
         Word* dw = reinterpret_cast<Word*>(seg + (uint64_t)dst_blk * b);
         const Word* sw = reinterpret_cast<const Word*>(seg + (uint64_t)src_blk * b);
-        for (uint32_t i = lane; i < words; i += 64) dw[i] = sw[i];
+        // eight words per lane in flight: all loads of a chunk before its stores
+        for (uint32_t i0 = 0; i0 < words; i0 += 8 * 64) {
+            Word tmp[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t i = i0 + u * 64 + lane;
+                if (i < words) tmp[u] = sw[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t i = i0 + u * 64 + lane;
+                if (i < words) dw[i] = tmp[u];
+            }
+        }
     }
     // In-place prefix: the first full blocks of the range may hold bucket j
     // already (presorted inputs; a bucket that holds the whole task).  They

@@ -1216,19 +1216,20 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
         // inputs it piles every worker onto the same few buckets.)
         bool got = false;
         uint32_t destA = 0;
-        for (uint32_t scanned = 0; !got && scanned < K;) {
-            // look at 64 buckets at once, starting at p
+        for (uint32_t scanned = 0, width = 1; !got && scanned < K; width = 64) {
+            // look at the primary bucket first, then at 64 buckets at once
+            // (each look reads a slot's cache line)
             uint32_t q = p + lane;
             if (q >= K) q -= K;
             bool cand = false;
-            if (scanned + lane < K) {
+            if (lane < width && scanned + lane < K) {
                 uint64_t v = atom_load64(&sl[q].wr);
                 int64_t w = (int64_t)(v >> 32), r = (int64_t)(v & 0xffffffffull) - 0x80000000ll;
                 cand = r >= w;
             }
             uint64_t mask = __ballot(cand);
             if (mask == 0) {
-                uint32_t adv = (K - scanned) < 64 ? (K - scanned) : 64;
+                uint32_t adv = (K - scanned) < width ? (K - scanned) : width;
                 scanned += adv;
                 p += adv;
                 if (p >= K) p -= K;

@@ -1603,7 +1603,8 @@ __device__ inline uint64_t item_lead(const KeyIdx<Key>& it) { return lead_word(i
 
 // LDS layout of the base case: the items first (CAP of them for the
 // counting sort; CAP + CAP/VT + VT padded slots for the merge sort), then
-// either the 2^(log2 CAP - 1) digit counters or the merge-path starts.
+// either the digit counters (RADIX words holding 2*RADIX = CAP 16-bit
+// counters) or the merge-path starts.
 template <int DT, int NT, int VT>
 struct BaseLds {
     using It = typename BaseItem<DT>::T;
@@ -1623,12 +1624,12 @@ struct BaseLds {
 // Counting sort of each listed segment (at most NT*VT elements) inside one
 // workgroup's LDS, on the top bits of the leading word: every thread holds
 // VT items in registers; the span [lo, hi] of their leading words is split
-// into 2^(log2 CAP - 1) equal digit ranges, an LDS atomic per item counts
-// its digit (and returns its rank in it), and after an exclusive scan each
-// item goes to its digit's group.  Groups hold about two items; each item's
-// final place is the group start plus the number of group members that
-// precede it (smaller, or equal and placed earlier).  A segment whose keys
-// are all equal is left as it is.  Segments whose items crowd into a few
+// into 2^(log2 CAP) equal digit ranges (16-bit counters, two per LDS word),
+// an LDS atomic per item counts its digit (and returns its rank in it), and
+// after an exclusive scan each item goes to its digit's group.  Groups hold
+// about one item; each item's final place is the group start plus the
+// number of group members that precede it (smaller, or equal and placed
+// earlier).  A segment whose keys are all equal is left as it is.  Segments whose items crowd into a few
 // digits (a group of more than 64, or records with one leading word) are
 // left untouched and appended to `fail` for k_basecase (merge sort).
 template <int DT, int NT, int VT>
@@ -1641,7 +1642,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     using It = typename BI::T;
     using LB = BaseLds<DT, NT, VT>;
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
-    constexpr uint32_t RADIX = LB::RADIX, GMAX = 64, NW = NT / 64;
+    // 2*RADIX digits with 16-bit counters, two to a word (counts and
+    // offsets stay below 2^16)
+    constexpr uint32_t RADIX = LB::RADIX, NDIG = 2 * RADIX, GMAX = 64, NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     It* items = reinterpret_cast<It*>(smem_raw);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);
@@ -1650,6 +1653,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // array, which is free until the items are scattered into it
     uint32_t* scan_sh = reinterpret_cast<uint32_t*>(smem_raw);
     uint32_t* gmax_sh = scan_sh + 32;
+    auto digit_start = [&](uint32_t d) { return (cnt[d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
     // u64/f64: the next bin's keys are loaded before this bin is written
@@ -1713,14 +1717,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (radix) {
             const uint64_t span = hi - lo;
             const uint32_t bits = 64u - (uint32_t)__clzll(span);
-            const uint32_t sh = bits > LB::LOG_CAP - 1 ? bits - (LB::LOG_CAP - 1) : 0u;
-            for (uint32_t q = tid; q < RADIX; q += NT) cnt[q] = 0;
+            const uint32_t sh = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
+            for (uint32_t q = tid; q < RADIX; q += NT) cnt[q] = 0;            // NDIG 16-bit counters
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {
                     const uint32_t d = (uint32_t)((item_lead(x[v]) - lo) >> sh);
-                    dr[v] = d | (atomicAdd(&cnt[d], 1u) << 16);
+                    const uint32_t hs = (d & 1u) * 16u;
+                    const uint32_t old = atomicAdd(&cnt[d >> 1], 1u << hs);
+                    dr[v] = d | (((old >> hs) & 0xffffu) << 16);
                 }
             }
             __syncthreads();
@@ -1730,15 +1736,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
             for (uint32_t q = 0; q < PERC; ++q) {
                 cv[q] = cnt[tid * PERC + q];
-                loc += cv[q];
-                gm = cv[q] > gm ? cv[q] : gm;
+                const uint32_t c0 = cv[q] & 0xffffu, c1 = cv[q] >> 16;
+                loc += c0 + c1;
+                gm = max(gm, max(c0, c1));
             }
             uint32_t total;
             uint32_t pre = block_excl_scan<NT>(loc, scan_sh, &total);
 #pragma unroll
             for (uint32_t q = 0; q < PERC; ++q) {
-                cnt[tid * PERC + q] = pre;
-                pre += cv[q];
+                const uint32_t p0 = pre, p1 = pre + (cv[q] & 0xffffu);
+                cnt[tid * PERC + q] = p0 | (p1 << 16);
+                pre = p1 + (cv[q] >> 16);
             }
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) {
@@ -1756,13 +1764,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             // each item to its group; then to its place inside the group
 #pragma unroll
             for (int v = 0; v < VT; ++v)
-                if (v * NT + tid < len) items[cnt[dr[v] & 0xffffu] + (dr[v] >> 16)] = x[v];
+                if (v * NT + tid < len) items[digit_start(dr[v] & 0xffffu) + (dr[v] >> 16)] = x[v];
             __syncthreads();
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {
                     const uint32_t d = dr[v] & 0xffffu;
-                    const uint32_t g0 = cnt[d], g1 = d + 1 < RADIX ? cnt[d + 1] : len;
+                    const uint32_t g0 = digit_start(d), g1 = d + 1 < NDIG ? digit_start(d + 1) : len;
                     const uint32_t pos = g0 + (dr[v] >> 16);
                     uint32_t rank = 0;
                     for (uint32_t j = g0; j < g1; ++j) {

@@ -29,6 +29,8 @@ namespace {
 
 constexpr uint32_t kDefaultK = 256;
 constexpr size_t kStatsOffset = 1024;        // misc: error word at 0, level counters here
+constexpr uint32_t kStatLevels = 16;         // levels with counters of their own (deeper ones share the last)
+constexpr size_t kStatsBytes = 32 * 64;      // one level's counters (STAT_SPREAD cache lines)
 constexpr uint32_t kDefaultBlockBytes = 2048;
 constexpr uint32_t kMaxBlockBytes = 8192;
 constexpr uint64_t kDefaultSeed = 0x1705022570ull;
@@ -126,12 +128,17 @@ enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_B
 struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
-    Arena work;       // per-level workspace
+    Arena work;       // per-level workspace (even levels)
+    Arena work2;      // per-level workspace (odd levels: planned while the previous level runs)
     Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
     Arena rflag;      // permutation read marks, one word per block of the array
-    HostArena hbounds;    // pinned copy of a level's bucket bounds
+    HostArena hbounds;    // pinned copy of a level's error word, task state and bounds (even levels)
+    HostArena hbounds2;   // the same for odd levels
+    HostArena hdesc;      // pinned staging of a level's descriptors (even levels)
+    HostArena hdesc2;     // the same for odd levels
+    hipEvent_t scanned[2] = {nullptr, nullptr};   // a level's bounds have reached the host
     HostArena hsegs;      // pinned staging of the base-case bin list
     uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
@@ -399,6 +406,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             L.stripes.push_back(sd);
         }
         uint64_t w = (uint64_t)std::llround((double)R.workers * (double)nb / (double)total_blocks);
+        w = std::min<uint64_t>(w, nb);              // no more workers than blocks
         w = std::max<uint64_t>(4, (w + 3) & ~3ull);
         t.worker_begin = wk;
         t.nworkers = (uint32_t)w;
@@ -451,7 +459,7 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
 }
 
 template <int DT>
-void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolved& R) {
+void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolved& R, uint32_t level = 0) {
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     const size_t T = L.tasks.size(), S = L.stripes.size();
@@ -475,7 +483,7 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolve
     c.nstripes = (uint32_t)S;
     char* m = (char*)misc;
     c.err = (uint32_t*)m;
-    c.stats = (unsigned long long*)(m + kStatsOffset);
+    c.stats = (unsigned long long*)(m + kStatsOffset + std::min(level, kStatLevels - 1) * kStatsBytes);
     c.b = R.b;
     c.spin_limit = R.spin;
     c.total_workers = L.total_workers;
@@ -516,17 +524,36 @@ struct LevelMarks {    // timer records whose byte counts are known after the le
     int fix = -1, permute = -1, cleanup = -1;
 };
 
+// First half of a level: descriptors, sampling, classification, bounds.
+// With `stage` the descriptors go through that pinned buffer, so the copies
+// do not wait for earlier work on the stream (the buffer must not be
+// reused before they ran).
 template <int DT>
-int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
-              LevelMarks& mk, bool check) {
+int launch_level_head(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
+                      bool check, HostArena* stage) {
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     constexpr int CNT = Shape<DT>::CNT, EPT = Shape<DT>::EPT;
     Ctx<DT>& c = L.c;
     const size_t T = L.tasks.size(), S = L.stripes.size();
-    HIP_TRY(hipMemcpyAsync((void*)c.tasks, L.tasks.data(), T * sizeof(TaskD), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync((void*)c.stripes, L.stripes.data(), S * sizeof(StripeD), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync((void*)c.order, L.order.data(), S * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    const void* src_tasks = L.tasks.data();
+    const void* src_stripes = L.stripes.data();
+    const void* src_order = L.order.data();
+    if (stage) {
+        const size_t bt = T * sizeof(TaskD), bs = S * sizeof(StripeD), bo = S * sizeof(uint32_t);
+        int rc = stage->ensure(bt + bs + bo);
+        if (rc) return rc;
+        char* p = (char*)stage->p;
+        std::memcpy(p, L.tasks.data(), bt);
+        std::memcpy(p + bt, L.stripes.data(), bs);
+        std::memcpy(p + bt + bs, L.order.data(), bo);
+        src_tasks = p;
+        src_stripes = p + bt;
+        src_order = p + bt + bs;
+    }
+    HIP_TRY(hipMemcpyAsync((void*)c.tasks, src_tasks, T * sizeof(TaskD), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)c.stripes, src_stripes, S * sizeof(StripeD), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync((void*)c.order, src_order, S * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (given) {
         HIP_TRY(hipMemcpyAsync(c.tree, given->tree.data(), given->tree.size() * sizeof(Key), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
@@ -554,6 +581,14 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     hipLaunchKernelGGL((k_scan<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
     HIP_TRY(hipGetLastError());
     tm.end(r, 0.0);
+    return IPS4O_OK;
+}
+
+// Second half of a level: empty-block fix, block permutation, cleanup.
+template <int DT>
+int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, LevelMarks& mk, bool check) {
+    Ctx<DT>& c = L.c;
+    const uint32_t T = (uint32_t)L.tasks.size();
     mk.fix = tm.begin(KK_FIX);
     {
         // one workgroup per bucket: 16 waves when tasks have many stripes
@@ -610,6 +645,14 @@ int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>*
     return IPS4O_OK;
 }
 
+template <int DT>
+int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
+              LevelMarks& mk, bool check) {
+    int rc = launch_level_head<DT>(h, L, st, given, tm, check, nullptr);
+    if (rc) return rc;
+    return launch_level_tail<DT>(h, L, st, tm, mk, check);
+}
+
 // bytes of the launches whose amount of work is counted on the device
 template <int DT>
 void account_level(Timer& tm, const LevelMarks& mk, const unsigned long long* now,
@@ -632,9 +675,10 @@ int check_device_error(ips4o_handle* h, hipStream_t st) {
 }
 
 int reset_misc(ips4o_handle* h, hipStream_t st) {
-    int rc = h->misc.ensure(4096);
+    static_assert(kStatsBytes == STAT_SPREAD * 64, "counter block size");
+    int rc = h->misc.ensure(kStatsOffset + kStatLevels * kStatsBytes);
     if (rc) return rc;
-    HIP_TRY(hipMemsetAsync(h->misc.p, 0, kStatsOffset + STAT_SPREAD * 64, st));
+    HIP_TRY(hipMemsetAsync(h->misc.p, 0, kStatsOffset + kStatLevels * kStatsBytes, st));
     return IPS4O_OK;
 }
 
@@ -793,6 +837,26 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     return IPS4O_OK;
 }
 
+// Copies of a level's error word, task state and bounds into pinned memory,
+// enqueued right after its scan; `ev` fires when they have arrived.
+template <int DT>
+int enqueue_readback(ips4o_handle* h, Level<DT>& L, HostArena& dst, hipEvent_t ev, hipStream_t st) {
+    const size_t T = L.tasks.size(), nb = L.total_slots + T;
+    int rc = dst.ensure(256 + T * sizeof(TaskS) + nb * sizeof(uint64_t));
+    if (rc) return rc;
+    char* p = (char*)dst.p;
+    HIP_TRY(hipMemcpyAsync(p, h->misc.p, 256, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(p + 256, L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(p + 256 + T * sizeof(TaskS), L.c.bounds, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(ev, st));
+    return IPS4O_OK;
+}
+
+// The recursion.  A level's bounds are read back as soon as its scan is
+// done; while its permutation and cleanup still run, the host turns them
+// into the next level's plan (or the base-case bins) and enqueues that
+// work behind them.  Levels alternate between two workspaces, so the one a
+// new level takes was last used two levels before, which has finished.
 template <int DT>
 int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, hipStream_t st) {
     Resolved R;
@@ -802,6 +866,8 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     if (n <= 1) return IPS4O_OK;
     rc = reset_misc(h, st);
     if (rc) return rc;
+    for (hipEvent_t& e : h->scanned)
+        if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     std::vector<SegD> base;
     std::vector<Seg> cur;
     if (n <= R.cap) {
@@ -810,56 +876,68 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     }
     else cur.push_back(Seg{0, n});
     uint32_t level = 0;
-    Level<DT> L;
-    std::vector<TaskS> ts;
-    const uint64_t* bounds = nullptr;     // pinned, valid until the next level's readback
+    Level<DT> levels[2];
+    std::vector<LevelMarks> marks;
+    std::vector<uint32_t> level_tasks, level_stripes, level_workers;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
-    unsigned long long before[4] = {0, 0, 0, 0};
+    const bool check = (R.flags & IPS4O_FLAG_CHECK) != 0;
     while (!cur.empty()) {
         if (level >= kMaxLevels) return IPS4O_ERR_DEVICE_FAULT;
+        const int par = (int)(level & 1);
+        Level<DT>& L = levels[par];
+        Arena& work = par ? h->work2 : h->work;
+        HostArena& rb = par ? h->hbounds2 : h->hbounds;
         plan_level<DT>(L, cur, R, level, level == 0, 0);
-        rc = h->work.ensure(level_bytes<DT>(L, R.b));
+        rc = work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
-        carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+        carve_level<DT>(L, work.p, h->misc.p, d_data, R, level);
         rc = prepare_rflag<DT>(h, L, n, R.b, st);
         if (rc) return rc;
-        LevelMarks mk;
-        rc = run_level<DT>(h, L, st, nullptr, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
+        marks.emplace_back();
+        rc = launch_level_head<DT>(h, L, st, nullptr, tm, check, par ? &h->hdesc2 : &h->hdesc);
         if (rc) return rc;
-        unsigned long long stats[4] = {0, 0, 0, 0};
-        const auto hr0 = std::chrono::steady_clock::now();
-        rc = read_level<DT>(h, L, st, ts, bounds, stats);
-        const auto hr1 = std::chrono::steady_clock::now();
-        if (log_enabled())
-            std::fprintf(stderr, "[ips4o] level %u readback %.3f ms\n", level,
-                         std::chrono::duration<double, std::milli>(hr1 - hr0).count());
+        rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
         if (rc) return rc;
-        account_level<DT>(tm, mk, stats, before, R.b);
-        for (int q = 0; q < 4; ++q) before[q] = stats[q];
-        if (log_enabled()) {
-            std::fprintf(stderr, "[ips4o] level %u: %zu tasks, %zu stripes, %u workers, moves %llu skips %llu\n",
-                         level, L.tasks.size(), L.stripes.size(), L.total_workers, stats[0], stats[1]);
-            for (size_t t = 0; t < L.tasks.size() && t < 64; ++t) {
-                const TaskD& td = L.tasks[t];
-                std::fprintf(stderr, "[ips4o]   task %zu off %llu m %llu k %u alpha %u K %u eq %u stripes %u\n", t,
-                             (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, ts[t].K,
-                             ts[t].eq, td.nstripes);
-            }
+        rc = launch_level_tail<DT>(h, L, st, tm, marks.back(), check);
+        if (rc) return rc;
+        level_tasks.push_back((uint32_t)L.tasks.size());
+        level_stripes.push_back((uint32_t)L.stripes.size());
+        level_workers.push_back(L.total_workers);
+        for (const Seg& sg : cur) h->last.elements_distributed += sg.m;
+        // ---- the bounds are on the host once the scan has run
+        HIP_TRY(hipEventSynchronize(h->scanned[par]));
+        const char* rp = (const char*)rb.p;
+        const size_t T = L.tasks.size();
+        if (((const uint32_t*)rp)[0] != 0) {        // a fault so far: no plan from these bounds
+            (void)check_device_error(h, st);
+            return IPS4O_ERR_DEVICE_FAULT;
         }
-        h->last.block_moves = stats[0];
-        h->last.block_skips = stats[1];
-        for (const Seg& s : cur) h->last.elements_distributed += s.m;
+        const TaskS* ts = (const TaskS*)(rp + 256);
+        const uint64_t* bounds = (const uint64_t*)(rp + 256 + T * sizeof(TaskS));
         std::vector<Seg> next;
         const size_t first_bin = base.size();
         base.reserve(base.size() + L.total_slots);
-        for (size_t t = 0; t < L.tasks.size(); ++t) {
+        for (size_t t = 0; t < T; ++t) {
             const TaskD& td = L.tasks[t];
             const uint64_t* bd = bounds + td.slot_begin + t;
-            for (uint32_t i = 0; i < ts[t].K; ++i) {
-                uint64_t sz = bd[i + 1] - bd[i];
+            const uint32_t K = ts[t].K;
+            if (K == 0 || K > (uint32_t)KMAX || bd[0] != 0 || bd[K] != td.m) {
+                (void)check_device_error(h, st);
+                return IPS4O_ERR_DEVICE_FAULT;
+            }
+            if (log_enabled() && t < 64)
+                std::fprintf(stderr, "[ips4o]   level %u task %zu off %llu m %llu k %u alpha %u K %u eq %u stripes %u\n",
+                             level, t, (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, K,
+                             ts[t].eq, td.nstripes);
+            for (uint32_t i = 0; i < K; ++i) {
+                if (bd[i + 1] < bd[i]) {
+                    (void)check_device_error(h, st);
+                    return IPS4O_ERR_DEVICE_FAULT;
+                }
+                const uint64_t sz = bd[i + 1] - bd[i];
                 if (sz <= 1) continue;
                 if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
-                uint64_t off = td.off + bd[i];
+                const uint64_t off = td.off + bd[i];
                 if (sz <= R.cap) {
                     add_to_bins(base, first_bin, off, sz, std::min(R.cap, small_bin_cap<DT>()));
                     h->last.elements_base += sz;
@@ -867,20 +945,30 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
                 else next.push_back(Seg{off, sz});
             }
         }
-        if (log_enabled())
-            std::fprintf(stderr, "[ips4o] level %u host planning %.3f ms\n", level,
-                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - hr1).count());
         cur.swap(next);
         ++level;
     }
     h->last.levels = level;
-    const auto hb0 = std::chrono::steady_clock::now();
-    rc = run_basecase<DT>(h, d_data, base, R, st, tm);
-    if (log_enabled())
-        std::fprintf(stderr, "[ips4o] base case: %zu bins, %.3f ms including the kernels\n", base.size(),
-                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - hb0).count());
+    rc = run_basecase<DT>(h, d_data, base, R, st, tm);       // ends with a stream synchronize
     if (rc) return rc;
     rc = check_device_error(h, st);
+    // per-level counters: block moves, skips, cleanup and fix element counts
+    std::vector<unsigned long long> cnt(kStatLevels * kStatsBytes / 8);
+    HIP_TRY(hipMemcpy(cnt.data(), (char*)h->misc.p + kStatsOffset, kStatLevels * kStatsBytes, hipMemcpyDeviceToHost));
+    for (uint32_t l = 0; l < level; ++l) {
+        unsigned long long now[4] = {0, 0, 0, 0}, zero[4] = {0, 0, 0, 0};
+        if (l < kStatLevels) {
+            const unsigned long long* blk = cnt.data() + (size_t)l * kStatsBytes / 8;
+            for (int q = 0; q < 4; ++q)
+                for (int r = 0; r < STAT_SPREAD; ++r) now[q] += blk[r * 8 + q];
+        }
+        account_level<DT>(tm, marks[l], now, zero, R.b);
+        h->last.block_moves += now[0];
+        h->last.block_skips += now[1];
+        if (log_enabled())
+            std::fprintf(stderr, "[ips4o] level %u: %u tasks, %u stripes, %u workers, moves %llu skips %llu\n", l,
+                         level_tasks[l], level_stripes[l], level_workers[l], now[0], now[1]);
+    }
     tm.finish();
     return rc;
 }
@@ -1092,6 +1180,12 @@ void ips4o_destroy(ips4o_handle* h) {
     (void)hipSetDevice(h->device);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->work.release();
+    h->work2.release();
+    h->hbounds2.release();
+    h->hdesc.release();
+    h->hdesc2.release();
+    for (hipEvent_t& e : h->scanned)
+        if (e) (void)hipEventDestroy(e);
     h->misc.release();
     h->segs.release();
     h->scratch.release();
@@ -1103,7 +1197,7 @@ void ips4o_destroy(ips4o_handle* h) {
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
     if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
-    *bytes = h->work.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
+    *bytes = h->work.bytes + h->work2.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes + h->rflag.bytes;
     return IPS4O_OK;
 }
 

@@ -69,16 +69,18 @@ struct TaskS {                  // device-written per task
     uint32_t pad0, pad1;
 };
 
-// Per-bucket permutation state, one 256-byte slot per bucket so that the
-// atomics of different buckets land on different cache lines and channels.
-struct alignas(256) BucketSlot {
+// Per-bucket permutation state, one 64-byte slot per bucket: the atomics of
+// two buckets share at most a cache line, and a worker's scan over 64
+// buckets reads 4 KiB (wider slots made the scans of levels with many
+// buckets a large part of the permutation's memory traffic).
+struct alignas(64) BucketSlot {
     uint64_t wr;        // (w << 32) | (r + 2^31), block indices in the segment
     uint32_t unused;
     uint32_t flag;      // unused
     uint32_t rinit;     // r at the start of the permutation (last full block)
-    uint32_t pad[59];
+    uint32_t pad[11];
 };
-static_assert(sizeof(BucketSlot) == 256, "bucket slot size");
+static_assert(sizeof(BucketSlot) == 64, "bucket slot size");
 
 template <int DT>
 struct Ctx {

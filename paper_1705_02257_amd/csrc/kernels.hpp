@@ -1650,11 +1650,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     extern __shared__ __align__(16) unsigned char smem_raw[];
     It* items = reinterpret_cast<It*>(smem_raw);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);
-    uint64_t* red = reinterpret_cast<uint64_t*>(smem_raw + LB::counters_at);     // before cnt is used
-    // scan and maximum scratch of the counting sort: the start of the item
-    // array, which is free until the items are scattered into it
+    // reduction, scan and maximum scratch: the start of the item array,
+    // which is free until the items are scattered into it
     uint32_t* scan_sh = reinterpret_cast<uint32_t*>(smem_raw);
     uint32_t* gmax_sh = scan_sh + 32;
+    uint64_t* red = reinterpret_cast<uint64_t*>(smem_raw + 256);
     auto digit_start = [&](uint32_t d) { return (cnt[d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     Elem* scr = scratch + (uint64_t)blockIdx.x * (NT * VT);
@@ -1704,6 +1704,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             hi = h2 > hi ? h2 : hi;
         }
         if (lane == 0) { red[2 * wid] = lo; red[2 * wid + 1] = hi; }
+        for (uint32_t q = tid; q < RADIX; q += NT) cnt[q] = 0;            // NDIG 16-bit counters
         __syncthreads();
         lo = red[0];
         hi = red[1];
@@ -1711,7 +1712,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             lo = red[2 * w] < lo ? red[2 * w] : lo;
             hi = red[2 * w + 1] > hi ? red[2 * w + 1] : hi;
         }
-        __syncthreads();
         // all keys equal: already sorted; records with one leading word: merge sort
         bool radix = lo != hi;
         bool sorted = false;
@@ -1720,8 +1720,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const uint64_t span = hi - lo;
             const uint32_t bits = 64u - (uint32_t)__clzll(span);
             const uint32_t sh = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
-            for (uint32_t q = tid; q < RADIX; q += NT) cnt[q] = 0;            // NDIG 16-bit counters
-            __syncthreads();
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {
@@ -1734,10 +1732,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             __syncthreads();
             // exclusive scan of the counters; largest group
             constexpr uint32_t PERC = RADIX / NT;
+            static_assert(PERC % 4 == 0, "counter words per thread");
             uint32_t cv[PERC], loc = 0, gm = 0;
+            uint4* cnt4 = reinterpret_cast<uint4*>(cnt) + tid * (PERC / 4);
+#pragma unroll
+            for (uint32_t q = 0; q < PERC / 4; ++q) {
+                const uint4 w4 = cnt4[q];
+                cv[4 * q] = w4.x; cv[4 * q + 1] = w4.y; cv[4 * q + 2] = w4.z; cv[4 * q + 3] = w4.w;
+            }
 #pragma unroll
             for (uint32_t q = 0; q < PERC; ++q) {
-                cv[q] = cnt[tid * PERC + q];
                 const uint32_t c0 = cv[q] & 0xffffu, c1 = cv[q] >> 16;
                 loc += c0 + c1;
                 gm = max(gm, max(c0, c1));
@@ -1746,10 +1750,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             uint32_t pre = block_excl_scan<NT>(loc, scan_sh, &total);
 #pragma unroll
             for (uint32_t q = 0; q < PERC; ++q) {
-                const uint32_t p0 = pre, p1 = pre + (cv[q] & 0xffffu);
-                cnt[tid * PERC + q] = p0 | (p1 << 16);
-                pre = p1 + (cv[q] >> 16);
+                const uint32_t c0 = cv[q] & 0xffffu, c1 = cv[q] >> 16;
+                const uint32_t p0 = pre, p1 = pre + c0;
+                cv[q] = p0 | (p1 << 16);
+                pre = p1 + c1;
             }
+#pragma unroll
+            for (uint32_t q = 0; q < PERC / 4; ++q)
+                cnt4[q] = make_uint4(cv[4 * q], cv[4 * q + 1], cv[4 * q + 2], cv[4 * q + 3]);
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) {
                 const uint32_t o = __shfl_xor(gm, d, 64);

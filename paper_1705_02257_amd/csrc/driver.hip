@@ -417,18 +417,21 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         treeb += k;
         L.tasks.push_back(t);
     }
-    // classification launch order: largest stripes first, so that the
+    // classification launch order: longest stripes first, so that the
     // workgroups dispatched last are the short ones (longest processing
-    // time first)
+    // time first).  A stripe's cost is its length plus about twice its
+    // head of 2k blocks, which is copied aside and then goes through the
+    // partial buffers.
     L.order.resize(L.stripes.size());
     for (size_t q = 0; q < L.order.size(); ++q) L.order[q] = (uint32_t)q;
-    auto stripe_len = [&](uint32_t q) {
+    auto stripe_cost = [&](uint32_t q) {
         const StripeD& sd = L.stripes[q];
-        const uint64_t e = std::min<uint64_t>((uint64_t)sd.blk_end * b, L.tasks[sd.task].m);
-        return e - (uint64_t)sd.blk_begin * b;
+        const TaskD& td = L.tasks[sd.task];
+        const uint64_t e = std::min<uint64_t>((uint64_t)sd.blk_end * b, td.m) - (uint64_t)sd.blk_begin * b;
+        return e + 2 * std::min<uint64_t>(e, (uint64_t)td.k * b);
     };
     std::stable_sort(L.order.begin(), L.order.end(),
-                     [&](uint32_t x, uint32_t y) { return stripe_len(x) > stripe_len(y); });
+                     [&](uint32_t x, uint32_t y) { return stripe_cost(x) > stripe_cost(y); });
     L.total_slots = slot;
     L.total_tree = treeb;
     L.total_workers = wk;

@@ -27,15 +27,18 @@
  * 4 bytes for BYTES100.  The caller owns all arrays it passes.
  *
  * Streams: `hip_stream` is a hipStream_t (NULL = the null stream).  Work is
- * enqueued on that stream.  The calls read per-level results back to the
- * host (the recursion is planned on the host) or copy host arguments, so
- * they synchronize the stream before returning.
+ * enqueued on that stream.  The recursion is planned on the host: a level's
+ * bucket bounds are copied back as soon as they exist and the next level is
+ * enqueued while the current one still runs; every call synchronizes the
+ * stream before it returns.  A handle serves one call at a time (it owns
+ * the workspace and pinned staging buffers); use one handle per host thread.
  *
  * Errors: every call validates its arguments before touching the device and
  * returns IPS4O_OK (0) or a negative status (ips4o_status_string describes
- * it).  n = 0 and n = 1 are valid no-ops.  After IPS4O_ERR_DEVICE_FAULT (a
- * bounded wait inside a kernel ran out) the contents of the array are
- * undefined: blocks held in flight by the permutation may be lost.
+ * it).  n = 0 and n = 1 are valid no-ops.  IPS4O_ERR_DEVICE_FAULT means a
+ * kernel detected an inconsistent state (a bounded wait ran out, counts that
+ * do not add up, bucket bounds out of range); the contents of the array are
+ * then undefined: blocks held in flight by the permutation may be lost.
  */
 #ifndef IPS4O_H
 #define IPS4O_H
@@ -52,7 +55,7 @@ extern "C" {
 #define IPS4O_ERR_OUT_OF_MEMORY    -2  /* workspace allocation failed */
 #define IPS4O_ERR_HIP              -3  /* a HIP runtime call failed */
 #define IPS4O_ERR_NOT_SUPPORTED    -4  /* device is not gfx950, or n too large */
-#define IPS4O_ERR_DEVICE_FAULT     -5  /* a kernel's bounded wait expired; data undefined */
+#define IPS4O_ERR_DEVICE_FAULT     -5  /* a kernel found an inconsistent state; data undefined */
 
 typedef enum {
     IPS4O_U64 = 0,

@@ -1299,7 +1299,7 @@ const char* ips4o_status_string(int status) {
     case IPS4O_ERR_OUT_OF_MEMORY: return "out of device memory";
     case IPS4O_ERR_HIP: return "HIP runtime error";
     case IPS4O_ERR_NOT_SUPPORTED: return "not supported (device is not gfx950, or n too large)";
-    case IPS4O_ERR_DEVICE_FAULT: return "device fault: a bounded wait expired; data undefined";
+    case IPS4O_ERR_DEVICE_FAULT: return "device fault: a kernel found an inconsistent state; data undefined";
     }
     return "unknown status";
 }

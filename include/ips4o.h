@@ -83,7 +83,8 @@ typedef enum {
  *   seed        sampling seed (default a fixed constant).
  *   flags       IPS4O_FLAG_* bits.
  *   spin_limit  iterations a kernel may wait for another workgroup before it
- *               reports IPS4O_ERR_DEVICE_FAULT (default 2^26). */
+ *               reports IPS4O_ERR_DEVICE_FAULT (default 2^16, about 0.1 s;
+ *               a legitimate wait lasts microseconds). */
 typedef struct {
     uint32_t k;
     uint32_t block_bytes;

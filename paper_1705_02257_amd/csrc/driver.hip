@@ -34,8 +34,9 @@ constexpr size_t kStatsBytes = 32 * 64;      // one level's counters (STAT_SPREA
 constexpr uint32_t kDefaultBlockBytes = 2048;
 constexpr uint32_t kMaxBlockBytes = 8192;
 constexpr uint64_t kDefaultSeed = 0x1705022570ull;
-constexpr uint32_t kDefaultSpin = 1u << 26;
+constexpr uint32_t kDefaultSpin = 1u << 16;      // waits last microseconds; this is about 0.1 s
 constexpr uint32_t kMaxLevels = 48;
+constexpr uint64_t kStripeBlocksMax = 256 * 1024 - 2048;   // blocks per classification stripe
 constexpr uint32_t kLevelStripes = 512;      // classification workgroups per level
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
@@ -393,6 +394,9 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         uint64_t by_size = nb / (8ull * k);
         uint64_t ns = std::max<uint64_t>(1, std::min(by_size, share[i]));
         if (first && R.stripes) ns = R.stripes;
+        // the classification's block lists fit its LDS for stripes of up
+        // to kStripeBlocksMax blocks
+        ns = std::max<uint64_t>(ns, (nb + kStripeBlocksMax - 1) / kStripeBlocksMax);
         ns = std::min<uint64_t>(ns, std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
         t.stripe_begin = (uint32_t)L.stripes.size();
         t.nstripes = (uint32_t)ns;

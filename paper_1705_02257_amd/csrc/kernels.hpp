@@ -485,25 +485,22 @@ __device__ inline void classify_lut_batch(const Key (&k)[EPT], uint32_t (&out)[E
 // One workgroup per stripe (Section 4.1).  The workgroup keeps one buffer
 // block of b elements per bucket; a full buffer block is a finished block of
 // the stripe.  To write every element only once, the buffer block a bucket is
-// filling ("open" block) lives inside the stripe at the write front, and a
-// full open block simply stays where it is.  Open blocks may be allocated
-// only where elements have already been read; the slack for the K open
-// blocks comes from first copying the stripe's first C = K*b elements to a
-// side area ("head"):
-//   phase 0  copy the head out;
-//   phase 1  tiles of NT*EPT elements after the head: classify in registers,
-//            counting-sort by bucket in LDS, write every element into its
-//            bucket's open block or into new blocks allocated at the write
-//            front (at most C + read elements are ever allocated);
+// filling ("open" block) is a slot of the stripe's block space, and a full
+// open block simply stays where it is.  Slots are numbered in allocation
+// order; the first K slots live in a side area of K blocks, slot s >= K is
+// stripe block s - K.  At most read/b + K slots are allocated after `read`
+// elements (one partly filled block per bucket), so a slot in the stripe
+// never lies beyond what has been read:
+//   phase 1  tiles of NT*EPT elements: classify in registers, counting-sort
+//            by bucket in LDS, write every element into its bucket's open
+//            block or into new slots allocated at the write front;
 //   phase 2  move the content of every partly filled open block to the
-//            bucket's partial buffer (its slot becomes a hole), then run the
-//            head through the classic buffer scheme: buffer blocks that fill
-//            up become full blocks placed into the holes first and then at
-//            the write front;
-//   phase 3  if holes remain, move the last full blocks into them, so the
-//            stripe ends as [full blocks | empty blocks] with the partial
-//            buffers outside it, exactly as the paper's local classification
-//            leaves it.
+//            bucket's partial buffer (its slot becomes a hole); then the
+//            full blocks outside stripe blocks [0, F) (those in the side
+//            area and those at or beyond F) move into the free stripe blocks
+//            below F, so the stripe ends as [F full blocks | empty blocks]
+//            with the partial buffers outside it, exactly as the paper's
+//            local classification leaves it.
 template <int DT, int NT, int EPT>
 struct ClassifyLds {
     using Elem = typename Traits<DT>::Elem;
@@ -657,20 +654,20 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     const uint64_t s_begin = (uint64_t)sd.blk_begin * b;
     const uint64_t s_end = ((uint64_t)sd.blk_end * b < td.m) ? (uint64_t)sd.blk_end * b : td.m;
     const uint32_t E = (uint32_t)(s_end - s_begin);         // stripe elements
-    const uint32_t C = E < (K << lb) ? E : (K << lb);       // head size
     Elem* sp = c.data + td.off + s_begin;                   // the stripe
     Elem* buf = c.bufs + sd.buf_off;                        // partial buffers, bucket j at j*b
-    Elem* head = buf + ((uint64_t)(2 * td.k) << lb);        // copy of the head
+    Elem* side = buf + ((uint64_t)(2 * td.k) << lb);        // slots 0 .. K-1
+    const int64_t KB = (int64_t)K << lb;
+    // element e of slot space (slot e >> lb) in memory
+    auto slot_elem = [&](int64_t e) -> Elem* { return e < KB ? side + e : sp + (e - KB); };
 
     for (uint32_t q = threadIdx.x; q < K; q += NT) {
         L.cnt[q] = 0; L.fill[q] = b; L.open[q] = 0; L.nfull[q] = 0;
     }
     if (threadIdx.x == 0) { L.wf = 0; L.nholes = 0; L.nalloc = 0; }
-    // ---- phase 0: the head goes to the side area
-    for (uint32_t i = threadIdx.x; i < C; i += NT) head[i] = sp[i];
     __syncthreads();
 
-    // ---- phase 1: the rest of the stripe, straight into open blocks.
+    // ---- phase 1: the stripe, straight into open blocks.
     // Full tiles take a path without per-element guards: straight-line
     // loads and stores let the compiler wait for exactly the loads it needs
     // instead of every outstanding memory operation.
@@ -739,20 +736,20 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
                 const uint32_t p = e * NT + threadIdx.x;
                 const uint32_t jb = L.ids[p];
                 const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
-                sp[d] = L.tile[p];
+                *slot_elem(d) = L.tile[p];
             }
         } else {
             for (uint32_t p = threadIdx.x; p < tn; p += NT) {
                 const uint32_t jb = L.ids[p];
                 const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
-                sp[d] = L.tile[p];
+                *slot_elem(d) = L.tile[p];
             }
         }
         for (uint32_t q = threadIdx.x; q < K; q += NT) L.cnt[q] = 0;
         lds_barrier();
     };
-    if (C < E) load_tile(sp, C, E);
-    uint32_t t0 = C;
+    load_tile(sp, 0, E);
+    uint32_t t0 = 0;
     {
         // steady state: the next tile is full too.  Its loads go to a second
         // register set at the start of the iteration; the body has no other
@@ -775,133 +772,81 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     }
     __syncthreads();        // phase 1's stores are read back in phase 2
 
-    // ---- phase 2: evacuate partly filled open blocks, then the head
+    // ---- phase 2: evacuate partly filled open blocks ...
     for (uint32_t jb = threadIdx.x; jb < K; jb += NT) {
         const uint32_t f = L.fill[jb];
         if (f < b) {
             L.holes[atomicAdd(&L.nholes, 1u)] = L.open[jb];
             L.nfull[jb] -= 1;               // that block is not full
         } else {
-            L.fill[jb] = 0;                 // partial buffer starts empty
+            L.fill[jb] = 0;                 // the partial buffer stays empty
         }
     }
     __syncthreads();
     for (uint32_t jb = wid; jb < K; jb += NT / 64) {
         const uint32_t f = L.fill[jb];
         if (f == 0) continue;
-        const Elem* src = sp + ((uint64_t)L.open[jb] << lb);
+        const Elem* src = slot_elem((int64_t)L.open[jb] << lb);
         Elem* dst = buf + ((uint64_t)jb << lb);
         for (uint32_t r = lane; r < f; r += 64) dst[r] = src[r];
     }
     __syncthreads();
-    const uint32_t O = L.nholes, wf1 = L.wf;
-    auto slot_of = [&](uint32_t a) -> uint32_t { return a < O ? L.holes[a] : wf1 + (a - O); };
-    if (C > 0) load_tile(head, 0, C);
-    for (uint32_t t0 = 0; t0 < C; t0 += TILE) {
-        const uint32_t tn = (C - t0) < TILE ? (C - t0) : TILE;
-        uint32_t bk[EPT], rk[EPT];
-        classify_rank<DT, NT, EPT, false>(L, x, tn, lkt, st, bk, rk);
-        __syncthreads();
-        {
-            const uint32_t na = L.nalloc;
-            uint64_t v[PER], loc = 0;
-#pragma unroll
-            for (uint32_t q = 0; q < PER; ++q) {
-                const uint32_t jb = threadIdx.x * PER + q;
-                v[q] = 0;
-                if (jb < K) {
-                    const uint32_t cn = L.cnt[jb];
-                    v[q] = ((uint64_t)((L.fill[jb] + cn) >> lb) << 32) | cn;
-                }
-                loc += v[q];
-            }
-            uint64_t total;
-            uint64_t pre = block_excl_scan64<NT>(loc, L.scan_sh, &total);
-#pragma unroll
-            for (uint32_t q = 0; q < PER; ++q) {
-                const uint32_t jb = threadIdx.x * PER + q;
-                if (jb < K) {
-                    L.off[jb] = (uint32_t)pre;
-                    L.abase[jb] = na + (uint32_t)(pre >> 32);
-                    pre += v[q];
-                }
-            }
-            if (threadIdx.x == 0) L.nalloc = na + (uint32_t)(total >> 32);
-        }
-        __syncthreads();
-        scatter_tile<DT, NT, EPT, false>(L, x, tn, bk, rk);
-        if (t0 + TILE < C) load_tile(head, t0 + TILE, C);
-        __syncthreads();
-        // buffered elements of buckets that complete a block go to the front
-        // of their first new block (one wavefront per bucket)
-        for (uint32_t jb = wid; jb < K; jb += NT / 64) {
-            const uint32_t f = L.fill[jb];
-            if (f == 0 || ((f + L.cnt[jb]) >> lb) == 0) continue;
-            Elem* dst = sp + ((uint64_t)slot_of(L.abase[jb]) << lb);
-            const Elem* src = buf + ((uint64_t)jb << lb);
-            for (uint32_t r = lane; r < f; r += 64) dst[r] = src[r];
-        }
-        __syncthreads();
-        for (uint32_t p = threadIdx.x; p < tn; p += NT) {
-            const uint32_t jb = L.ids[p];
-            const uint32_t f = L.fill[jb];
-            const uint32_t pos = f + (p - L.off[jb]);
-            const uint32_t nf = (f + L.cnt[jb]) >> lb;
-            const uint32_t blk = pos >> lb;
-            if (blk < nf) sp[((uint64_t)slot_of(L.abase[jb] + blk) << lb) + (pos & (b - 1))] = L.tile[p];
-            else buf[((uint64_t)jb << lb) + (pos - (nf << lb))] = L.tile[p];
-        }
-        __syncthreads();          // the loop above reads fill and cnt
-        for (uint32_t q = threadIdx.x; q < K; q += NT) {
-            const uint32_t tot = L.fill[q] + L.cnt[q];
-            L.nfull[q] += tot >> lb;
-            L.fill[q] = tot & (b - 1);
-            L.cnt[q] = 0;
-        }
-        __syncthreads();
+    // ... then every full block outside stripe blocks [0, F) moves into a
+    // free stripe block below F (scratch lists in the tile area)
+    const uint32_t wf1 = L.wf, O = L.nholes, F = wf1 - O;
+    __syncthreads();                                 // every wave has read wf and nholes
+    uint32_t* hole_bits = reinterpret_cast<uint32_t*>(L.tile);
+    const uint32_t nbits = (wf1 + 31) / 32;
+    // at most K full side slots plus O <= K full stripe blocks beyond F move
+    uint32_t* mis = hole_bits + nbits;               // full blocks to move (slots)
+    uint32_t* fre = mis + 2 * K;                     // free stripe blocks below F
+    static_assert(sizeof(L.tile) >= 4 * (4 * KMAX + 1024), "phase 2 scratch in the tile area");
+    if (nbits + 4 * K > sizeof(L.tile) / 4) {        // stripes of more than 2^15 blocks
+        if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
+        return;
     }
-
-    // ---- phase 3: holes left over are filled with the last full blocks
-    const uint32_t na = L.nalloc;
-    uint32_t full_blocks;
-    if (na >= O) {
-        full_blocks = wf1 + (na - O);
+    for (uint32_t i = threadIdx.x; i < nbits; i += NT) hole_bits[i] = 0;
+    if (threadIdx.x == 0) { L.nalloc = 0; L.wf = 0; }   // reused as list lengths
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < O; i += NT) atomicOr(&hole_bits[L.holes[i] >> 5], 1u << (L.holes[i] & 31));
+    __syncthreads();
+    for (uint32_t s = threadIdx.x; s < wf1; s += NT) {
+        const bool hole = (hole_bits[s >> 5] >> (s & 31)) & 1u;
+        if (s < K) {
+            if (!hole) mis[atomicAdd(&L.nalloc, 1u)] = s;
+        } else {
+            const uint32_t q = s - K;
+            if (q >= F && !hole) mis[atomicAdd(&L.nalloc, 1u)] = s;
+            if (q < F && hole) fre[atomicAdd(&L.wf, 1u)] = q;
+        }
+    }
+    const uint32_t used_top = wf1 > K ? wf1 - K : 0u;     // stripe blocks [used_top, F) were never used
+    for (uint32_t q = used_top + threadIdx.x; q < F; q += NT) fre[atomicAdd(&L.wf, 1u)] = q;
+    __syncthreads();
+    const uint32_t nmove = L.nalloc;
+    if (nmove != L.wf) {
+        if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
     } else {
-        const uint32_t R = O - na;                  // holes[na .. O) stay empty
-        full_blocks = wf1 - R;
-        // sort the remaining holes ascending (rank sort, at most K entries)
-        uint32_t* rest = L.cnt;                     // reuse: cnt is all zero here
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < R; i += NT) {
-            const uint32_t hv = L.holes[na + i];
-            uint32_t rank = 0;
-            for (uint32_t q = 0; q < R; ++q) rank += L.holes[na + q] < hv ? 1u : 0u;
-            rest[rank] = hv;
-        }
-        __syncthreads();
-        // slots [full_blocks, wf1) that are not holes hold full blocks; they
-        // move, in order, to the holes below full_blocks (rest[0 ..))
-        const uint32_t F = full_blocks;
-        for (uint32_t i = wid; i < R; i += NT / 64) {
-            const uint32_t s = F + i;
-            // position of s among the non-hole slots of [F, wf1)
-            uint32_t lo = 0, hi = R;                // holes in rest[] >= F start at hcut
-            while (lo < hi) { uint32_t mid = (lo + hi) / 2; if (rest[mid] < F) lo = mid + 1; else hi = mid; }
-            const uint32_t hcut = lo;
-            bool is_hole = false;
-            uint32_t holes_before = 0;              // holes in [F, s)
-            for (uint32_t q = hcut; q < R; ++q) {
-                if (rest[q] == s) is_hole = true;
-                if (rest[q] < s) ++holes_before;
+        for (uint32_t i = wid; i < nmove; i += NT / 64) {
+            const Word* sw = reinterpret_cast<const Word*>(slot_elem((int64_t)mis[i] << lb));
+            Word* dw = reinterpret_cast<Word*>(sp + ((uint64_t)fre[i] << lb));
+            // eight words per lane in flight: all loads of a chunk before its stores
+            for (uint32_t i0 = 0; i0 < b * WPE; i0 += 8 * 64) {
+                Word tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t w = i0 + u * 64 + lane;
+                    if (w < b * WPE) tmp[u] = sw[w];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const uint32_t w = i0 + u * 64 + lane;
+                    if (w < b * WPE) dw[w] = tmp[u];
+                }
             }
-            if (is_hole) continue;
-            const uint32_t idx = (s - F) - holes_before;   // idx-th full block above F
-            const uint32_t dst = rest[idx];                // idx-th hole below F
-            const Word* sw = reinterpret_cast<const Word*>(sp + ((uint64_t)s << lb));
-            Word* dw = reinterpret_cast<Word*>(sp + ((uint64_t)dst << lb));
-            for (uint32_t w = lane; w < (b * WPE); w += 64) dw[w] = sw[w];
         }
     }
+    const uint32_t full_blocks = F;
     __syncthreads();
     uint32_t* cnt_out = c.counts + (uint64_t)sid * KMAX;
     for (uint32_t q = threadIdx.x; q < K; q += NT) cnt_out[q] = (L.nfull[q] << lb) + L.fill[q];

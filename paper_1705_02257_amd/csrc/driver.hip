@@ -406,7 +406,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             sd.blk_begin = (uint32_t)(nb * q / ns);
             sd.blk_end = (uint32_t)(nb * (q + 1) / ns);
             sd.buf_off = bufoff;
-            bufoff += (uint64_t)4 * k * b;   // partial buffers (2k*b) and head copy (2k*b)
+            bufoff += (uint64_t)4 * k * b;   // partial buffers (2k*b) and side area (2k*b)
             L.stripes.push_back(sd);
         }
         uint64_t w = (uint64_t)std::llround((double)R.workers * (double)nb / (double)total_blocks);

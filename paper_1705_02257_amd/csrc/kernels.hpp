@@ -8,14 +8,14 @@
 //                 Preliminaries; Section 4, Sampling, Implementation Details)
 //   k_classify    one workgroup per stripe: local classification into
 //                 per-workgroup buffer blocks of b elements, full blocks
-//                 written back to the stripe front (Section 4.1)
+//                 gathered at the stripe front (Section 4.1)
 //   k_scan        one workgroup per task: bucket boundaries and block
 //                 delimiters from the per-stripe counts (Section 4.2)
 //   k_fix_empty   one workgroup per bucket: move full blocks of buckets that
 //                 cross stripe ends so every bucket is [full | empty]
 //                 (Appendix A, empty block movement); sets (w_i, r_i)
 //   k_permute     wavefront workers: the block permutation with atomic
-//                 read/write pointers and reader counts (Section 4.2)
+//                 read/write pointers and per-block read marks (Section 4.2)
 //   k_cleanup     one workgroup per bucket: heads, tails, partial buffers and
 //                 the overflow block (Section 4.3)
 // and k_basecase sorts small subproblems inside LDS.
@@ -1261,7 +1261,7 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
 //
 // The paper's threads clean their buckets one after another.  Here every
 // bucket is cleaned at once in two launches: k_overhang copies each
-// overhang to a side slot (the task's first stripe's head-copy area, free
+// overhang to a side slot (the side area of the task's first stripe, free
 // once classification is over), so that k_cleanup can then fill every
 // bucket's free positions with no ordering between buckets.
 struct BucketGeom {
@@ -1576,9 +1576,12 @@ struct BaseLds {
 // after an exclusive scan each item goes to its digit's group.  Groups hold
 // about one item; each item's final place is the group start plus the
 // number of group members that precede it (smaller, or equal and placed
-// earlier).  A segment whose keys are all equal is left as it is.  Segments whose items crowd into a few
-// digits (a group of more than 64, or records with one leading word) are
-// left untouched and appended to `fail` for k_basecase (merge sort).
+// earlier), counted with the items taken in group order.  Where a digit
+// covers a single u64/f64 key value every group is a run of equal keys and
+// needs no ranking.  A segment whose keys are all equal is left as it is.
+// Segments whose ranking would cost more than WMAX compares per item (keys
+// crowded into a few digits), and records with one leading word, are left
+// untouched and appended to `fail` for k_basecase (merge sort).
 template <int DT, int NT, int VT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
                                                        typename Traits<DT>::Elem* scratch, SegD* fail,
@@ -1591,14 +1594,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr bool kPlain = (DT == DT_U64 || DT == DT_F64);
     // 2*RADIX digits with 16-bit counters, two to a word (counts and
     // offsets stay below 2^16)
-    constexpr uint32_t RADIX = LB::RADIX, NDIG = 2 * RADIX, GMAX = 64, NW = NT / 64;
+    // ranking inside the groups costs about the sum of the squared group
+    // sizes; beyond WMAX per item the merge sort is cheaper, and beyond
+    // SPREAD per item the items are ranked in group order
+    constexpr uint32_t RADIX = LB::RADIX, NDIG = 2 * RADIX, WMAX = 48, SPREAD = 4, NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     It* items = reinterpret_cast<It*>(smem_raw);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);
     // reduction, scan and maximum scratch: the start of the item array,
     // which is free until the items are scattered into it
     uint32_t* scan_sh = reinterpret_cast<uint32_t*>(smem_raw);
-    uint32_t* gmax_sh = scan_sh + 32;
+    uint32_t* work_sh = scan_sh + 32;
     uint64_t* red = reinterpret_cast<uint64_t*>(smem_raw + 256);
     auto digit_start = [&](uint32_t d) { return (cnt[d >> 1] >> ((d & 1u) * 16u)) & 0xffffu; };
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1660,11 +1666,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // all keys equal: already sorted; records with one leading word: merge sort
         bool radix = lo != hi;
         bool sorted = false;
-        uint32_t dr[VT];                            // digit | rank << 16
+        uint32_t dr[VT];                            // digit | arrival << 16, then the final place
+        uint32_t sh = 0;
+        bool exact = false, spread = true;
         if (radix) {
             const uint64_t span = hi - lo;
             const uint32_t bits = 64u - (uint32_t)__clzll(span);
-            const uint32_t sh = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
+            sh = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
+            // u64/f64 keys with one key value per digit: every group is a
+            // run of equal keys, already in place once scattered
+            exact = kPlain && sh == 0;
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {
@@ -1675,10 +1686,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 }
             }
             __syncthreads();
-            // exclusive scan of the counters; largest group
-            constexpr uint32_t PERC = RADIX / NT;
+            // exclusive scan of the counters; ranking work (sum of squared
+            // group sizes, each size clamped to 1024, the sum saturating)
+            constexpr uint32_t PERC = RADIX / NT, SAT = 1u << 30;
             static_assert(PERC % 4 == 0, "counter words per thread");
-            uint32_t cv[PERC], loc = 0, gm = 0;
+            uint32_t cv[PERC], loc = 0, wk = 0;
             uint4* cnt4 = reinterpret_cast<uint4*>(cnt) + tid * (PERC / 4);
 #pragma unroll
             for (uint32_t q = 0; q < PERC / 4; ++q) {
@@ -1688,8 +1700,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
             for (uint32_t q = 0; q < PERC; ++q) {
                 const uint32_t c0 = cv[q] & 0xffffu, c1 = cv[q] >> 16;
+                const uint32_t k0 = min(c0, 1024u), k1 = min(c1, 1024u);
                 loc += c0 + c1;
-                gm = max(gm, max(c0, c1));
+                wk += k0 * k0 + k1 * k1;
             }
             uint32_t total;
             uint32_t pre = block_excl_scan<NT>(loc, scan_sh, &total);
@@ -1704,41 +1717,69 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             for (uint32_t q = 0; q < PERC / 4; ++q)
                 cnt4[q] = make_uint4(cv[4 * q], cv[4 * q + 1], cv[4 * q + 2], cv[4 * q + 3]);
 #pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint32_t o = __shfl_xor(gm, d, 64);
-                gm = o > gm ? o : gm;
-            }
-            if (lane == 0) gmax_sh[wid] = gm;
+            for (int d = 32; d >= 1; d >>= 1) wk = min(wk + (uint32_t)__shfl_xor((int)wk, d, 64), SAT);
+            if (lane == 0) work_sh[wid] = wk;
             __syncthreads();
-            gm = 0;
-            for (uint32_t w = 0; w < NW; ++w) gm = gmax_sh[w] > gm ? gmax_sh[w] : gm;
-            radix = gm <= GMAX;
-            __syncthreads();                        // scan_sh and gmax_sh are read
+            wk = 0;
+            for (uint32_t w = 0; w < NW; ++w) wk = min(wk + work_sh[w], SAT);
+            radix = exact || wk <= WMAX * len;
+            spread = wk <= SPREAD * len;
+            __syncthreads();                        // scan_sh and work_sh are read
         }
         if (radix) {
-            // each item to its group; then to its place inside the group
+            // each item to its group ...
 #pragma unroll
             for (int v = 0; v < VT; ++v)
                 if (v * NT + tid < len) items[digit_start(dr[v] & 0xffffu) + (dr[v] >> 16)] = x[v];
-            __syncthreads();
+            if (!exact && !spread) {
+                // ... then to its place inside the group, from the registers
+                __syncthreads();
 #pragma unroll
-            for (int v = 0; v < VT; ++v) {
-                if (v * NT + tid < len) {
-                    const uint32_t d = dr[v] & 0xffffu;
-                    const uint32_t g0 = digit_start(d), g1 = d + 1 < NDIG ? digit_start(d + 1) : len;
-                    const uint32_t pos = g0 + (dr[v] >> 16);
-                    uint32_t rank = 0;
-                    for (uint32_t j = g0; j < g1; ++j) {
-                        const It y = items[j];
-                        rank += (BI::less(y, x[v]) || (j < pos && !BI::less(x[v], y))) ? 1u : 0u;
+                for (int v = 0; v < VT; ++v) {
+                    if (v * NT + tid < len) {
+                        const uint32_t d = dr[v] & 0xffffu;
+                        const uint32_t g0 = digit_start(d), g1 = d + 1 < NDIG ? digit_start(d + 1) : len;
+                        const uint32_t pos = g0 + (dr[v] >> 16);
+                        uint32_t rank = 0;
+                        for (uint32_t j = g0; j < g1; ++j) {
+                            const It z = items[j];
+                            rank += (BI::less(z, x[v]) || (j < pos && !BI::less(x[v], z))) ? 1u : 0u;
+                        }
+                        dr[v] = g0 + rank;
                     }
-                    dr[v] = g0 + rank;
                 }
-            }
-            __syncthreads();
+                __syncthreads();
 #pragma unroll
-            for (int v = 0; v < VT; ++v)
-                if (v * NT + tid < len) items[dr[v]] = x[v];
+                for (int v = 0; v < VT; ++v)
+                    if (v * NT + tid < len) items[dr[v]] = x[v];
+            } else if (!exact) {
+                // ... or, where groups are large, with the items walked in
+                // group order: the 64 lanes of a wave then rank members of
+                // neighbouring groups, so a wave's scan is about as long as
+                // the largest of them, not the largest group any of its
+                // items fell into
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < VT; ++v) {
+                    const uint32_t p = v * NT + tid;
+                    if (p < len) {
+                        const It y = items[p];
+                        const uint32_t d = (uint32_t)((item_lead(y) - lo) >> sh);
+                        const uint32_t g0 = digit_start(d), g1 = d + 1 < NDIG ? digit_start(d + 1) : len;
+                        uint32_t rank = 0;
+                        for (uint32_t j = g0; j < g1; ++j) {
+                            const It z = items[j];
+                            rank += (BI::less(z, y) || (j < p && !BI::less(y, z))) ? 1u : 0u;
+                        }
+                        x[v] = y;
+                        dr[v] = g0 + rank;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < VT; ++v)
+                    if (v * NT + tid < len) items[dr[v]] = x[v];
+            }
             sorted = true;
         } else if (!(kPlain && lo == hi)) {
             if (tid == 0) fail[atomicAdd(nfail, 1u)] = sg;

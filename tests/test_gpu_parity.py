@@ -164,6 +164,72 @@ def test_sort_equality_buckets_thinned(env):
         assert np.array_equal(out.view(np.uint64), ref.view(np.uint64)), dtype
 
 
+def _clustered_keys(n, seed, clusters):
+    """u64 keys spread over [0, 2^62) plus clusters: (size, width) puts
+    `size` keys in [c, c + width) for a random c, so that they share one
+    digit range of the base case's counting sort (width 1: all equal)."""
+    rng = np.random.default_rng(seed)
+    keys = rng.integers(0, 1 << 62, n, dtype=np.uint64)
+    pos = rng.permutation(n)
+    at = 0
+    for size, width in clusters:
+        c = rng.integers(0, (1 << 62) - width, dtype=np.uint64)
+        keys[pos[at:at + size]] = c + rng.integers(0, width, size, dtype=np.uint64)
+        at += size
+    return keys
+
+
+def _with_keys(dtype, n, keys, seed):
+    """An input of `dtype` whose leading key word is `keys` (payload =
+    index; the other key words of a quartet and the last two key bytes of a
+    100-byte record are few-valued, so that equal leading words still order
+    by them)."""
+    rng = np.random.default_rng(seed)
+    if dtype == "u64":
+        return keys.copy()
+    if dtype == "f64":
+        return (keys >> np.uint64(2)).view(np.float64)    # positive finite values
+    inp = workloads.generate("uniform", dtype, n, seed)
+    if dtype in ("pair", "quartet"):
+        inp[:, 0] = keys
+        if dtype == "quartet":
+            inp[:, 1] = rng.integers(0, 3, n, dtype=np.uint64)
+            inp[:, 2] = rng.integers(0, 3, n, dtype=np.uint64)
+    else:
+        inp[:, 0:8] = keys.astype(">u8").view(np.uint8).reshape(n, 8)
+        inp[:, 8:10] = rng.integers(0, 3, (n, 2), dtype=np.uint8)
+    return inp
+
+
+# base-case capacity (and its half, the small bin class) per element type
+BASE_CAP = {"u64": 16384, "f64": 16384, "pair": 8192, "quartet": 4096, "bytes100": 4096}
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("shape", ["crowded", "equal_runs", "too_crowded", "narrow"])
+@pytest.mark.parametrize("which", ["small_bin", "large_bin", "levels"])
+def test_sort_crowded_digit_groups(env, dtype, shape, which):
+    """Inputs whose keys crowd into a few digit ranges of the base case:
+    groups of 65 to 500 close keys (ranked in group order), long runs of
+    equal keys, a group too large to rank (the bin goes to the merge sort),
+    and keys from a range narrower than the digit count (every digit one
+    key value); as one small or large bin, and through distribution levels."""
+    cap = BASE_CAP[dtype]
+    n = {"small_bin": cap // 2 - 37, "large_bin": cap - 5, "levels": 300007}[which]
+    width = 1 << 30
+    clusters = {"crowded": [(65, width), (130, width), (257, width), (min(500, n // 8), width), (80, 2)],
+                "equal_runs": [(n // 4, 1), (n // 8, 1), (300, 1)],
+                "too_crowded": [(n // 3, width), (90, width)], "narrow": []}[shape]
+    seed = 8000 + 10 * list(BASE_CAP).index(dtype) + ["crowded", "equal_runs", "too_crowded", "narrow"].index(shape)
+    keys = _clustered_keys(n, seed, clusters)
+    if shape == "narrow":
+        keys = np.uint64(1 << 50) + np.random.default_rng(seed).integers(0, 3000, n, dtype=np.uint64)
+    inp = _with_keys(dtype, n, keys, seed)
+    print(f"[gpu] sort {dtype} {shape} {which} n={n}", flush=True)
+    out = gpu_sort(env, inp, dtype)
+    assert_sorted_like_oracle(out, inp, dtype)
+
+
 # ---------------------------------------------------- one distribution step
 def _splitters(inp, dtype, m, seed, dup=False):
     srt = oracle.sort(inp, dtype)

@@ -121,6 +121,24 @@ int ips4o_workspace_bytes(const ips4o_handle *h, size_t *bytes);
 int ips4o_sort(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
                const ips4o_params *params, void *hip_stream);
 
+/* Sort each of num_segments independent segments of one array in place:
+ * segment i is d_data[h_offsets[i] .. h_offsets[i+1]).  The recursion of
+ * Section 4 already treats the buckets of a level as independent
+ * subproblems; here the caller's segments are the subproblems of the top
+ * level, and every level runs one set of launches over all of them.
+ * Segments within the base-case capacity go straight to the base case,
+ * each on its own; larger ones are distributed with k chosen from their
+ * size (at most params->k).  Elements outside [h_offsets[0],
+ * h_offsets[num_segments]) are not touched.
+ * h_offsets: host pointer to num_segments + 1 non-decreasing element
+ * offsets, read before the call returns (NULL allowed when num_segments is
+ * 0).  d_data: device pointer holding h_offsets[num_segments] elements.
+ * Errors: IPS4O_ERR_INVALID_ARG for decreasing offsets or the checks of
+ * ips4o_sort; IPS4O_ERR_NOT_SUPPORTED when h_offsets[num_segments] >= 2^32.
+ * Same stream and handle rules as ips4o_sort. */
+int ips4o_sort_segmented(ips4o_handle *h, void *d_data, int dtype, const uint64_t *h_offsets,
+                         uint32_t num_segments, const ips4o_params *params, void *hip_stream);
+
 /* One distribution step with caller-given splitters (Section 4: local
  * classification, block permutation, cleanup; no sampling, no recursion).
  * h_splitters: host pointer to num_splitters whole elements of `dtype`
@@ -165,6 +183,13 @@ int ips4o_select_splitters(ips4o_handle *h, const void *d_data, uint64_t n, int 
  * without a handle: returns IPS4O_OK, or the status ips4o_sort would return
  * for these arguments (d_data is only inspected for NULL and alignment). */
 int ips4o_check_args(const void *d_data, uint64_t n, int dtype, const ips4o_params *params);
+
+/* The argument checks that ips4o_sort_segmented applies before any device
+ * work, without a handle: the offsets (NULL allowed only for 0 segments,
+ * non-decreasing), then those of ips4o_check_args for the
+ * h_offsets[num_segments] elements. */
+int ips4o_check_segments(const void *d_data, int dtype, const uint64_t *h_offsets, uint32_t num_segments,
+                         const ips4o_params *params);
 
 /* The checks ips4o_distribute and ips4o_classify apply to caller-given
  * splitters (host pointer to num_splitters elements of `dtype`): count in

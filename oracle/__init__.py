@@ -44,6 +44,7 @@ def _load():
         u64, vp, u32, i32 = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
         L.or_sort.argtypes = [vp, u64, i32]; L.or_sort.restype = i32
         L.or_compare.argtypes = [vp, vp, i32]; L.or_compare.restype = i32
+        L.or_sort_segmented.argtypes = [vp, vp, u32, i32]; L.or_sort_segmented.restype = i32
         L.or_bucket.argtypes = [vp, i32, vp, u32, i32]; L.or_bucket.restype = u32
         L.or_num_buckets.argtypes = [i32, vp, u32, i32]; L.or_num_buckets.restype = u32
         L.or_classify.argtypes = [vp, u64, i32, vp, u32, i32, vp]; L.or_classify.restype = i32
@@ -72,6 +73,19 @@ def sort(arr: np.ndarray, dtype: str) -> np.ndarray:
     out = np.ascontiguousarray(arr).copy()
     if _load().or_sort(_ptr(out), _n(out), DTYPES[dtype]) != 0:
         raise ValueError(dtype)
+    return out
+
+
+def sort_segmented(arr: np.ndarray, offsets, dtype: str) -> np.ndarray:
+    """Copy of arr with arr[offsets[i]:offsets[i+1]] sorted for every i."""
+    out = np.ascontiguousarray(arr).copy()
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nseg = max(offs.shape[0] - 1, 0)
+    if nseg and int(offs[-1]) > out.shape[0]:
+        raise ValueError("offsets beyond the array")
+    rc = _load().or_sort_segmented(_ptr(out), _ptr(offs), nseg, DTYPES[dtype])
+    if rc != 0:
+        raise ValueError(f"or_sort_segmented: {rc}")
     return out
 
 

@@ -101,6 +101,20 @@ int or_sort(void *data, uint64_t n, int dtype) {
     return 0;
 }
 
+/* Many independent problems (the subproblems of Section 4, given by the
+ * caller): segment i is A[offs[i] .. offs[i+1]), each sorted on its own by
+ * the problem statement above; elements outside [offs[0], offs[nseg]) are
+ * untouched.  Returns 0, -1 for a bad dtype, -2 for decreasing offsets. */
+int or_sort_segmented(void *data, const uint64_t *offs, uint32_t nseg, int dtype) {
+    if (!qcmp_for(dtype)) return -1;
+    for (uint32_t i = 0; i < nseg; ++i)
+        if (offs[i + 1] < offs[i]) return -2;
+    unsigned char *a = (unsigned char *)data;
+    for (uint32_t i = 0; i < nseg; ++i)
+        or_sort(a + offs[i] * or_elem_size(dtype), offs[i + 1] - offs[i], dtype);
+    return 0;
+}
+
 /* Bucket of one element for splitters s_1..s_m (sorted, non-decreasing).
  *  eq == 0 (Section 3, Preliminaries): element e goes to bucket i when
  *     s_{i-1} <= e < s_i with s_0 = -inf and s_{m+1} = +inf, i.e. the bucket

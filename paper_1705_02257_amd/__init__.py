@@ -76,6 +76,7 @@ def _load():
     L.ips4o_destroy.restype = None
     L.ips4o_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
+    L.ips4o_sort_segmented.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
     L.ips4o_distribute.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, ctypes.POINTER(u32),
                                    ctypes.POINTER(Params), vp]
     L.ips4o_classify.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp]
@@ -83,14 +84,16 @@ def _load():
                                          ctypes.POINTER(u32), ctypes.POINTER(i32), vp]
     L.ips4o_check_args.argtypes = [vp, u64, i32, ctypes.POINTER(Params)]
     L.ips4o_check_splitters.argtypes = [vp, u32, i32, i32]
+    L.ips4o_check_segments.argtypes = [vp, i32, vp, u32, ctypes.POINTER(Params)]
     L.ips4o_sync.argtypes = [vp, vp]
     L.ips4o_status_string.argtypes = [i32]
     L.ips4o_status_string.restype = ctypes.c_char_p
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
-    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_distribute",
+    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
-                 "ips4o_check_args", "ips4o_check_splitters", "ips4o_last_kernel_stats"]:
+                 "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
+                 "ips4o_last_kernel_stats"]:
         getattr(L, name).restype = i32
     return L
 
@@ -182,6 +185,15 @@ def ips4o_workspace_bytes(h: int) -> int:
 def ips4o_sort(h, data, n, dtype, params=None, stream=None) -> None:
     _check(_L().ips4o_sort(h, _addr(data), n, _dtype(dtype), _params(params), _stream(stream)),
            "ips4o_sort", h)
+
+
+def ips4o_sort_segmented(h, data, offsets, dtype, params=None, stream=None) -> None:
+    """Sorts data[offsets[i]:offsets[i+1]] for every i, each on its own;
+    `offsets` is a host sequence of non-decreasing element offsets."""
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nseg = max(offs.shape[0] - 1, 0)
+    _check(_L().ips4o_sort_segmented(h, _addr(data), _dtype(dtype), offs.ctypes.data if nseg else None, nseg,
+                                     _params(params), _stream(stream)), "ips4o_sort_segmented", h)
 
 
 def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool,

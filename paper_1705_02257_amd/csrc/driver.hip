@@ -120,6 +120,7 @@ struct Carve {  // sequential sub-allocation with 256-byte alignment
 
 struct Seg {
     uint64_t off, m;
+    uint32_t grp;     // input segment it belongs to (base-case bins never span two)
 };
 
 }  // namespace
@@ -347,9 +348,18 @@ struct Level {
     Ctx<DT> c{};
 };
 
+// Bucket count for a subproblem of m elements: enough leaves that the
+// average bucket is half the base-case capacity.
+uint32_t adaptive_k(uint64_t m, const Resolved& R) {
+    return std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * m + R.cap - 1) / R.cap)));
+}
+
+// `first`: the top level of one array, whose k is the caller's (or the
+// default); `segmented`: the top level of many segments, each with the
+// adaptive k but at most the caller's.
 template <int DT>
 void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, uint32_t level,
-                bool first, uint32_t k_given) {
+                bool first, uint32_t k_given, bool segmented = false) {
     const uint32_t b = R.b;
     uint64_t total_m = 0, total_blocks = 0;
     for (const Seg& s : segs) {
@@ -383,8 +393,9 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         t.m = s.m;
         uint32_t k;
         if (k_given) k = k_given;
+        else if (segmented) k = std::min(R.k, adaptive_k(s.m, R));
         else if (first) k = R.k;
-        else k = std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * s.m + R.cap - 1) / R.cap)));
+        else k = adaptive_k(s.m, R);
         t.k = k;
         t.alpha = alpha_for<DT>(s.m, R, k);
         t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
@@ -423,9 +434,9 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     }
     // classification launch order: longest stripes first, so that the
     // workgroups dispatched last are the short ones (longest processing
-    // time first).  A stripe's cost is its length plus about twice its
-    // head of 2k blocks, which is copied aside and then goes through the
-    // partial buffers.
+    // time first).  A stripe's cost is its length plus about 2k blocks:
+    // the blocks filled in the side area, moved into the stripe at the end,
+    // and the partly filled blocks moved to the partial buffers.
     L.order.resize(L.stripes.size());
     for (size_t q = 0; q < L.order.size(); ++q) L.order[q] = (uint32_t)q;
     auto stripe_cost = [&](uint32_t q) {
@@ -738,9 +749,11 @@ int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>
 // of a level is already final (equality buckets, buckets of at most one
 // element) or is a bucket larger than `cap` (which no bin can span), so
 // sorting the span sorts each bucket in place exactly as sorting them one
-// by one would.  `first` is the index of the level's first bin.
-void add_to_bins(std::vector<SegD>& bins, size_t first, uint64_t off, uint64_t len, uint32_t cap) {
-    if (bins.size() > first) {
+// by one would.  `first` is the index of the level's first bin.  A bin
+// holds buckets of one input segment only (`grp`, parallel to the bins).
+void add_to_bins(std::vector<SegD>& bins, std::vector<uint32_t>& grp, size_t first, uint64_t off, uint64_t len,
+                 uint32_t cap, uint32_t g) {
+    if (bins.size() > first && grp.back() == g) {
         SegD& cur = bins.back();
         const uint64_t end = off + len;
         if (end - cur.off <= cap) {
@@ -749,6 +762,7 @@ void add_to_bins(std::vector<SegD>& bins, size_t first, uint64_t off, uint64_t l
         }
     }
     bins.push_back(SegD{off, (uint32_t)len, 0});
+    grp.push_back(g);
 }
 
 // Base-case bins larger than half the capacity are sorted by one
@@ -859,29 +873,36 @@ int enqueue_readback(ips4o_handle* h, Level<DT>& L, HostArena& dst, hipEvent_t e
     return IPS4O_OK;
 }
 
-// The recursion.  A level's bounds are read back as soon as its scan is
-// done; while its permutation and cleanup still run, the host turns them
-// into the next level's plan (or the base-case bins) and enqueues that
-// work behind them.  Levels alternate between two workspaces, so the one a
-// new level takes was last used two levels before, which has finished.
+// The recursion over a list of independent subproblems in [0, n_end): the
+// whole array, or the segments of a segmented sort.  A level's bounds are
+// read back as soon as its scan is done; while its permutation and cleanup
+// still run, the host turns them into the next level's plan (or the
+// base-case bins) and enqueues that work behind them.  Levels alternate
+// between two workspaces, so the one a new level takes was last used two
+// levels before, which has finished.
 template <int DT>
-int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, hipStream_t st) {
-    Resolved R;
-    int rc = resolve<DT>(p, &R);
-    if (rc) return rc;
+int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg> init, const Resolved& R,
+                  bool segmented, hipStream_t st) {
     h->last = ips4o_stats{};
-    if (n <= 1) return IPS4O_OK;
-    rc = reset_misc(h, st);
+    int rc = reset_misc(h, st);
     if (rc) return rc;
     for (hipEvent_t& e : h->scanned)
         if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // subproblems within the base-case capacity go there at once, each in
+    // a bin of its own
     std::vector<SegD> base;
+    std::vector<uint32_t> bgrp;
     std::vector<Seg> cur;
-    if (n <= R.cap) {
-        base.push_back(SegD{0, (uint32_t)n, 0});
-        h->last.elements_base = n;
+    for (const Seg& sg : init) {
+        if (sg.m <= 1) continue;
+        if (sg.m <= R.cap) {
+            base.push_back(SegD{sg.off, (uint32_t)sg.m, 0});
+            bgrp.push_back(sg.grp);
+            h->last.elements_base += sg.m;
+        } else {
+            cur.push_back(sg);
+        }
     }
-    else cur.push_back(Seg{0, n});
     uint32_t level = 0;
     Level<DT> levels[2];
     std::vector<LevelMarks> marks;
@@ -894,11 +915,11 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
         Level<DT>& L = levels[par];
         Arena& work = par ? h->work2 : h->work;
         HostArena& rb = par ? h->hbounds2 : h->hbounds;
-        plan_level<DT>(L, cur, R, level, level == 0, 0);
+        plan_level<DT>(L, cur, R, level, level == 0, 0, segmented && level == 0);
         rc = work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
         carve_level<DT>(L, work.p, h->misc.p, d_data, R, level);
-        rc = prepare_rflag<DT>(h, L, n, R.b, st);
+        rc = prepare_rflag<DT>(h, L, n_end, R.b, st);
         if (rc) return rc;
         marks.emplace_back();
         rc = launch_level_head<DT>(h, L, st, nullptr, tm, check, par ? &h->hdesc2 : &h->hdesc);
@@ -946,10 +967,10 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
                 if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
                 const uint64_t off = td.off + bd[i];
                 if (sz <= R.cap) {
-                    add_to_bins(base, first_bin, off, sz, std::min(R.cap, small_bin_cap<DT>()));
+                    add_to_bins(base, bgrp, first_bin, off, sz, std::min(R.cap, small_bin_cap<DT>()), cur[t].grp);
                     h->last.elements_base += sz;
                 }
-                else next.push_back(Seg{off, sz});
+                else next.push_back(Seg{off, sz, cur[t].grp});
             }
         }
         cur.swap(next);
@@ -978,6 +999,31 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     }
     tm.finish();
     return rc;
+}
+
+template <int DT>
+int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, hipStream_t st) {
+    Resolved R;
+    int rc = resolve<DT>(p, &R);
+    if (rc) return rc;
+    h->last = ips4o_stats{};
+    if (n <= 1) return IPS4O_OK;
+    return run_sort_list<DT>(h, d_data, n, std::vector<Seg>{Seg{0, n, 0}}, R, false, st);
+}
+
+// Segment i is [offs[i], offs[i + 1]); the offsets were checked by the caller.
+template <int DT>
+int run_sort_segmented(ips4o_handle* h, void* d_data, const uint64_t* offs, uint32_t nseg, const ips4o_params* p,
+                       hipStream_t st) {
+    Resolved R;
+    int rc = resolve<DT>(p, &R);
+    if (rc) return rc;
+    h->last = ips4o_stats{};
+    std::vector<Seg> segs;
+    for (uint32_t i = 0; i < nseg; ++i)
+        if (offs[i + 1] - offs[i] > 1) segs.push_back(Seg{offs[i], offs[i + 1] - offs[i], i});
+    if (segs.empty()) return IPS4O_OK;
+    return run_sort_list<DT>(h, d_data, offs[nseg], std::move(segs), R, true, st);
 }
 
 template <int DT>
@@ -1220,6 +1266,18 @@ int ips4o_sort(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const ips4o
     DISPATCH(dtype, run_sort<D>(h, d_data, n, params, st));
 }
 
+int ips4o_sort_segmented(ips4o_handle* h, void* d_data, int dtype, const uint64_t* h_offsets, uint32_t num_segments,
+                         const ips4o_params* params, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_segments(d_data, dtype, h_offsets, num_segments, params);
+    if (rc) return rc;
+    if (num_segments == 0 || h_offsets[num_segments] <= 1) return IPS4O_OK;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_sort_segmented<D>(h, d_data, h_offsets, num_segments, params, st));
+}
+
 int ips4o_distribute(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const void* h_splitters,
                      uint32_t num_splitters, int equality_buckets, uint64_t* h_bounds_out,
                      uint32_t* num_buckets_out, const ips4o_params* params, void* hip_stream) {
@@ -1275,6 +1333,14 @@ int ips4o_check_args(const void* d_data, uint64_t n, int dtype, const ips4o_para
     if (rc) return rc;
     if (n >= (1ull << 32)) return IPS4O_ERR_NOT_SUPPORTED;
     return IPS4O_OK;
+}
+
+int ips4o_check_segments(const void* d_data, int dtype, const uint64_t* h_offsets, uint32_t num_segments,
+                         const ips4o_params* params) {
+    if (num_segments > 0 && !h_offsets) return IPS4O_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < num_segments; ++i)
+        if (h_offsets[i + 1] < h_offsets[i]) return IPS4O_ERR_INVALID_ARG;
+    return ips4o_check_args(d_data, num_segments ? h_offsets[num_segments] : 0, dtype, params);
 }
 
 int ips4o_check_splitters(const void* h_splitters, uint32_t num_splitters, int dtype, int equality_buckets) {

@@ -109,6 +109,25 @@ def test_check_splitters(ips):
     assert lib.ips4o_check_splitters(r[::-1].copy().ctypes.data, 2, ips.BYTES100, 0) == -1
 
 
+def test_check_segments(ips):
+    lib = ips.lib
+    ok = np.array([0, 5, 5, 17, 100], dtype=np.uint64)
+    dev = ctypes.c_void_p(4096)        # only inspected for NULL and alignment
+    assert lib.ips4o_check_segments(dev, ips.U64, ok.ctypes.data, 4, None) == 0
+    assert lib.ips4o_check_segments(None, ips.U64, None, 0, None) == 0
+    assert lib.ips4o_check_segments(dev, ips.U64, None, 3, None) == -1
+    bad = np.array([0, 5, 4, 17], dtype=np.uint64)
+    assert lib.ips4o_check_segments(dev, ips.U64, bad.ctypes.data, 3, None) == -1
+    assert lib.ips4o_check_segments(None, ips.U64, ok.ctypes.data, 4, None) == -1
+    assert lib.ips4o_check_segments(ctypes.c_void_p(4100), ips.U64, ok.ctypes.data, 4, None) == -1
+    assert lib.ips4o_check_segments(dev, 9, ok.ctypes.data, 4, None) == -1
+    huge = np.array([0, 1 << 32], dtype=np.uint64)
+    assert lib.ips4o_check_segments(dev, ips.U64, huge.ctypes.data, 1, None) == -4
+    # offsets may start past 0 (the elements before are left alone)
+    late = np.array([7, 9, 30], dtype=np.uint64)
+    assert lib.ips4o_check_segments(dev, ips.PAIR, late.ctypes.data, 2, None) == 0
+
+
 def test_null_handle_rejected(ips):
     lib = ips.lib
     assert lib.ips4o_sort(None, None, 0, 0, None, None) == -1
@@ -118,6 +137,8 @@ def test_null_handle_rejected(ips):
                                 None) == -1
     assert lib.ips4o_create(0, None) == -1
     assert lib.ips4o_sync(None, None) == -1
+    o = np.array([0, 3], dtype=np.uint64)
+    assert lib.ips4o_sort_segmented(None, None, 0, o.ctypes.data, 1, None, None) == -1
 
 
 def test_create_without_gpu_is_an_error_not_a_crash(ips):

@@ -1,0 +1,117 @@
+"""Parity of the segmented sort (ips4o_sort_segmented, through the C ABI)
+with the CPU oracle: every segment sorted on its own, keys bit-exact,
+records checked by payload (payload = original index), elements outside the
+segments untouched."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_gpu_parity import env, from_dev, keys_of, payload_of, to_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+BASE_CAP = {"u64": 16384, "f64": 16384, "pair": 8192, "quartet": 4096, "bytes100": 4096}
+
+
+def gpu_sort_segmented(env, arr, offsets, dtype, params=None):
+    torch, ips, h = env
+    d = to_dev(torch, arr)
+    ips.ips4o_sort_segmented(h, d, offsets, dtype, params)
+    torch.cuda.synchronize()
+    return from_dev(d, arr)
+
+
+def assert_segments_like_oracle(out, inp, offsets, dtype):
+    ref = oracle.sort_segmented(inp, offsets, dtype)
+    assert np.array_equal(keys_of(out, dtype), keys_of(ref, dtype)), "keys differ from the oracle"
+    if dtype in ("u64", "f64"):
+        assert np.array_equal(out.view(np.uint64), ref.view(np.uint64))
+        return
+    pay = payload_of(out, dtype)
+    assert np.array_equal(out, inp[pay]), "a record was torn or mixed"
+    n = inp.shape[0]
+    lo, hi = int(offsets[0]), int(offsets[-1])
+    assert np.array_equal(pay[:lo], np.arange(lo)) and np.array_equal(pay[hi:], np.arange(hi, n))
+    for a, b in zip(np.asarray(offsets[:-1], dtype=np.int64), np.asarray(offsets[1:], dtype=np.int64)):
+        assert np.array_equal(np.sort(pay[a:b]), np.arange(a, b)), "an element left its segment"
+
+
+def _layout(sizes, lead=0, trail=0):
+    offs = np.concatenate([[lead], lead + np.cumsum(sizes)]).astype(np.uint64)
+    return offs, int(offs[-1]) + trail
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
+@pytest.mark.parametrize("dist", ["uniform", "twodup"])
+def test_segmented_mixed_sizes(env, dtype, dist):
+    """Empty, one-element, tiny, base-case-sized (both bin classes, at and
+    around the capacity) and multi-level segments side by side, in random
+    order, between a prefix and a suffix that must stay as they are."""
+    cap = BASE_CAP[dtype]
+    sizes = [0, 1, 2, 17, 500, cap // 2, cap // 2 + 1, cap - 1, cap, cap + 1, 3 * cap + 7, 40 * cap + 3, 0, 5]
+    rng = np.random.default_rng(len(dtype) + len(dist))
+    sizes = list(rng.permutation(sizes))
+    offs, n = _layout(sizes, lead=13, trail=29)
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(3, dist, dtype))
+    print(f"[gpu] segmented {dtype} {dist} n={n} segments={len(sizes)}", flush=True)
+    out = gpu_sort_segmented(env, inp, offs, dtype)
+    assert_segments_like_oracle(out, inp, offs, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["u64", "pair"])
+def test_segmented_many_small(env, dtype):
+    """Thousands of small segments of uniform keys: base-case bins must not
+    merge neighbouring segments (their key ranges overlap)."""
+    rng = np.random.default_rng(21)
+    sizes = rng.integers(0, 3000, 3000)
+    offs, n = _layout(sizes)
+    inp = workloads.generate("uniform", dtype, n, 77)
+    print(f"[gpu] segmented {dtype} many small n={n}", flush=True)
+    out = gpu_sort_segmented(env, inp, offs, dtype)
+    assert_segments_like_oracle(out, inp, offs, dtype)
+
+
+def test_segmented_equal_large_neighbours(env):
+    """Equal-sized multi-level segments with identical key distributions:
+    their buckets at every level interleave in key order but must stay in
+    their own segment."""
+    sizes = [200003] * 6
+    offs, n = _layout(sizes)
+    one = workloads.generate("uniform", "u64", sizes[0], 99)
+    inp = np.concatenate([np.random.default_rng(i).permutation(one) for i in range(6)])
+    print(f"[gpu] segmented u64 equal neighbours n={n}", flush=True)
+    out = gpu_sort_segmented(env, inp, offs, "u64")
+    assert_segments_like_oracle(out, inp, offs, "u64")
+
+
+def test_segmented_log_uniform_sizes_and_params(env):
+    """Segment sizes 2^U[4, 17.6] (the batched workload's shape) with three
+    distributions mixed, under the default and a few other parameters."""
+    rng = np.random.default_rng(5)
+    sizes = np.floor(2.0 ** rng.uniform(4, 17.63, 400)).astype(np.int64)
+    offs, n = _layout(sizes)
+    parts = []
+    for i, m in enumerate(sizes):
+        dist = ["uniform", "twodup", "sorted"][i % 3]
+        parts.append(workloads.generate(dist, "u64", int(m), 1000 + i))
+    inp = np.concatenate(parts)
+    for params in [None, {"k": 16}, {"block_bytes": 512}, {"base_cap": 1000}, {"workers": 64}]:
+        print(f"[gpu] segmented u64 log-uniform n={n} params={params}", flush=True)
+        out = gpu_sort_segmented(env, inp, offs, "u64", params)
+        assert_segments_like_oracle(out, inp, offs, "u64")
+
+
+def test_segmented_matches_plain_sort_for_one_segment(env):
+    torch, ips, h = env
+    n = 1 << 20
+    inp = workloads.generate("exponential", "f64", n, 3)
+    out = gpu_sort_segmented(env, inp, [0, n], "f64")
+    assert np.array_equal(out.view(np.uint64), oracle.sort(inp, "f64").view(np.uint64))
+
+
+def test_segmented_rejects_decreasing_offsets(env):
+    torch, ips, h = env
+    d = to_dev(torch, np.zeros(100, dtype=np.uint64))
+    with pytest.raises(Exception):
+        ips.ips4o_sort_segmented(h, d, [0, 50, 40, 100], "u64")

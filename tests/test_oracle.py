@@ -129,6 +129,49 @@ def test_sort_brute_force_alphabet_012(oracle_mod, dtype):
         assert tuple(_records(dtype, oracle_mod.sort(arr, dtype))) in good
 
 
+@pytest.mark.parametrize("dtype", ["u64", "quartet", "bytes100"])
+def test_sort_segmented_brute_force(oracle_mod, dtype):
+    """Every way to cut a 6-element array into segments (and to leave a
+    prefix and a suffix outside them): each segment comes out as one of its
+    own non-decreasing permutations, and nothing outside the segments moves."""
+    n = 6
+    rng = np.random.default_rng(11)
+    keys = [(int(v) % 3, int(v) % 2, 0) if dtype == "quartet" else
+            (bytes([0] * 9 + [int(v) % 4]) if dtype == "bytes100" else int(v) % 5)
+            for v in rng.integers(0, 60, n)]
+    arr = _mk(dtype, keys, payloads=list(range(n)))
+    for lo in range(0, 2):
+        for hi in range(n - 1, n + 1):
+            inner = hi - lo
+            for cuts in itertools.product([0, 1], repeat=inner - 1):
+                offs = [lo] + [lo + i + 1 for i, c in enumerate(cuts) if c] + [hi]
+                out = oracle_mod.sort_segmented(arr, offs, dtype)
+                assert _records(dtype, out[:lo]) == _records(dtype, arr[:lo])
+                assert _records(dtype, out[hi:]) == _records(dtype, arr[hi:])
+                for a, b in zip(offs[:-1], offs[1:]):
+                    good, _ = _brute_force_sorted_set(dtype, arr[a:b])
+                    assert tuple(_records(dtype, out[a:b])) in good
+
+
+def test_sort_segmented_invariants(oracle_mod, workloads_mod):
+    """Random layouts with empty and one-element segments: every segment
+    holds its own elements (no element crosses a cut), in numpy's sorted
+    order; one segment over everything is the full sort."""
+    rng = np.random.default_rng(3)
+    n = 20000
+    arr = workloads_mod.generate("twodup", "u64", n, 5)
+    for trial in range(5):
+        cuts = np.sort(rng.integers(0, n, 40 + 30 * trial)).astype(np.uint64)
+        offs = np.concatenate([[0], cuts, cuts[:3], [n]]).astype(np.uint64)
+        offs.sort()
+        out = oracle_mod.sort_segmented(arr, offs, "u64")
+        for a, b in zip(offs[:-1].astype(int), offs[1:].astype(int)):
+            assert np.array_equal(out[a:b], np.sort(arr[a:b]))
+    assert np.array_equal(oracle_mod.sort_segmented(arr, [0, n], "u64"), oracle_mod.sort(arr, "u64"))
+    with pytest.raises(ValueError):
+        oracle_mod.sort_segmented(arr, [0, 10, 5, n], "u64")
+
+
 def test_f64_total_order_listing(oracle_mod):
     """IEEE 754 totalOrder: a shuffled copy of the listing sorts back to it,
     and -0.0 precedes +0.0 as distinct bit patterns."""

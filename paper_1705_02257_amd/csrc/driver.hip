@@ -38,6 +38,8 @@ constexpr uint32_t kDefaultSpin = 1u << 16;      // waits last microseconds; thi
 constexpr uint32_t kMaxLevels = 48;
 constexpr uint64_t kStripeBlocksMax = 256 * 1024 - 2048;   // blocks per classification stripe
 constexpr uint32_t kLevelStripes = 512;      // classification workgroups per level
+constexpr int kSmallSample = 2048;           // sample capacity of the small sampling instance
+constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by one wave
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
 
@@ -577,8 +579,15 @@ int launch_level_head(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostT
         HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(c.ts, &given->ts, sizeof(TaskS), hipMemcpyHostToDevice, st));
     } else {
+        // levels whose samples are all small (many small tasks) take an
+        // instance with a small LDS sample array, several per CU
+        uint64_t pmax = 1;
+        for (const TaskD& t : L.tasks) pmax = std::max<uint64_t>(pmax, next_pow2((uint64_t)t.alpha * t.k - 1));
         int r = tm.begin(KK_SAMPLE);
-        hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
+        if (pmax <= kSmallSample)
+            hipLaunchKernelGGL((k_sample<DT, 256, kSmallSample>), dim3(T), dim3(256), 0, st, c);
+        else
+            hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(T), dim3(1024), 0, st, c);
         HIP_TRY(hipGetLastError());
         tm.end(r, 0.0);
     }
@@ -808,16 +817,18 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     static_assert(BNT * BVT == TR::kBaseCap, "base-case capacity");
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
     const uint32_t half = small_bin_cap<DT>();
-    // small bins first, then the large ones, staged in pinned memory
-    size_t nsmall = 0;
-    for (const SegD& sg : list) nsmall += sg.len <= half ? 1 : 0;
-    const size_t nlarge = list.size() - nsmall;
+    // small bins first, then the large ones, then (u64/f64) the tiny ones
+    // that one wave sorts in registers, staged in pinned memory
+    auto cls = [&](const SegD& sg) { return plain && sg.len <= kTinyBin ? 2 : sg.len <= half ? 0 : 1; };
+    size_t ncls[3] = {0, 0, 0};
+    for (const SegD& sg : list) ++ncls[cls(sg)];
+    const size_t nsmall = ncls[0], nlarge = ncls[1], ntiny = ncls[2];
     int rc = h->hsegs.ensure(list.size() * sizeof(SegD));
     if (rc) return rc;
     {
         SegD* hs = (SegD*)h->hsegs.p;
-        size_t a = 0, bl = nsmall;
-        for (const SegD& sg : list) hs[sg.len <= half ? a++ : bl++] = sg;
+        size_t at[3] = {0, nsmall, nsmall + nlarge};
+        for (const SegD& sg : list) hs[at[cls(sg)]++] = sg;
     }
     // the list, then room for the bins each size class hands back
     rc = h->segs.ensure(2 * list.size() * sizeof(SegD));
@@ -847,13 +858,21 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
         rc = launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, g_large, scr, fail + nsmall, nfail + 1, st);
         if (rc) return rc;
     }
+    if constexpr (plain) {
+        if (ntiny) {
+            const uint32_t g = (uint32_t)std::min<size_t>((ntiny + 3) / 4, 4 * kBaseGrid);
+            hipLaunchKernelGGL((k_basecase_tiny<DT, kTinyBin / 64>), dim3(g), dim3(256), 0, st, c,
+                               (const SegD*)(d_segs + nsmall + nlarge), (uint32_t)ntiny);
+            HIP_TRY(hipGetLastError());
+        }
+    }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
     HIP_TRY(hipStreamSynchronize(st));   // the staged list must outlive the copy
     if (log_enabled()) {
         uint32_t nf[2] = {0, 0};
         HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
-        std::fprintf(stderr, "[ips4o] base case: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted)\n",
-                     nsmall, nf[0], nlarge, nf[1]);
+        std::fprintf(stderr, "[ips4o] base case: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted), "
+                     "%zu tiny\n", nsmall, nf[0], nlarge, nf[1], ntiny);
     }
     return IPS4O_OK;
 }

@@ -281,11 +281,13 @@ __device__ inline uint32_t ilog2(uint32_t x) { return 31u - __clz(x); }
 // duplicates, switches equality buckets on when there were any, pads the
 // splitter array to a power-of-two tree and stores the level-order tree
 // a_i = s_{(2p+1) kt / 2^(l+1)} (l = floor(log2 i), p = i - 2^l).
-template <int DT, int NT>
+// SMAX: sample capacity of this instance (every task's alpha*k - 1,
+// rounded up to a power of two, must fit).
+template <int DT, int NT, int SMAX = sample_max<typename Traits<DT>::Key>()>
 __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
     using TR = Traits<DT>;
     using Key = typename TR::Key;
-    __shared__ Key smp[sample_max<Key>()];
+    __shared__ Key smp[SMAX];
     __shared__ uint32_t isnew[KT_MAX];
     __shared__ uint32_t scan_sh[NT / 64 + 1];
     const TaskD td = c.tasks[blockIdx.x];
@@ -293,13 +295,20 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
     const uint32_t S = alpha * k - 1;
     uint32_t P = 1;
     while (P < S) P <<= 1;
-    for (uint32_t i = threadIdx.x; i < P; i += NT) {
-        if (i < S) {
-            uint64_t h = splitmix64_at(td.seed, i);
-            uint64_t pos = __umul64hi(h, td.m);
-            smp[i] = TR::key(c.data[td.off + pos]);
-        } else {
-            smp[i] = TR::max_key();
+    {
+        // every load of this thread issued before the first store
+        constexpr int LPT = SMAX / NT;
+        Key v[LPT];
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const uint32_t i = threadIdx.x + (uint32_t)q * NT;
+            v[q] = TR::max_key();
+            if (i < S) v[q] = TR::key(c.data[td.off + __umul64hi(splitmix64_at(td.seed, i), td.m)]);
+        }
+#pragma unroll
+        for (int q = 0; q < LPT; ++q) {
+            const uint32_t i = threadIdx.x + (uint32_t)q * NT;
+            if (i < P) smp[i] = v[q];
         }
     }
     __syncthreads();
@@ -339,37 +348,42 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
         __syncthreads();
         nuniq = pick_unique(kp, step);
     }
-    Key* spl = c.spl + td.tree_begin;
-    Key* tree = c.tree + td.tree_begin;
-    for (uint32_t i = 1 + threadIdx.x; i < kp; i += NT) {
-        Key pick = smp[i * step - 1];
-        bool nw = (i == 1) || !(smp[(i - 1) * step - 1] == pick);
-        if (nw) spl[isnew[i]] = pick;
+    // the unique picks move to the front of smp (all picks are read before
+    // any is overwritten), padded with the largest pick to kt entries; the
+    // splitter array and the level-order tree are written from there
+    constexpr int PPT = (KT_MAX + NT - 1) / NT;
+    Key pk[PPT];
+    bool nw[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const uint32_t i = 1 + threadIdx.x + (uint32_t)q * NT;
+        nw[q] = false;
+        if (i < kp) {
+            pk[q] = smp[i * step - 1];
+            nw[q] = (i == 1) || !(smp[(i - 1) * step - 1] == pk[q]);
+        }
     }
+    const Key last = smp[(kp - 1) * step - 1];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q)
+        if (nw[q]) smp[isnew[1 + threadIdx.x + (uint32_t)q * NT]] = pk[q];
     const uint32_t eq = nuniq < kp - 1 ? 1u : 0u;
     uint32_t kt = kp;
     if (eq) {
         kt = 2;
         while (kt < nuniq + 1) kt <<= 1;
     }
-    __threadfence_block();
     __syncthreads();
-    // pad with the largest splitter
-    Key last = smp[0];
-    {
-        // the largest pick is the last one
-        last = smp[(kp - 1) * step - 1];
-    }
-    for (uint32_t j = nuniq + threadIdx.x; j < kt; j += NT) spl[j] = last;
+    for (uint32_t j = nuniq + threadIdx.x; j < kt; j += NT) smp[j] = last;
     __syncthreads();
-    __threadfence();
-    __syncthreads();
-    const uint32_t lk = ilog2(kt);
+    Key* spl = c.spl + td.tree_begin;
+    Key* tree = c.tree + td.tree_begin;
+    for (uint32_t j = threadIdx.x; j < kt; j += NT) spl[j] = smp[j];
     for (uint32_t i = 1 + threadIdx.x; i < kt; i += NT) {
-        uint32_t l = ilog2(i), p = i - (1u << l);
-        uint32_t idx = ((2 * p + 1) * kt) >> (l + 1);   // 1-based splitter index
-        (void)lk;
-        tree[i] = spl[idx - 1];
+        const uint32_t l = ilog2(i), p = i - (1u << l);
+        const uint32_t idx = ((2 * p + 1) * kt) >> (l + 1);   // 1-based splitter index
+        tree[i] = smp[idx - 1];
     }
     if (threadIdx.x == 0) {
         TaskS s;
@@ -1806,6 +1820,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
         }
         __syncthreads();
+    }
+}
+
+// Sort of each listed segment of at most 64 R u64/f64 keys by one wave:
+// the keys in registers (element e = 64 r + lane, padded with the maximal
+// key to 64 R), a bitonic sorting network whose exchanges at a distance of
+// 64 or more pair two registers of one lane and whose shorter ones pair two
+// lanes through shuffles (each lane keeps the minimum or the maximum), then
+// written back.  No LDS and no barrier, so many bins run per CU at once.
+template <int DT, int R>
+__global__ __launch_bounds__(256) void k_basecase_tiny(Ctx<DT> c, const SegD* segs, uint32_t nseg) {
+    static_assert(DT == DT_U64 || DT == DT_F64, "plain keys only");
+    using TR = Traits<DT>;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
+    for (uint32_t si = wave; si < nseg; si += nwaves) {
+        const SegD sg = segs[si];
+        uint64_t* seg = c.data + sg.off;
+        uint64_t x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = (uint32_t)r * 64u + lane;
+            x[r] = e < sg.len ? TR::key(seg[e]).v : ~0ull;
+        }
+#pragma unroll
+        for (uint32_t k = 2; k <= 64u * R; k <<= 1) {
+#pragma unroll
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                if (j >= 64) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const int l = r ^ (int)(j >> 6);
+                        if (l > r) {
+                            const bool up = (((uint32_t)r * 64u + lane) & k) == 0;
+                            const uint64_t a = x[r], b = x[l];
+                            const bool w = up ? b < a : a < b;
+                            x[r] = w ? b : a;
+                            x[l] = w ? a : b;
+                        }
+                    }
+                } else {
+                    const bool lower = (lane & j) == 0;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x[r], (int)j, 64);
+                        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x[r] >> 32), (int)j, 64);
+                        const uint64_t y = ((uint64_t)hi << 32) | lo;
+                        const bool up = (((uint32_t)r * 64u + lane) & k) == 0;
+                        const bool take = lower == up ? y < x[r] : x[r] < y;
+                        x[r] = take ? y : x[r];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = (uint32_t)r * 64u + lane;
+            if (e < sg.len) {
+                if constexpr (DT == DT_F64) seg[e] = Traits<DT_F64>::unkey(x[r]);
+                else seg[e] = x[r];
+            }
+        }
     }
 }
 

@@ -114,6 +114,24 @@ def test_sort_records(env, dtype, dist, n):
     assert_sorted_like_oracle(out, inp, dtype)
 
 
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 300, 511, 512, 513])
+def test_sort_tiny_bins_with_extreme_keys(env, n):
+    """Bins small enough for one wave: keys equal to the padding value (the
+    largest u64; the f64 whose totalOrder image is the largest) sort with
+    the rest."""
+    rng = np.random.default_rng(n)
+    u = rng.integers(0, 2**64, n, dtype=np.uint64)
+    u[rng.integers(0, n, max(1, n // 5))] = np.uint64(2**64 - 1)
+    out = gpu_sort(env, u, "u64")
+    assert_sorted_like_oracle(out, u, "u64")
+    f = u.copy()
+    f[rng.integers(0, n, max(1, n // 5))] = np.uint64(0x7FFFFFFFFFFFFFFF)   # +NaN, largest image
+    f[rng.integers(0, n, max(1, n // 7))] = np.uint64(0xFFFFFFFFFFFFFFFF)   # -NaN, smallest image
+    fv = f.view(np.float64)
+    out = gpu_sort(env, fv, "f64")
+    assert_sorted_like_oracle(out, fv, "f64")
+
+
 def test_sort_f64_special_values(env):
     """Signed zeros, infinities, NaNs with payloads and subnormals sort by
     IEEE totalOrder with their bit patterns intact."""

@@ -1,0 +1,62 @@
+"""The serving loop's batching and admission policy, on the CPU (no
+workers, fake requests): batches take the head's element type, skip other
+types without losing their order, respect the batch and pool limits, and
+release their bytes."""
+import types
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1705_02257_amd.serving import SortServer
+
+
+def fake(n, dtype="u64"):
+    nb = n * (16 if dtype == "pair" else 8)
+    return types.SimpleNamespace(n=n, nbytes=nb, dtype=dtype)
+
+
+def server(**kw):
+    return SortServer(workers=0, **kw)
+
+
+def test_batches_take_the_head_type_in_order():
+    s = server()
+    reqs = [fake(10), fake(20, "pair"), fake(30), fake(40, "f64"), fake(50)]
+    s.queue.extend(reqs)
+    batch, held = s._take_batch()
+    assert batch == [reqs[0], reqs[2], reqs[4]]
+    assert held == 2 * 90 * 8 and s.inflight == held
+    assert list(s.queue) == [reqs[1], reqs[3]]
+    batch2, _ = s._take_batch()
+    assert batch2 == [reqs[1]]
+
+
+def test_batch_and_pool_limits():
+    s = server(max_batch_bytes=100 * 8, pool_bytes=1000 * 8)
+    reqs = [fake(60), fake(30), fake(20), fake(5)]
+    s.queue.extend(reqs)
+    batch, held = s._take_batch()
+    assert batch == [reqs[0], reqs[1]]          # 60 + 30 fits, + 20 does not
+    s.queue.clear()
+    s.inflight = 998 * 8
+    s.queue.extend([fake(5), fake(6)])
+    assert s._take_batch() is None              # nothing fits beside the work in flight
+    s.inflight = 0
+    batch, held = s._take_batch()
+    assert len(batch) == 2 and held == 2 * 11 * 8
+
+
+def test_single_request_holds_its_bytes_only():
+    s = server()
+    s.queue.append(fake(7))
+    batch, held = s._take_batch()
+    assert len(batch) == 1 and held == 7 * 8 and s.inflight == held
+
+
+def test_one_at_a_time_mode():
+    s = server(batching=False)
+    reqs = [fake(1), fake(2), fake(3)]
+    s.queue.extend(reqs)
+    assert s._take_batch()[0] == [reqs[0]]
+    assert s._take_batch()[0] == [reqs[1]]

@@ -1584,8 +1584,9 @@ struct BaseLds {
 
 // Counting sort of each listed segment (at most NT*VT elements) inside one
 // workgroup's LDS, on the top bits of the leading word: every thread holds
-// VT items in registers; the span [lo, hi] of their leading words is split
-// into 2^(log2 CAP) equal digit ranges (16-bit counters, two per LDS word),
+// VT items in registers; the span [lo, hi] of their leading words, less the
+// low bits in which all of them agree, is split into 2^(log2 CAP) equal
+// digit ranges (16-bit counters, two per LDS word),
 // an LDS atomic per item counts its digit (and returns its rank in it), and
 // after an exclusive scan each item goes to its digit's group.  Groups hold
 // about one item; each item's final place is the group start plus the
@@ -1611,7 +1612,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // ranking inside the groups costs about the sum of the squared group
     // sizes; beyond WMAX per item the merge sort is cheaper, and beyond
     // SPREAD per item the items are ranked in group order
-    constexpr uint32_t RADIX = LB::RADIX, NDIG = 2 * RADIX, WMAX = 48, SPREAD = 4, NW = NT / 64;
+    constexpr uint32_t RADIX = LB::RADIX, NDIG = 2 * RADIX, WMAX = 16, SPREAD = 4, NW = NT / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     It* items = reinterpret_cast<It*>(smem_raw);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(smem_raw + LB::counters_at);
@@ -1677,6 +1678,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             lo = red[2 * w] < lo ? red[2 * w] : lo;
             hi = red[2 * w + 1] > hi ? red[2 * w + 1] : hi;
         }
+        // the low bits in which every leading word agrees with lo
+        // (integer-valued f64 keys agree in many): a second reduction, only
+        // when the span is wider than the digit count
+        uint32_t tz = 0;
+        if (lo != hi && 64u - (uint32_t)__clzll(hi - lo) > LB::LOG_CAP) {
+            uint64_t orx = 0;
+#pragma unroll
+            for (int v = 0; v < VT; ++v)
+                if (v * NT + tid < len) orx |= item_lead(x[v]) - lo;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) orx |= __shfl_xor(orx, d, 64);
+            if (lane == 0) red[4 * NW + wid] = orx;
+            __syncthreads();
+            orx = 0;
+            for (uint32_t w = 0; w < NW; ++w) orx |= red[4 * NW + w];
+            tz = (uint32_t)__builtin_ctzll(orx);
+        }
         // all keys equal: already sorted; records with one leading word: merge sort
         bool radix = lo != hi;
         bool sorted = false;
@@ -1684,12 +1702,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         uint32_t sh = 0;
         bool exact = false, spread = true;
         if (radix) {
-            const uint64_t span = hi - lo;
+            // digits: (lead - lo) >> sh, where sh first drops the tz low
+            // bits shared by every leading word (lead - lo has them zero)
+            const uint64_t span = (hi - lo) >> tz;
             const uint32_t bits = 64u - (uint32_t)__clzll(span);
-            sh = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
+            const uint32_t over = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
+            sh = tz + over;
             // u64/f64 keys with one key value per digit: every group is a
             // run of equal keys, already in place once scattered
-            exact = kPlain && sh == 0;
+            exact = kPlain && over == 0;
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {

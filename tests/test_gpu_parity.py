@@ -224,24 +224,30 @@ BASE_CAP = {"u64": 16384, "f64": 16384, "pair": 8192, "quartet": 4096, "bytes100
 
 
 @pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
-@pytest.mark.parametrize("shape", ["crowded", "equal_runs", "too_crowded", "narrow"])
+@pytest.mark.parametrize("shape", ["crowded", "equal_runs", "too_crowded", "narrow", "shared_low_bits"])
 @pytest.mark.parametrize("which", ["small_bin", "large_bin", "levels"])
 def test_sort_crowded_digit_groups(env, dtype, shape, which):
     """Inputs whose keys crowd into a few digit ranges of the base case:
     groups of 65 to 500 close keys (ranked in group order), long runs of
     equal keys, a group too large to rank (the bin goes to the merge sort),
-    and keys from a range narrower than the digit count (every digit one
-    key value); as one small or large bin, and through distribution levels."""
+    keys from a range narrower than the digit count (every digit one key
+    value), and few-valued keys whose low 20 bits all agree (as integer
+    valued doubles do); as one small or large bin, and through distribution
+    levels."""
     cap = BASE_CAP[dtype]
     n = {"small_bin": cap // 2 - 37, "large_bin": cap - 5, "levels": 300007}[which]
     width = 1 << 30
     clusters = {"crowded": [(65, width), (130, width), (257, width), (min(500, n // 8), width), (80, 2)],
                 "equal_runs": [(n // 4, 1), (n // 8, 1), (300, 1)],
-                "too_crowded": [(n // 3, width), (90, width)], "narrow": []}[shape]
-    seed = 8000 + 10 * list(BASE_CAP).index(dtype) + ["crowded", "equal_runs", "too_crowded", "narrow"].index(shape)
+                "too_crowded": [(n // 3, width), (90, width)], "narrow": [], "shared_low_bits": []}[shape]
+    shapes = ["crowded", "equal_runs", "too_crowded", "narrow", "shared_low_bits"]
+    seed = 8000 + 10 * list(BASE_CAP).index(dtype) + shapes.index(shape)
     keys = _clustered_keys(n, seed, clusters)
     if shape == "narrow":
         keys = np.uint64(1 << 50) + np.random.default_rng(seed).integers(0, 3000, n, dtype=np.uint64)
+    if shape == "shared_low_bits":
+        vals = np.random.default_rng(seed).integers(0, 2500, n, dtype=np.uint64) << np.uint64(20)
+        keys = vals + np.uint64(0x5A5A5)
     inp = _with_keys(dtype, n, keys, seed)
     print(f"[gpu] sort {dtype} {shape} {which} n={n}", flush=True)
     out = gpu_sort(env, inp, dtype)

@@ -40,6 +40,7 @@ constexpr uint64_t kStripeBlocksMax = 256 * 1024 - 2048;   // blocks per classif
 constexpr uint32_t kLevelStripes = 512;      // classification workgroups per level
 constexpr int kSmallSample = 2048;           // sample capacity of the small sampling instance
 constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by one wave
+constexpr size_t kExactOrder = 4096;         // stripes sorted exactly by cost for the launch order
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
 
@@ -439,16 +440,34 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     // time first).  A stripe's cost is its length plus about 2k blocks:
     // the blocks filled in the side area, moved into the stripe at the end,
     // and the partly filled blocks moved to the partial buffers.
-    L.order.resize(L.stripes.size());
-    for (size_t q = 0; q < L.order.size(); ++q) L.order[q] = (uint32_t)q;
-    auto stripe_cost = [&](uint32_t q) {
+    // Up to kExactOrder stripes are sorted exactly (ties keep the stripe
+    // order); above that (many small tasks) by classes of a quarter octave
+    // of cost, which is as good for balance and linear in the stripe count.
+    const size_t S = L.stripes.size();
+    std::vector<uint64_t> cost(S);
+    for (size_t q = 0; q < S; ++q) {
         const StripeD& sd = L.stripes[q];
         const TaskD& td = L.tasks[sd.task];
         const uint64_t e = std::min<uint64_t>((uint64_t)sd.blk_end * b, td.m) - (uint64_t)sd.blk_begin * b;
-        return e + 2 * std::min<uint64_t>(e, (uint64_t)td.k * b);
-    };
-    std::stable_sort(L.order.begin(), L.order.end(),
-                     [&](uint32_t x, uint32_t y) { return stripe_cost(x) > stripe_cost(y); });
+        cost[q] = e + 2 * std::min<uint64_t>(e, (uint64_t)td.k * b);
+    }
+    L.order.resize(S);
+    for (size_t q = 0; q < S; ++q) L.order[q] = (uint32_t)q;
+    if (S <= kExactOrder) {
+        std::stable_sort(L.order.begin(), L.order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+    } else {
+        constexpr int NCLS = 4 * 64;
+        auto cls = [&](uint64_t c) {          // 4 log2(c), rounded down, larger cost -> smaller class
+            if (c == 0) return NCLS - 1;
+            const int l = 63 - __builtin_clzll(c);
+            const int frac = l >= 2 ? (int)((c >> (l - 2)) & 3) : (int)((c << (2 - l)) & 3);
+            return NCLS - 1 - (4 * l + frac);
+        };
+        std::vector<uint32_t> start(NCLS + 1, 0);
+        for (size_t q = 0; q < S; ++q) ++start[cls(cost[q]) + 1];
+        for (int i = 0; i < NCLS; ++i) start[i + 1] += start[i];
+        for (size_t q = 0; q < S; ++q) L.order[start[cls(cost[q])]++] = (uint32_t)q;
+    }
     L.total_slots = slot;
     L.total_tree = treeb;
     L.total_workers = wk;
@@ -642,8 +661,11 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
     if (check) {
         uint32_t kmax = 0;
         for (const TaskD& t : L.tasks) kmax = std::max(kmax, 2 * t.k);
-        hipLaunchKernelGGL((k_check_permute<DT, 256>), dim3(kmax, T), dim3(256), 0, st, c);
-        HIP_TRY(hipGetLastError());
+        for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+            const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+            hipLaunchKernelGGL((k_check_permute<DT, 256>), dim3(kmax, nt), dim3(256), 0, st, c, t0);
+            HIP_TRY(hipGetLastError());
+        }
     }
     // cleanup: a bucket has a source (under a block) per stripe, plus the
     // overhang and the overflow block; with many stripes the sources are
@@ -928,8 +950,14 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     std::vector<uint32_t> level_tasks, level_stripes, level_workers;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     const bool check = (R.flags & IPS4O_FLAG_CHECK) != 0;
+    // host time (IPS4O_LOG): planning and enqueueing, waiting for a level's
+    // bounds, turning them into the next plan
+    using clk = std::chrono::steady_clock;
+    double t_plan = 0, t_wait = 0, t_next = 0;
+    auto since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
     while (!cur.empty()) {
         if (level >= kMaxLevels) return IPS4O_ERR_DEVICE_FAULT;
+        const auto t0 = clk::now();
         const int par = (int)(level & 1);
         Level<DT>& L = levels[par];
         Arena& work = par ? h->work2 : h->work;
@@ -952,7 +980,11 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         level_workers.push_back(L.total_workers);
         for (const Seg& sg : cur) h->last.elements_distributed += sg.m;
         // ---- the bounds are on the host once the scan has run
+        t_plan += since(t0);
+        const auto t1 = clk::now();
         HIP_TRY(hipEventSynchronize(h->scanned[par]));
+        t_wait += since(t1);
+        const auto t2 = clk::now();
         const char* rp = (const char*)rb.p;
         const size_t T = L.tasks.size();
         if (((const uint32_t*)rp)[0] != 0) {        // a fault so far: no plan from these bounds
@@ -994,10 +1026,15 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         }
         cur.swap(next);
         ++level;
+        t_next += since(t2);
     }
     h->last.levels = level;
+    const auto t3 = clk::now();
     rc = run_basecase<DT>(h, d_data, base, R, st, tm);       // ends with a stream synchronize
     if (rc) return rc;
+    if (log_enabled())
+        std::fprintf(stderr, "[ips4o] host ms: plan+enqueue %.3f, wait for bounds %.3f, next plan %.3f, "
+                     "base case (to the end) %.3f\n", t_plan, t_wait, t_next, since(t3));
     rc = check_device_error(h, st);
     // per-level counters: block moves, skips, cleanup and fix element counts
     std::vector<unsigned long long> cnt(kStatLevels * kStatsBytes / 8);

@@ -2062,10 +2062,10 @@ __global__ __launch_bounds__(NT) void k_check_classify(Ctx<DT> c) {
 // After the block permutation (Section 4.2 invariant at the end): every
 // block in [d_i, w_i) holds only elements of bucket i.
 template <int DT, int NT>
-__global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c) {
+__global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c, uint32_t task0) {
     using TR = Traits<DT>;
     __shared__ TreeLds<DT> tr;
-    const uint32_t t = blockIdx.y;
+    const uint32_t t = task0 + blockIdx.y;
     const TaskD td = c.tasks[t];
     const TaskS st = c.ts[t];
     const uint32_t j = blockIdx.x;

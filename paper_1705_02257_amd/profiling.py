@@ -10,7 +10,7 @@ average duration per kernel) headed by the command that produced it.
 
 `traffic` reads the counter_collection.csv of two `rocprofv3 --pmc` runs of
 the same program, one with FETCH_SIZE and one with WRITE_SIZE (KiB per
-dispatch).  The program must sort exactly once and contain one plain
+dispatch), each summed per kernel kind over its own run.  The program must sort exactly once and contain one plain
 device-to-device copy of `copy-bytes` bytes (the largest copyBuffer
 dispatch): the ratio between its
 known size and what each counter reports for it is the calibration factor
@@ -84,27 +84,29 @@ def _counter(d: str, counter: str):
 
 
 def traffic(fetch_dir: str, write_dir: str, copy_bytes: int):
-    """Calibrated HBM bytes of every library kernel kind over the run."""
+    """Calibrated HBM bytes of every library kernel kind over the run.  Each
+    counter is summed per kind over its own run; the two runs may differ by
+    a small extra recursion level (the sample of a level is random), which
+    `same_dispatches` records."""
     fetch = _counter(fetch_dir, "FETCH_SIZE")
     write = _counter(write_dir, "WRITE_SIZE")
-    if len(fetch) != len(write):
-        raise ValueError("the FETCH_SIZE and WRITE_SIZE runs saw different dispatch lists")
     cf = max(v for n, v in fetch if n.startswith(COPY)) * 1024.0
     cw = max(v for n, v in write if n.startswith(COPY)) * 1024.0
     sf, sw = copy_bytes / cf, copy_bytes / cw
+    same = [n for n, _ in fetch] == [n for n, _ in write]
     acc = {}
-    for (nf, vf), (nw, vw) in zip(fetch, write):
-        if nf != nw:
-            raise ValueError("dispatch order differs between the two runs")
-        kind = kind_of(nf)
-        if kind is None:
-            continue
-        a = acc.setdefault(kind, {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0})
-        a["launches"] += 1
-        a["fetch_kib"] += vf
-        a["write_kib"] += vw
+    for runs, field in ((fetch, "fetch_kib"), (write, "write_kib")):
+        for name, v in runs:
+            kind = kind_of(name)
+            if kind is None:
+                continue
+            a = acc.setdefault(kind, {"launches": 0, "fetch_kib": 0.0, "write_kib": 0.0})
+            a[field] += v
+            if field == "fetch_kib":
+                a["launches"] += 1
     for a in acc.values():
         a["hbm_bytes"] = (a["fetch_kib"] * sf + a["write_kib"] * sw) * 1024.0
+        a["same_dispatches"] = same
     return acc, sf, sw
 
 

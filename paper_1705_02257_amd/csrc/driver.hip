@@ -1,13 +1,14 @@
 // Host side of the gfx950 samplesort: the C ABI declared in include/ips4o.h,
 // argument validation, workspace management and the recursion planner.
 //
-// Recursion (Section 4: "as long as problems with at least beta*n/t elements
-// exist, we partition those problems ... then we assign remaining problems"):
-// here every level partitions all current subproblems at once, as tasks of
-// one set of launches; subproblems no larger than the base-case capacity are
-// collected and sorted by one base-case launch at the end; equality buckets
-// are never recursed into (Section 4, many identical keys).  The host reads
-// the bucket boundaries back after each level to plan the next one.
+// Recursion (Section 4, first paragraph: large subproblems are partitioned
+// by all threads together, the remaining ones are handed out to be sorted
+// independently): here every level partitions all current subproblems at
+// once, as tasks of one set of launches; subproblems no larger than the
+// base-case capacity are collected and sorted by one base-case launch at the
+// end; equality buckets are never recursed into (Section 4, many identical
+// keys).  The host reads the bucket boundaries back after each level to plan
+// the next one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -870,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
 // --------------------------------------------------------------- scan
 // One workgroup per task: C_i = sum over stripes, bounds B_i (exclusive
 // prefix), delimiters d_i = ceil(B_i / b) (Section 4.2).  Also resets the
-// reader counts and the overflow owner of the task.  With few buckets the
+// overflow owner of the task.  With few buckets the
 // stripes are summed by NT / K thread groups side by side.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {

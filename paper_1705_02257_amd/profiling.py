@@ -10,7 +10,9 @@ average duration per kernel) headed by the command that produced it.
 
 `traffic` reads the counter_collection.csv of two `rocprofv3 --pmc` runs of
 the same program, one with FETCH_SIZE and one with WRITE_SIZE (KiB per
-dispatch), each summed per kernel kind over its own run.  The program must sort exactly once and contain one plain
+dispatch), each summed per kernel kind over its own run.  Records are
+stamped with a hash of the kernel and driver code (comments and whitespace
+left out).  The program must sort exactly once and contain one plain
 device-to-device copy of `copy-bytes` bytes (the largest copyBuffer
 dispatch): the ratio between its
 known size and what each counter reports for it is the calibration factor
@@ -40,11 +42,36 @@ KINDS = [("k_sample", "sample"), ("k_classify", "classify"), ("k_scan", "scan"),
 COPY = "__amd_rocclr_copyBuffer"
 
 
-def source_sha() -> str:
+def _code_only(text: str) -> str:
+    """The source without comments and whitespace (string literals kept), so
+    that an edit to comments alone leaves the hash as it was."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            if not text[i].isspace():
+                out.append(text[i])
+            i += 1
+    return "".join(out)
+
+
+def source_sha(sources=None) -> str:
+    """Hash of the kernel and driver code the counters describe."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for p in sources or KERNEL_SOURCES:
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -912,8 +912,6 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
         bd[j] = B;
         dl[j] = (uint32_t)((B + c.b - 1) / c.b);
     }
-    for (uint32_t j = threadIdx.x; j < K; j += NT) {
-    }
     if (threadIdx.x == 0) c.ts[t].ovf_bucket = NO_BUCKET;
 }
 

@@ -1053,6 +1053,68 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c, uint32_t task0) {
             __syncthreads();
             if (first_foreign < occ) break;
         }
+        // A presorted range whose prefix ends at a few foreign blocks (a
+        // stripe leaves its first allocated blocks at its end): list the nf
+        // foreign blocks after the prefix (at most FMAX, else the range stays
+        // as it is) and swap every foreign block below the last nf positions
+        // with an in-place block among those positions; then the first
+        // occ - nf blocks all hold bucket j and count as processed.
+        const uint32_t p0 = first_foreign;
+        if (p0 > 0 && p0 < occ) {
+            constexpr uint32_t FMAX = NT >= 1024 ? 2048 : 128;
+            __shared__ uint32_t flist[FMAX], ilist[FMAX];
+            uint32_t nf = 0;
+            bool fits = true;
+            for (uint32_t base = p0; base < occ; base += NT) {
+                const uint32_t i = base + threadIdx.x;
+                const uint32_t f =
+                    (i < occ && !in_bucket(Traits<DT>::key(seg[(uint64_t)(d0 + i) * b]))) ? 1u : 0u;
+                uint32_t tot;
+                const uint32_t pre = block_excl_scan<NT>(f, sh, &tot);
+                if (nf + tot > FMAX) { fits = false; break; }        // tot is the same in every thread
+                if (f) flist[nf + pre] = i;
+                nf += tot;
+            }
+            if (fits) {
+                // the in-place blocks among the last nf positions: as many as
+                // the foreign blocks below them, which are flist[0 .. ni)
+                const uint32_t lo = occ - nf;
+                uint32_t ni = 0;
+                for (uint32_t base = lo; base < occ; base += NT) {
+                    const uint32_t i = base + threadIdx.x;
+                    const uint32_t f =
+                        (i < occ && in_bucket(Traits<DT>::key(seg[(uint64_t)(d0 + i) * b]))) ? 1u : 0u;
+                    uint32_t tot;
+                    const uint32_t pre = block_excl_scan<NT>(f, sh, &tot);
+                    if (f) ilist[ni + pre] = i;
+                    ni += tot;
+                }
+                __syncthreads();
+                const uint32_t lane = threadIdx.x & 63;
+                const uint32_t words = b * (uint32_t)(sizeof(Elem) / sizeof(Word));
+                for (uint32_t x = threadIdx.x >> 6; x < ni; x += NT / 64) {
+                    Word* pa = reinterpret_cast<Word*>(seg + (uint64_t)(d0 + flist[x]) * b);
+                    Word* pb = reinterpret_cast<Word*>(seg + (uint64_t)(d0 + ilist[x]) * b);
+                    for (uint32_t i0 = 0; i0 < words; i0 += 4 * 64) {
+                        Word ta[4], tb[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t i = i0 + u * 64 + lane;
+                            if (i < words) { ta[u] = pa[i]; tb[u] = pb[i]; }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const uint32_t i = i0 + u * 64 + lane;
+                            if (i < words) { pa[i] = tb[u]; pb[i] = ta[u]; }
+                        }
+                    }
+                }
+                if (threadIdx.x == 0) {
+                    first_foreign = lo;
+                    if (ni) stat_add(c.stats, 3, ni, blockIdx.x);
+                }
+            }
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {

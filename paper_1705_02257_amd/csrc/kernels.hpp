@@ -499,22 +499,27 @@ __device__ inline void classify_lut_batch(const Key (&k)[EPT], uint32_t (&out)[E
 // One workgroup per stripe (Section 4.1).  The workgroup keeps one buffer
 // block of b elements per bucket; a full buffer block is a finished block of
 // the stripe.  To write every element only once, the buffer block a bucket is
-// filling ("open" block) is a slot of the stripe's block space, and a full
-// open block simply stays where it is.  Slots are numbered in allocation
-// order; the first K slots live in a side area of K blocks, slot s >= K is
-// stripe block s - K.  At most read/b + K slots are allocated after `read`
-// elements (one partly filled block per bucket), so a slot in the stripe
-// never lies beyond what has been read:
+// filling ("open" block) is a block of the stripe's own space, and a full
+// open block simply stays where it is.  A block location is either a block
+// of a side area of K blocks (locations 0 .. K-1) or stripe block q
+// (location K + q).  A tile's new blocks take, in allocation order, the next
+// stripe blocks as long as those have been read (H stripe blocks used, R
+// read: at most R - H of them), and the rest the next side blocks (G used).
+// Side blocks are taken only when the stripe is used up to R, and then every
+// allocated block beyond R is partly filled (full blocks hold data already
+// read), so G never exceeds K.  Presorted data has one or two partly filled
+// blocks at a time and keeps its order: only the first block of a bucket that
+// starts in a tile whose stripe blocks are used up goes to the side area.
 //   phase 1  tiles of NT*EPT elements: classify in registers, counting-sort
 //            by bucket in LDS, write every element into its bucket's open
-//            block or into new slots allocated at the write front;
+//            block or into new blocks allocated as above;
 //   phase 2  move the content of every partly filled open block to the
-//            bucket's partial buffer (its slot becomes a hole); then the
+//            bucket's partial buffer (its block becomes a hole); then the
 //            full blocks outside stripe blocks [0, F) (those in the side
-//            area and those at or beyond F) move into the free stripe blocks
-//            below F, so the stripe ends as [F full blocks | empty blocks]
-//            with the partial buffers outside it, exactly as the paper's
-//            local classification leaves it.
+//            area and those at or beyond F), in location order, move into
+//            the free stripe blocks below F, in order, so the stripe ends as
+//            [F full blocks | empty blocks] with the partial buffers outside
+//            it, exactly as the paper's local classification leaves it.
 template <int DT, int NT, int EPT>
 struct ClassifyLds {
     using Elem = typename Traits<DT>::Elem;
@@ -526,18 +531,20 @@ struct ClassifyLds {
     uint32_t cnt[KMAX];         // elements of the tile per bucket (atomic ranks)
     uint32_t fill[KMAX];        // phase 1: fill of the open block (b: none or full);
                                 // phase 2: fill of the partial buffer
-    uint32_t open[KMAX];        // phase 1: slot of the open block
+    uint32_t open[KMAX];        // phase 1: location of the open block
     uint32_t nfull[KMAX];       // phase 1: blocks allocated; then full blocks
     uint32_t off[KMAX];         // start of the bucket's run in the tile
-    int32_t lim[KMAX];          // phase 1: tile positions p < lim go to the open block
-    uint32_t abase[KMAX];       // phase 2: allocation index of the first new block
-    int64_t base0[KMAX];        // phase 1: stripe index of position p: base0 + p ...
-    int64_t base1[KMAX];        // ... or base1 + p at and beyond lim
-    uint32_t holes[KMAX];       // slots of evacuated open blocks
+    int32_t lim[KMAX];          // phase 1: tile positions p < lim go to the open block,
+    int32_t lim2[KMAX];         // p < lim2 to new stripe blocks, the rest to new side blocks
+    int32_t base0[KMAX];        // phase 1: location element of position p: base0 + p,
+    int32_t base1[KMAX];        // base1 + p,
+    int32_t base2[KMAX];        // base2 + p (location element: location * b + offset)
+    uint32_t holes[KMAX];       // locations of evacuated open blocks
     uint64_t scan_sh[NT / 64 + 1];
-    uint32_t wf;                // slots allocated in phase 1
+    uint32_t wf;                // phase 1: stripe blocks used (H); phase 2: list length
+    uint32_t gside;             // phase 1: side blocks used (G)
     uint32_t nholes;
-    uint32_t nalloc;            // full blocks allocated in phase 2
+    uint32_t nalloc;            // phase 2: list length
 };
 
 // Exclusive scan of one 64-bit value per thread over the workgroup.
@@ -678,7 +685,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     for (uint32_t q = threadIdx.x; q < K; q += NT) {
         L.cnt[q] = 0; L.fill[q] = b; L.open[q] = 0; L.nfull[q] = 0;
     }
-    if (threadIdx.x == 0) { L.wf = 0; L.nholes = 0; L.nalloc = 0; }
+    if (threadIdx.x == 0) { L.wf = 0; L.gside = 0; L.nholes = 0; L.nalloc = 0; }
     __syncthreads();
 
     // ---- phase 1: the stripe, straight into open blocks.
@@ -708,8 +715,10 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             // per bucket: run offset (low half) and new blocks (high half).
             // Stream position pos = fill + rank lies in the open block while
             // pos < b, else in new block (pos >> lb) - 1 counted from the
-            // first new slot.
-            const uint32_t wf = L.wf;
+            // bucket's first new block.  The tile's new blocks in scan order
+            // take the first C of them stripe blocks H.., the rest side
+            // blocks G.. (C: stripe blocks read but not used yet).
+            const uint32_t H = L.wf, G = L.gside, R = (t0 + tn) >> lb;
             uint64_t v[PER], loc = 0;
 #pragma unroll
             for (uint32_t q = 0; q < PER; ++q) {
@@ -724,43 +733,61 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             }
             uint64_t total;
             uint64_t pre = block_excl_scan64<NT>(loc, L.scan_sh, &total);
+            const uint32_t Tn = (uint32_t)(total >> 32);
+            const uint32_t C = R > H ? min(R - H, Tn) : 0u;
 #pragma unroll
             for (uint32_t q = 0; q < PER; ++q) {
                 const uint32_t jb = threadIdx.x * PER + q;
                 if (jb < K) {
-                    const uint32_t o = (uint32_t)pre, ns = wf + (uint32_t)(pre >> 32);
+                    const int32_t o = (int32_t)(uint32_t)pre, r = (int32_t)(pre >> 32);
                     const uint32_t f = L.fill[jb], cn = (uint32_t)v[q], nn = (uint32_t)(v[q] >> 32);
-                    L.off[jb] = o;
-                    L.lim[jb] = (int32_t)(o + b - f);
-                    L.base0[jb] = ((int64_t)L.open[jb] << lb) - (int64_t)o + (int64_t)f;
-                    L.base1[jb] = ((int64_t)ns - 1) * (int64_t)b - (int64_t)o + (int64_t)f;
+                    const int32_t bi = (int32_t)b, fi = (int32_t)f, Ci = (int32_t)C;
+                    L.off[jb] = (uint32_t)o;
+                    L.lim[jb] = o + bi - fi;
+                    L.lim2[jb] = o + (Ci - r + 1) * bi - fi;
+                    L.base0[jb] = (int32_t)(L.open[jb] << lb) - o + fi;
+                    L.base1[jb] = ((int32_t)(K + H) + r - 1) * bi - o + fi;
+                    L.base2[jb] = ((int32_t)G + r - Ci - 1) * bi - o + fi;
                     if (cn) L.fill[jb] = ((f + cn - 1) & (b - 1)) + 1;
-                    if (nn) { L.open[jb] = ns + nn - 1; L.nfull[jb] += nn; }
+                    if (nn) {
+                        const uint32_t last = (uint32_t)r + nn - 1;
+                        L.open[jb] = last < C ? K + H + last : G + (last - C);
+                        L.nfull[jb] += nn;
+                    }
                     pre += v[q];
                 }
             }
-            if (threadIdx.x == 0) L.wf = wf + (uint32_t)(total >> 32);
+            if (threadIdx.x == 0) {
+                L.wf = H + C;
+                L.gside = G + (Tn - C);
+            }
         }
         lds_barrier();
+        // never more side blocks than the side area holds (cannot happen:
+        // see above); checked before any write
+        if (L.gside > K) {
+            if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
+            return false;
+        }
         scatter_tile<DT, NT, EPT, FULL>(L, x, tn, bk, rk);
         lds_barrier();
+        auto loc_of = [&](uint32_t p, uint32_t jb) -> int64_t {
+            const int32_t pi = (int32_t)p;
+            const int32_t base = pi < L.lim[jb] ? L.base0[jb] : (pi < L.lim2[jb] ? L.base1[jb] : L.base2[jb]);
+            return (int64_t)(base + pi);
+        };
         if constexpr (FULL) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const uint32_t p = e * NT + threadIdx.x;
-                const uint32_t jb = L.ids[p];
-                const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
-                *slot_elem(d) = L.tile[p];
+                *slot_elem(loc_of(p, L.ids[p])) = L.tile[p];
             }
         } else {
-            for (uint32_t p = threadIdx.x; p < tn; p += NT) {
-                const uint32_t jb = L.ids[p];
-                const int64_t d = ((int32_t)p < L.lim[jb] ? L.base0[jb] : L.base1[jb]) + (int64_t)p;
-                *slot_elem(d) = L.tile[p];
-            }
+            for (uint32_t p = threadIdx.x; p < tn; p += NT) *slot_elem(loc_of(p, L.ids[p])) = L.tile[p];
         }
         for (uint32_t q = threadIdx.x; q < K; q += NT) L.cnt[q] = 0;
         lds_barrier();
+        return true;
     };
     load_tile(sp, 0, E);
     uint32_t t0 = 0;
@@ -773,15 +800,15 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
         for (; t0 + 2 * TILE <= E; t0 += TILE) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) xn[e] = sp[t0 + TILE + e * NT + threadIdx.x];
-            phase1_tile(t0, TILE, std::true_type{});
+            if (!phase1_tile(t0, TILE, std::true_type{})) return;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) x[e] = xn[e];
         }
     }
     for (; t0 < E; t0 += TILE) {
         const uint32_t tn = (E - t0) < TILE ? (E - t0) : TILE;
-        if (tn == TILE) phase1_tile(t0, TILE, std::true_type{});
-        else phase1_tile(t0, tn, std::false_type{});
+        const bool ok = tn == TILE ? phase1_tile(t0, TILE, std::true_type{}) : phase1_tile(t0, tn, std::false_type{});
+        if (!ok) return;
         if (t0 + TILE < E) load_tile(sp, t0 + TILE, E);
     }
     __syncthreads();        // phase 1's stores are read back in phase 2
@@ -806,39 +833,56 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     }
     __syncthreads();
     // ... then every full block outside stripe blocks [0, F) moves into a
-    // free stripe block below F (scratch lists in the tile area)
-    const uint32_t wf1 = L.wf, O = L.nholes, F = wf1 - O;
-    __syncthreads();                                 // every wave has read wf and nholes
+    // free stripe block below F; both lists in location order (scratch in
+    // the tile area), so that data that arrived in order keeps it
+    const uint32_t H1 = L.wf, G1 = L.gside, O = L.nholes, F = G1 + H1 - O;
+    __syncthreads();                                 // every wave has read wf, gside and nholes
     uint32_t* hole_bits = reinterpret_cast<uint32_t*>(L.tile);
-    const uint32_t nbits = (wf1 + 31) / 32;
-    // at most K full side slots plus O <= K full stripe blocks beyond F move
-    uint32_t* mis = hole_bits + nbits;               // full blocks to move (slots)
+    const uint32_t nbits = (K + H1 + 31) / 32;       // locations [0, K + H1)
+    // at most G1 <= K side blocks plus O <= K stripe blocks at or beyond F
+    // move, into at most O holes plus F - H1 <= G1 unused stripe blocks
+    uint32_t* mis = hole_bits + nbits;               // full blocks to move (locations)
     uint32_t* fre = mis + 2 * K;                     // free stripe blocks below F
+    uint32_t* sh32 = reinterpret_cast<uint32_t*>(L.scan_sh);
     static_assert(sizeof(L.tile) >= 4 * (4 * KMAX + 1024), "phase 2 scratch in the tile area");
     if (nbits + 4 * K > sizeof(L.tile) / 4) {        // stripes of more than 2^15 blocks
         if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
         return;
     }
     for (uint32_t i = threadIdx.x; i < nbits; i += NT) hole_bits[i] = 0;
-    if (threadIdx.x == 0) { L.nalloc = 0; L.wf = 0; }   // reused as list lengths
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < O; i += NT) atomicOr(&hole_bits[L.holes[i] >> 5], 1u << (L.holes[i] & 31));
     __syncthreads();
-    for (uint32_t s = threadIdx.x; s < wf1; s += NT) {
-        const bool hole = (hole_bits[s >> 5] >> (s & 31)) & 1u;
-        if (s < K) {
-            if (!hole) mis[atomicAdd(&L.nalloc, 1u)] = s;
-        } else {
-            const uint32_t q = s - K;
-            if (q >= F && !hole) mis[atomicAdd(&L.nalloc, 1u)] = s;
-            if (q < F && hole) fre[atomicAdd(&L.wf, 1u)] = q;
+    // the used locations in order: side blocks 0 .. G1-1, stripe blocks 0 .. H1-1
+    uint32_t nmis = 0, nfre = 0;
+    for (uint32_t u0 = 0; u0 < G1 + H1; u0 += NT) {
+        const uint32_t u = u0 + threadIdx.x;
+        uint32_t fm = 0, ff = 0, loc = 0;
+        if (u < G1 + H1) {
+            loc = u < G1 ? u : K + (u - G1);
+            const bool hole = (hole_bits[loc >> 5] >> (loc & 31)) & 1u;
+            if (u < G1) {
+                fm = hole ? 0u : 1u;
+            } else {
+                const uint32_t q = u - G1;
+                fm = (q >= F && !hole) ? 1u : 0u;
+                ff = (q < F && hole) ? 1u : 0u;
+            }
         }
+        uint32_t tm, tf;
+        const uint32_t pm = block_excl_scan<NT>(fm, sh32, &tm);
+        const uint32_t pf = block_excl_scan<NT>(ff, sh32, &tf);
+        if (fm && nmis + pm < 2 * K) mis[nmis + pm] = loc;
+        if (ff && nfre + pf < 2 * K) fre[nfre + pf] = loc - K;
+        nmis += tm;
+        nfre += tf;
     }
-    const uint32_t used_top = wf1 > K ? wf1 - K : 0u;     // stripe blocks [used_top, F) were never used
-    for (uint32_t q = used_top + threadIdx.x; q < F; q += NT) fre[atomicAdd(&L.wf, 1u)] = q;
+    for (uint32_t q = H1 + threadIdx.x; q < F; q += NT)      // stripe blocks never used
+        if (nfre + (q - H1) < 2 * K) fre[nfre + (q - H1)] = q;
+    nfre += F > H1 ? F - H1 : 0u;
     __syncthreads();
-    const uint32_t nmove = L.nalloc;
-    if (nmove != L.wf) {
+    const uint32_t nmove = nmis;
+    if (nmis != nfre || nmis > 2 * K) {
         if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
     } else {
         for (uint32_t i = wid; i < nmove; i += NT / 64) {

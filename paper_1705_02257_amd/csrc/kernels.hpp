@@ -712,12 +712,17 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
         classify_rank<DT, NT, EPT, FULL>(L, x, tn, lkt, st, bk, rk);
         lds_barrier();
         {
-            // per bucket: run offset (low half) and new blocks (high half).
-            // Stream position pos = fill + rank lies in the open block while
+            // per bucket: run offset (bits 0..19), 1 if it gets new blocks
+            // (bits 20..39) and its new blocks (bits 40..63).  Stream
+            // position pos = fill + rank lies in the open block while
             // pos < b, else in new block (pos >> lb) - 1 counted from the
-            // bucket's first new block.  The tile's new blocks in scan order
-            // take the first C of them stripe blocks H.., the rest side
-            // blocks G.. (C: stripe blocks read but not used yet).
+            // bucket's first new block.  C of the tile's Tn new blocks take
+            // stripe blocks H.. (C: stripe blocks read but not used yet),
+            // E = Tn - C take side blocks G..: the first new block of each of
+            // the last E buckets that get new blocks (presorted data then
+            // keeps its order once phase 2 moves them into the holes left by
+            // the partly filled blocks before them), or, when fewer buckets
+            // than E get new blocks, the last E new blocks in scan order.
             const uint32_t H = L.wf, G = L.gside, R = (t0 + tn) >> lb;
             uint64_t v[PER], loc = 0;
 #pragma unroll
@@ -727,39 +732,63 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
                 if (jb < K) {
                     const uint32_t cn = L.cnt[jb];
                     const uint32_t nn = cn ? ((L.fill[jb] + cn - 1) >> lb) : 0u;
-                    v[q] = ((uint64_t)nn << 32) | cn;
+                    v[q] = ((uint64_t)nn << 40) | ((uint64_t)(nn ? 1u : 0u) << 20) | cn;
                 }
                 loc += v[q];
             }
             uint64_t total;
             uint64_t pre = block_excl_scan64<NT>(loc, L.scan_sh, &total);
-            const uint32_t Tn = (uint32_t)(total >> 32);
-            const uint32_t C = R > H ? min(R - H, Tn) : 0u;
+            const uint32_t Tn = (uint32_t)(total >> 40), M = (uint32_t)(total >> 20) & 0xfffffu;
+            const uint32_t C = R > H ? min(R - H, Tn) : 0u, E = Tn - C;
+            const bool firsts = E <= M;                 // side blocks: first new blocks of the last E buckets
 #pragma unroll
             for (uint32_t q = 0; q < PER; ++q) {
                 const uint32_t jb = threadIdx.x * PER + q;
                 if (jb < K) {
-                    const int32_t o = (int32_t)(uint32_t)pre, r = (int32_t)(pre >> 32);
-                    const uint32_t f = L.fill[jb], cn = (uint32_t)v[q], nn = (uint32_t)(v[q] >> 32);
+                    const int32_t o = (int32_t)(pre & 0xfffffu), r = (int32_t)(pre >> 40);
+                    const uint32_t ib = (uint32_t)(pre >> 20) & 0xfffffu;     // buckets with new blocks before
+                    const uint32_t f = L.fill[jb], cn = (uint32_t)v[q] & 0xfffffu, nn = (uint32_t)(v[q] >> 40);
                     const int32_t bi = (int32_t)b, fi = (int32_t)f, Ci = (int32_t)C;
+                    const int32_t S0 = (int32_t)(K + H), G0 = (int32_t)G;
                     L.off[jb] = (uint32_t)o;
                     L.lim[jb] = o + bi - fi;
-                    L.lim2[jb] = o + (Ci - r + 1) * bi - fi;
                     L.base0[jb] = (int32_t)(L.open[jb] << lb) - o + fi;
-                    L.base1[jb] = ((int32_t)(K + H) + r - 1) * bi - o + fi;
-                    L.base2[jb] = ((int32_t)G + r - Ci - 1) * bi - o + fi;
-                    if (cn) L.fill[jb] = ((f + cn - 1) & (b - 1)) + 1;
-                    if (nn) {
-                        const uint32_t last = (uint32_t)r + nn - 1;
-                        L.open[jb] = last < C ? K + H + last : G + (last - C);
-                        L.nfull[jb] += nn;
+                    if (firsts) {
+                        const bool chosen = nn && ib + E >= M;
+                        const int32_t cj = ib + E > M ? (int32_t)(ib + E - M) : 0;   // chosen buckets before
+                        if (chosen) {
+                            // new block 0 -> side block G + cj, blocks 1.. -> stripe
+                            L.lim2[jb] = o + 2 * bi - fi;
+                            L.base1[jb] = (G0 + cj - 1) * bi - o + fi;
+                            L.base2[jb] = (S0 + r - cj - 2) * bi - o + fi;
+                        } else {
+                            L.lim2[jb] = 0x7fffffff;
+                            L.base1[jb] = (S0 + r - cj - 1) * bi - o + fi;
+                            L.base2[jb] = 0;
+                        }
+                        if (nn) {
+                            L.open[jb] = chosen ? (nn == 1 ? (uint32_t)(G0 + cj) : (uint32_t)(S0 + r - cj) + nn - 2)
+                                                : (uint32_t)(S0 + r - cj) + nn - 1;
+                            L.nfull[jb] += nn;
+                        }
+                    } else {
+                        // the first C new blocks in scan order -> stripe, the rest -> side
+                        L.lim2[jb] = o + (Ci - r + 1) * bi - fi;
+                        L.base1[jb] = (S0 + r - 1) * bi - o + fi;
+                        L.base2[jb] = (G0 + r - Ci - 1) * bi - o + fi;
+                        if (nn) {
+                            const uint32_t last = (uint32_t)r + nn - 1;
+                            L.open[jb] = last < C ? K + H + last : G + (last - C);
+                            L.nfull[jb] += nn;
+                        }
                     }
+                    if (cn) L.fill[jb] = ((f + cn - 1) & (b - 1)) + 1;
                     pre += v[q];
                 }
             }
             if (threadIdx.x == 0) {
                 L.wf = H + C;
-                L.gside = G + (Tn - C);
+                L.gside = G + E;
             }
         }
         lds_barrier();

@@ -866,8 +866,10 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     // the tile area), so that data that arrived in order keeps it
     const uint32_t H1 = L.wf, G1 = L.gside, O = L.nholes, F = G1 + H1 - O;
     __syncthreads();                                 // every wave has read wf, gside and nholes
+    // hole bits: side blocks [0, K) in words [0, KW), stripe block q at bit
+    // q of words [KW, KW + SW)
     uint32_t* hole_bits = reinterpret_cast<uint32_t*>(L.tile);
-    const uint32_t nbits = (K + H1 + 31) / 32;       // locations [0, K + H1)
+    const uint32_t KW = (K + 31) / 32, SW = (H1 + 31) / 32, nbits = KW + SW;
     // at most G1 <= K side blocks plus O <= K stripe blocks at or beyond F
     // move, into at most O holes plus F - H1 <= G1 unused stripe blocks
     uint32_t* mis = hole_bits + nbits;               // full blocks to move (locations)
@@ -880,30 +882,48 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     }
     for (uint32_t i = threadIdx.x; i < nbits; i += NT) hole_bits[i] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < O; i += NT) atomicOr(&hole_bits[L.holes[i] >> 5], 1u << (L.holes[i] & 31));
+    for (uint32_t i = threadIdx.x; i < O; i += NT) {
+        const uint32_t h = L.holes[i];
+        const uint32_t bit = h < K ? h : 32 * KW + (h - K);
+        atomicOr(&hole_bits[bit >> 5], 1u << (bit & 31));
+    }
     __syncthreads();
-    // the used locations in order: side blocks 0 .. G1-1, stripe blocks 0 .. H1-1
+    auto is_hole = [&](uint32_t bit) { return (hole_bits[bit >> 5] >> (bit & 31)) & 1u; };
+    // full blocks to move, in location order: side blocks [0, G1), then
+    // stripe blocks [F, H1)
     uint32_t nmis = 0, nfre = 0;
-    for (uint32_t u0 = 0; u0 < G1 + H1; u0 += NT) {
+    const uint32_t top = H1 > F ? H1 - F : 0u;
+    for (uint32_t u0 = 0; u0 < G1 + top; u0 += NT) {
         const uint32_t u = u0 + threadIdx.x;
-        uint32_t fm = 0, ff = 0, loc = 0;
-        if (u < G1 + H1) {
-            loc = u < G1 ? u : K + (u - G1);
-            const bool hole = (hole_bits[loc >> 5] >> (loc & 31)) & 1u;
-            if (u < G1) {
-                fm = hole ? 0u : 1u;
-            } else {
-                const uint32_t q = u - G1;
-                fm = (q >= F && !hole) ? 1u : 0u;
-                ff = (q < F && hole) ? 1u : 0u;
-            }
+        uint32_t fm = 0, loc = 0;
+        if (u < G1 + top) {
+            loc = u < G1 ? u : K + F + (u - G1);
+            fm = is_hole(u < G1 ? u : 32 * KW + F + (u - G1)) ? 0u : 1u;
         }
-        uint32_t tm, tf;
+        uint32_t tm;
         const uint32_t pm = block_excl_scan<NT>(fm, sh32, &tm);
-        const uint32_t pf = block_excl_scan<NT>(ff, sh32, &tf);
         if (fm && nmis + pm < 2 * K) mis[nmis + pm] = loc;
-        if (ff && nfre + pf < 2 * K) fre[nfre + pf] = loc - K;
         nmis += tm;
+    }
+    // free stripe blocks below F, in order: the holes (a word of hole bits
+    // per thread), then the stripe blocks [H1, F) never used
+    const uint32_t fw = (min(F, H1) + 31) / 32;
+    for (uint32_t w0 = 0; w0 < fw; w0 += NT) {
+        const uint32_t w = w0 + threadIdx.x;
+        uint32_t word = 0;
+        if (w < fw) {
+            word = hole_bits[KW + w];
+            const uint32_t lim_q = min(F, H1);
+            if (32 * w + 32 > lim_q) word &= (lim_q - 32 * w >= 32) ? ~0u : ((1u << (lim_q - 32 * w)) - 1u);
+        }
+        uint32_t tf;
+        uint32_t pf = block_excl_scan<NT>((uint32_t)__popc(word), sh32, &tf);
+        while (word) {
+            const uint32_t bit = (uint32_t)__ffs(word) - 1u;
+            if (nfre + pf < 2 * K) fre[nfre + pf] = 32 * w + bit;
+            ++pf;
+            word &= word - 1u;
+        }
         nfre += tf;
     }
     for (uint32_t q = H1 + threadIdx.x; q < F; q += NT)      // stripe blocks never used

@@ -353,7 +353,11 @@ struct Level {
 };
 
 // Bucket count for a subproblem of m elements: enough leaves that the
-// average bucket is half the base-case capacity.
+// average bucket is half the base-case capacity.  Above the capacity this
+// gives k >= 4, so at least three splitters: a subproblem of one or two
+// distinct keys then always repeats a splitter, equality buckets switch on
+// and the level makes progress (with a single splitter all keys could stay
+// in one bucket, level after level).
 uint32_t adaptive_k(uint64_t m, const Resolved& R) {
     return std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * m + R.cap - 1) / R.cap)));
 }

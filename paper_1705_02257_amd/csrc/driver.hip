@@ -392,6 +392,28 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         for (size_t r = 0; given < kLevelStripes && r < rem.size(); ++r, ++given) share[rem[r].second] += 1;
     }
+    // Permutation workers per task, in groups of four (one workgroup):
+    // R.workers / 4 groups shared out in proportion to the task's blocks
+    // (largest remainders, at least one group each, no more workers than
+    // blocks), so that a level's workers fit the one round of workgroups
+    // that R.workers is sized for; a task whose workers wait for a second
+    // round only starts once the first round has drained.
+    std::vector<uint64_t> wgroups(segs.size(), 1);
+    {
+        const uint64_t G = std::max<uint32_t>(1u, R.workers / 4);
+        std::vector<std::pair<double, size_t>> rem;
+        uint64_t given = 0;
+        for (size_t i = 0; i < segs.size(); ++i) {
+            const uint64_t nb = (segs[i].m + b - 1) / b;
+            const uint64_t gmax = std::max<uint64_t>(1, (nb + 3) / 4);
+            const double q = (double)G * (double)nb / (double)std::max<uint64_t>(1, total_blocks);
+            wgroups[i] = std::min<uint64_t>(gmax, std::max<uint64_t>(1, (uint64_t)q));
+            given += wgroups[i];
+            if (wgroups[i] < gmax) rem.push_back({q - std::floor(q), i});
+        }
+        std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (size_t r = 0; given < G && r < rem.size(); ++r, ++given) wgroups[rem[r].second] += 1;
+    }
     uint32_t slot = 0, treeb = 0, wk = 0;
     uint64_t bufoff = 0;
     for (size_t i = 0; i < segs.size(); ++i) {
@@ -428,9 +450,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             bufoff += (uint64_t)4 * k * b;   // partial buffers (2k*b) and side area (2k*b)
             L.stripes.push_back(sd);
         }
-        uint64_t w = (uint64_t)std::llround((double)R.workers * (double)nb / (double)total_blocks);
-        w = std::min<uint64_t>(w, nb);              // no more workers than blocks
-        w = std::max<uint64_t>(4, (w + 3) & ~3ull);
+        const uint64_t w = 4 * wgroups[i];
         t.worker_begin = wk;
         t.nworkers = (uint32_t)w;
         wk += (uint32_t)w;

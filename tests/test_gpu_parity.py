@@ -152,13 +152,16 @@ def test_sort_f64_special_values(env):
 
 def test_sort_robust_to_parameters(env):
     """The same input sorts to the same keys under different bucket counts,
-    block sizes, stripe and worker counts, and with skipping disabled."""
+    block sizes, stripe and worker counts (also fewer workers than a level
+    has subproblems), and with skipping disabled."""
     n = 700001
     inp = workloads.generate("twodup", "u64", n, 31)
     ref = oracle.sort(inp, "u64")
     for params in [{"k": 2}, {"k": 16}, {"k": 512}, {"k": 1024}, {"block_bytes": 512}, {"block_bytes": 8192},
                    {"stripes": 1}, {"stripes": 7}, {"workers": 4}, {"workers": 64},
-                   {"flags": 1}, {"alpha_x100": 100}, {"base_cap": 1000}, {"seed": 12345}]:
+                   {"flags": 1}, {"alpha_x100": 100}, {"base_cap": 1000}, {"seed": 12345},
+                   # a second level of 16 subproblems sharing 2 and 25 groups of four workers
+                   {"k": 16, "base_cap": 1000, "workers": 8}, {"k": 16, "base_cap": 1000, "workers": 100}]:
         print(f"[gpu] sort u64 twodup n={n} params={params}", flush=True)
         out = gpu_sort(env, inp, "u64", params)
         assert np.array_equal(out, ref), params

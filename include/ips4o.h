@@ -78,8 +78,12 @@ typedef enum {
  *               min(32, sample capacity / k)).
  *   stripes     classification workgroups for the first level (default:
  *               chosen from n).
- *   workers     permutation workers (wavefronts) per level (default: chosen
- *               from the device).
+ *   workers     permutation workers (wavefronts) per level, rounded up to a
+ *               multiple of four (default 8192: one round of the permutation
+ *               kernel's workgroups on the device).  A level shares them
+ *               among its subproblems in groups of four, in proportion to
+ *               their blocks, at least one group each (so a level with more
+ *               subproblems than groups uses more).
  *   seed        sampling seed (default a fixed constant).
  *   flags       IPS4O_FLAG_* bits.
  *   spin_limit  iterations a kernel may wait for another workgroup before it

@@ -119,12 +119,22 @@ def _dtype(dt):
     return DTYPES[dt] if isinstance(dt, str) else int(dt)
 
 
-def _addr(x):
-    """Device address of a torch tensor or an int."""
+def _addr(x, need_bytes=None, what="data"):
+    """Device address of a torch tensor or of a raw address given as an int.
+    A tensor must be on a GPU and contiguous (the library reads its bytes
+    from data_ptr() on) and hold at least need_bytes bytes; anything else
+    raises ValueError before the library is called."""
     if x is None:
         return None
     if isinstance(x, int):
         return x
+    if not x.is_cuda:
+        raise ValueError(f"{what}: a GPU tensor is needed, got one on {x.device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{what}: the tensor must be contiguous")
+    have = x.numel() * x.element_size()
+    if need_bytes is not None and have < need_bytes:
+        raise ValueError(f"{what}: {need_bytes} bytes needed, the tensor holds {have}")
     return x.data_ptr()
 
 
@@ -183,7 +193,8 @@ def ips4o_workspace_bytes(h: int) -> int:
 
 
 def ips4o_sort(h, data, n, dtype, params=None, stream=None) -> None:
-    _check(_L().ips4o_sort(h, _addr(data), n, _dtype(dtype), _params(params), _stream(stream)),
+    d = _dtype(dtype)
+    _check(_L().ips4o_sort(h, _addr(data, n * ELEM_BYTES[d]), n, d, _params(params), _stream(stream)),
            "ips4o_sort", h)
 
 
@@ -192,7 +203,9 @@ def ips4o_sort_segmented(h, data, offsets, dtype, params=None, stream=None) -> N
     `offsets` is a host sequence of non-decreasing element offsets."""
     offs = np.ascontiguousarray(offsets, dtype=np.uint64)
     nseg = max(offs.shape[0] - 1, 0)
-    _check(_L().ips4o_sort_segmented(h, _addr(data), _dtype(dtype), offs.ctypes.data if nseg else None, nseg,
+    d = _dtype(dtype)
+    need = int(offs.max()) * ELEM_BYTES[d] if nseg else 0
+    _check(_L().ips4o_sort_segmented(h, _addr(data, need), d, offs.ctypes.data if nseg else None, nseg,
                                      _params(params), _stream(stream)), "ips4o_sort_segmented", h)
 
 
@@ -202,7 +215,7 @@ def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets:
     m = sp.shape[0]
     bounds = np.zeros(2 * m + 2, dtype=np.uint64)
     K = ctypes.c_uint32(0)
-    _check(_L().ips4o_distribute(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, m,
+    _check(_L().ips4o_distribute(h, _addr(data, n * ELEM_BYTES[_dtype(dtype)]), n, _dtype(dtype), sp.ctypes.data, m,
                                 int(bool(equality_buckets)), bounds.ctypes.data, ctypes.byref(K),
                                 _params(params), _stream(stream)), "ips4o_distribute", h)
     return bounds[:K.value + 1].copy()
@@ -211,8 +224,9 @@ def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets:
 def ips4o_classify(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool, out,
                    stream=None) -> None:
     sp = np.ascontiguousarray(splitters)
-    _check(_L().ips4o_classify(h, _addr(data), n, _dtype(dtype), sp.ctypes.data, sp.shape[0],
-                              int(bool(equality_buckets)), _addr(out), _stream(stream)),
+    _check(_L().ips4o_classify(h, _addr(data, n * ELEM_BYTES[_dtype(dtype)]), n, _dtype(dtype), sp.ctypes.data,
+                              sp.shape[0], int(bool(equality_buckets)), _addr(out, 4 * n, "out"),
+                              _stream(stream)),
            "ips4o_classify")
 
 
@@ -227,7 +241,7 @@ def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np
     out = np.zeros((k - 1) * s, dtype=np.uint8)
     nu = ctypes.c_uint32(0)
     eq = ctypes.c_int(0)
-    _check(_L().ips4o_select_splitters(h, _addr(data), n, d, _params(params), out.ctypes.data,
+    _check(_L().ips4o_select_splitters(h, _addr(data, n * ELEM_BYTES[d]), n, d, _params(params), out.ctypes.data,
                                       ctypes.byref(nu), ctypes.byref(eq), _stream(stream)),
            "ips4o_select_splitters")
     raw = out[:nu.value * s]

@@ -12,6 +12,11 @@ are on the GPU start as soon as a worker and memory are free, and their work
 overlaps on the device.  Latency runs from submit() to the completion of the
 request's copy back.
 
+A request tensor must be contiguous and on the server's GPU, and stay
+untouched until wait() returns.  submit() records an event on the caller's
+current stream, and the worker's stream waits for it, so work the caller
+queued on that stream before submitting (filling the tensor) comes first.
+
 The sorting itself is the library's (the recursion of Section 4 applied to
 many independent arrays); this module only schedules.
 """
@@ -29,9 +34,10 @@ ELEM_BYTES = {"u64": 8, "f64": 8, "pair": 16}
 class Request:
     """One sort request; wait() blocks until it is done."""
 
-    def __init__(self, tensor, dtype):
+    def __init__(self, tensor, dtype, ready=None):
         self.tensor = tensor
         self.dtype = dtype
+        self.ready = ready              # event on the submitting stream
         self.n = n_elements(tensor, dtype)
         self.nbytes = self.n * ELEM_BYTES[dtype]
         self.t_submit = time.perf_counter()
@@ -83,7 +89,18 @@ class SortServer:
 
     # ------------------------------------------------------------ clients
     def submit(self, tensor, dtype) -> Request:
-        r = Request(tensor, dtype)
+        torch = self.torch
+        if dtype not in ELEM_BYTES:
+            raise ValueError(f"element type {dtype!r} is not served (one of {sorted(ELEM_BYTES)})")
+        if not tensor.is_cuda or tensor.device.index != self.device:
+            raise ValueError(f"the tensor must be on cuda:{self.device}, not {tensor.device}")
+        if not tensor.is_contiguous():
+            raise ValueError("the tensor must be contiguous")
+        ready = torch.cuda.Event()
+        ready.record(torch.cuda.current_stream(self.device))
+        r = Request(tensor, dtype, ready)
+        if tensor.numel() * tensor.element_size() < r.nbytes:
+            raise ValueError(f"the tensor holds fewer than the {r.nbytes} bytes of {r.n} {dtype} elements")
         with self.cond:
             if self.closed:
                 raise RuntimeError("server closed")
@@ -179,6 +196,9 @@ class SortServer:
     def _run(self, h, stream, batch):
         torch = self.torch
         dtype = batch[0].dtype
+        for r in batch:
+            if r.ready is not None:
+                stream.wait_event(r.ready)
         if len(batch) == 1:
             r = batch[0]
             ips4o_sort(h, r.tensor, r.n, dtype, None, stream)

@@ -148,3 +148,14 @@ def test_create_without_gpu_is_an_error_not_a_crash(ips):
     h = ctypes.c_void_p(1)
     rc = ips.lib.ips4o_create(0, ctypes.byref(h))
     assert rc in (-4, -1, -3) and h.value is None
+
+
+def test_tensor_arguments_checked_before_the_library(ips):
+    """Raw addresses pass through; a tensor that is not on a GPU is refused
+    with ValueError before anything reaches the library."""
+    import torch
+    assert ips._addr(12345) == 12345 and ips._addr(None) is None
+    with pytest.raises(ValueError):
+        ips._addr(torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError):
+        ips.ips4o_sort(None, torch.zeros(4, dtype=torch.int64), 4, "u64")

@@ -488,3 +488,19 @@ def test_sort_2pow30_properties(env):
         assert int((s0 < v).sum()) <= int(r) < int((s0 <= v).sum())
     del d, d0, s, s0
     torch.cuda.empty_cache()
+
+
+def test_tensor_arguments_checked(env):
+    """A view that is not contiguous or a tensor shorter than n elements is
+    refused with ValueError before the library is called."""
+    torch, ips, h = env
+    d = torch.zeros(1000, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(ValueError):
+        ips.ips4o_sort(h, d[::2], 500, "u64")
+    with pytest.raises(ValueError):
+        ips.ips4o_sort(h, d, 1001, "u64")
+    with pytest.raises(ValueError):
+        ips.ips4o_sort(h, d.expand(4, 1000), 4000, "u64")
+    with pytest.raises(ValueError):
+        ips.ips4o_sort_segmented(h, d, [0, 600, 1200], "u64")
+    ips.ips4o_sort(h, d, 1000, "u64")          # the exact size is accepted

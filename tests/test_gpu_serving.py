@@ -75,3 +75,31 @@ def test_oversized_request_rejected(env):
     assert r2.wait(60) and r2.error is None
     srv.close()
     assert torch.equal(small.cpu(), torch.arange(1, 101, dtype=torch.int64))
+
+
+def test_submit_checks_the_tensor_and_orders_after_the_callers_stream(env):
+    """A view that is not contiguous, or a tensor short of the request's
+    bytes, is refused at submit; a tensor still being filled on the caller's
+    stream when it is submitted is sorted only after that fill."""
+    torch, ips, h = env
+    from paper_1705_02257_amd.serving import SortServer
+    srv = SortServer(workers=1)
+    base = torch.zeros(1000, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(ValueError):
+        srv.submit(base[::2], "u64")
+    with pytest.raises(ValueError):
+        srv.submit(torch.zeros((10, 1), dtype=torch.int64, device="cuda:0"), "pair")
+    n = 1 << 22
+    host = workloads.generate("uniform", "u64", n, 0x5EB)
+    src = torch.from_numpy(host.view(np.int64)).to("cuda:0")
+    dst = torch.zeros_like(src)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(8):                 # keep the side stream busy, then fill dst last
+            dst.copy_(src.flip(0))
+        dst.copy_(src)
+        r = srv.submit(dst, "u64")
+    assert r.wait(60) and r.error is None
+    srv.close()
+    assert np.array_equal(dst.cpu().numpy().view(np.uint64), oracle.sort(host, "u64"))

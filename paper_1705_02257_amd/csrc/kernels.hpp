@@ -731,6 +731,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
                 v[q] = 0;
                 if (jb < K) {
                     const uint32_t cn = L.cnt[jb];
+                    L.cnt[jb] = 0;              // ready for the next tile's ranks
                     const uint32_t nn = cn ? ((L.fill[jb] + cn - 1) >> lb) : 0u;
                     v[q] = ((uint64_t)nn << 40) | ((uint64_t)(nn ? 1u : 0u) << 20) | cn;
                 }
@@ -814,8 +815,9 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
         } else {
             for (uint32_t p = threadIdx.x; p < tn; p += NT) *slot_elem(loc_of(p, L.ids[p])) = L.tile[p];
         }
-        for (uint32_t q = threadIdx.x; q < K; q += NT) L.cnt[q] = 0;
-        lds_barrier();
+        // no barrier here: the next tile's ranking only touches cnt (cleared
+        // above), and the barrier after it comes before anything this loop
+        // reads is overwritten
         return true;
     };
     load_tile(sp, 0, E);

@@ -112,7 +112,7 @@ struct Ctx {
     uint32_t total_workers;
     uint32_t total_slots;
     uint32_t skip_inplace;
-    uint32_t pad;
+    uint32_t vtile;             // classification: virtual tiles of 2 tiles (8-byte keys)
 };
 
 enum ErrCode : uint32_t {
@@ -604,8 +604,9 @@ __device__ inline void classify_batch(const Key (&k)[EPT], uint32_t (&out)[EPT],
 
 // Classify the tile held in x[] (tn valid elements) and rank every element
 // within its bucket: one LDS atomic per wavefront when all its lanes share a
-// bucket (skewed inputs), else one per element.
-template <int DT, int NT, int EPT, bool FULL>
+// bucket (skewed inputs), else one per element.  PACK: the rank goes into
+// bits 10.. of bk[] (bucket < 1024) instead of rk[].
+template <int DT, int NT, int EPT, bool FULL, bool PACK = false>
 __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename Traits<DT>::Elem (&x)[EPT],
                                      uint32_t tn, uint32_t lkt, const TaskS& st, uint32_t (&bk)[EPT],
                                      uint32_t (&rk)[EPT]) {
@@ -627,9 +628,12 @@ __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename
             uint32_t base = 0;
             if (below == 0 && valid) base = atomicAdd(&L.cnt[b0], (uint32_t)__popcll(same));
             base = __builtin_amdgcn_readfirstlane(base);
-            rk[e] = base + below;
+            if constexpr (PACK) bk[e] |= (base + below) << 10;
+            else rk[e] = base + below;
         } else if (valid) {
-            rk[e] = atomicAdd(&L.cnt[bk[e]], 1u);
+            const uint32_t r = atomicAdd(&L.cnt[bk[e]], 1u);
+            if constexpr (PACK) bk[e] |= r << 10;
+            else rk[e] = r;
         }
     }
 }
@@ -706,11 +710,12 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             }
         }
     };
-    auto phase1_tile = [&](uint32_t t0, uint32_t tn, auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        uint32_t bk[EPT], rk[EPT];
-        classify_rank<DT, NT, EPT, FULL>(L, x, tn, lkt, st, bk, rk);
-        lds_barrier();
+    // per-bucket bookkeeping of a tile of tn keys starting at stripe
+    // position t0 whose ranks are in cnt: run offsets, where each run
+    // position goes (open block, new stripe blocks, new side blocks), the
+    // counters cleared for the next tile; false if the side area would
+    // overflow (checked before any write)
+    auto plan_tile = [&](uint32_t t0, uint32_t tn) -> bool {
         {
             // per bucket: run offset (bits 0..19), 1 if it gets new blocks
             // (bits 20..39) and its new blocks (bits 40..63).  Stream
@@ -799,13 +804,22 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             if (threadIdx.x == 0) raise_err(c.err, ERR_CHECK_BLOCK);
             return false;
         }
+        return true;
+    };
+    // memory location element of tile position p of bucket jb
+    auto loc_of = [&](uint32_t p, uint32_t jb) -> int64_t {
+        const int32_t pi = (int32_t)p;
+        const int32_t base = pi < L.lim[jb] ? L.base0[jb] : (pi < L.lim2[jb] ? L.base1[jb] : L.base2[jb]);
+        return (int64_t)(base + pi);
+    };
+    auto phase1_tile = [&](uint32_t t0, uint32_t tn, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        uint32_t bk[EPT], rk[EPT];
+        classify_rank<DT, NT, EPT, FULL>(L, x, tn, lkt, st, bk, rk);
+        lds_barrier();
+        if (!plan_tile(t0, tn)) return false;
         scatter_tile<DT, NT, EPT, FULL>(L, x, tn, bk, rk);
         lds_barrier();
-        auto loc_of = [&](uint32_t p, uint32_t jb) -> int64_t {
-            const int32_t pi = (int32_t)p;
-            const int32_t base = pi < L.lim[jb] ? L.base0[jb] : (pi < L.lim2[jb] ? L.base1[jb] : L.base2[jb]);
-            return (int64_t)(base + pi);
-        };
         if constexpr (FULL) {
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -816,12 +830,58 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
             for (uint32_t p = threadIdx.x; p < tn; p += NT) *slot_elem(loc_of(p, L.ids[p])) = L.tile[p];
         }
         // no barrier here: the next tile's ranking only touches cnt (cleared
-        // above), and the barrier after it comes before anything this loop
-        // reads is overwritten
+        // by plan_tile), and the barrier after it comes before anything this
+        // loop reads is overwritten
         return true;
     };
-    load_tile(sp, 0, E);
+    // A virtual tile of 2 TILE keys (8-byte keys only): x holds the first
+    // TILE, x2 the second.  Both halves are ranked together (cnt counts on
+    // across them), so every bucket's run is twice as long as in a tile
+    // and its writes cover whole cache lines more often; the runs are then
+    // scattered and written in two passes by tile position, positions
+    // [0, TILE) first, through the one TILE-key LDS buffer.  Bucket and rank
+    // of a key travel packed in one word (bucket < 1024, rank < 2^14).
+    auto phase1_vtile = [&](uint32_t t0, const Elem (&x2)[EPT]) -> bool {
+        static_assert(KMAX <= 1024 && 2 * TILE <= (1u << 22), "bucket and rank packed in one word");
+        uint32_t br[EPT], br2[EPT], unused[EPT];
+        classify_rank<DT, NT, EPT, true, true>(L, x, TILE, lkt, st, br, unused);
+        classify_rank<DT, NT, EPT, true, true>(L, x2, TILE, lkt, st, br2, unused);
+        lds_barrier();
+        if (!plan_tile(t0, 2 * TILE)) return false;
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t j = br[e] & 1023u, q = L.off[j] + (br[e] >> 10) - h * TILE;
+                if (q < TILE) { L.tile[q] = x[e]; L.ids[q] = (uint16_t)j; }
+                const uint32_t j2 = br2[e] & 1023u, q2 = L.off[j2] + (br2[e] >> 10) - h * TILE;
+                if (q2 < TILE) { L.tile[q2] = x2[e]; L.ids[q2] = (uint16_t)j2; }
+            }
+            lds_barrier();
+#pragma unroll 2
+            for (int e = 0; e < EPT; ++e) {
+                const uint32_t p = e * NT + threadIdx.x;
+                *slot_elem(loc_of(h * TILE + p, L.ids[p])) = L.tile[p];
+            }
+            if (h == 0) lds_barrier();      // the second pass overwrites tile and ids
+        }
+        return true;
+    };
     uint32_t t0 = 0;
+    if constexpr (sizeof(Elem) == 8) {
+        if (c.vtile) {
+            Elem x2[EPT];
+            for (; t0 + 2 * TILE <= E; t0 += 2 * TILE) {
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                    x[e] = sp[t0 + e * NT + threadIdx.x];
+                    x2[e] = sp[t0 + TILE + e * NT + threadIdx.x];
+                }
+                if (!phase1_vtile(t0, x2)) return;
+            }
+        }
+    }
+    load_tile(sp, t0, E);
     {
         // steady state: the next tile is full too.  Its loads go to a second
         // register set at the start of the iteration; the body has no other

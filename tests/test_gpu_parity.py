@@ -95,6 +95,21 @@ def test_sort_2pow20_all_distributions(env, dtype, dist):
     assert_sorted_like_oracle(out, inp, dtype)
 
 
+@pytest.mark.parametrize("dtype,dist,params", [
+    ("u64", "uniform", None), ("u64", "sorted", None), ("f64", "exponential", None),
+    ("u64", "uniform", {"k": 2}), ("u64", "twodup", {"k": 2}), ("f64", "almost", {"k": 2})])
+def test_sort_2pow24_second_level(env, dtype, dist, params):
+    """2^24 keys: a second level whose stripes hold several virtual tiles of
+    16384 keys plus a remainder; with the default k its subproblems take
+    k = 8, with k = 2 on the first level they take k = 1024.  Bit-exact
+    against the oracle."""
+    n = 1 << 24
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(2, dist, dtype))
+    print(f"[gpu] sort {dtype} {dist} n=2^24 params={params}", flush=True)
+    out = gpu_sort(env, inp, dtype, params)
+    assert_sorted_like_oracle(out, inp, dtype)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 17, 255, 256, 257, 4095, 16384, 16385, 65535, 65536,
                                65537, 100003, 262147, 1000003])
 def test_sort_sizes_u64(env, n):

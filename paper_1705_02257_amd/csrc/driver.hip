@@ -394,8 +394,8 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     }
     // Permutation workers per task, in groups of four (one workgroup):
     // R.workers / 4 groups shared out in proportion to the task's blocks
-    // (largest remainders, at least one group each, no more workers than
-    // blocks), so that a level's workers fit the one round of workgroups
+    // (largest remainders, at least one group each, no more groups than it
+    // takes to give every block a worker), so that a level's workers fit the one round of workgroups
     // that R.workers is sized for; a task whose workers wait for a second
     // round only starts once the first round has drained.
     std::vector<uint64_t> wgroups(segs.size(), 1);

@@ -1,12 +1,22 @@
 """Turn rocprofv3 CSV output into the short summaries kept under profiles/.
 
     python -m paper_1705_02257_amd.profiling stats  TRACE_DIR  OUT.md  --command "..."
+    python -m paper_1705_02257_amd.profiling sq     PMC_DIR    OUT.md  --command "..."
     python -m paper_1705_02257_amd.profiling traffic FETCH_DIR WRITE_DIR OUT_DIR \
         --copy-bytes N --command "..."
 
 `stats` reads the kernel_stats.csv of a `rocprofv3 --kernel-trace --stats
 --output-format csv` run and writes a markdown table (calls, total and
 average duration per kernel) headed by the command that produced it.
+
+`sq` reads the counter_collection.csv of one `rocprofv3 --pmc` run of SQ
+counters (SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT
+SQ_WAIT_INST_LDS SQ_BUSY_CYCLES) and writes per library kernel the counter
+sums and three shares of the kernel's time (its dispatch durations, 256 CUs
+at 2.4 GHz): LDS bank conflicts per CU-cycle, SIMD time issuing vector
+instructions (a wave64 instruction holds its 16-lane SIMD for 4 cycles),
+and wave time waiting to issue LDS instructions (for kernels whose resident
+waves per CU are known).
 
 `traffic` reads the counter_collection.csv of two `rocprofv3 --pmc` runs of
 the same program, one with FETCH_SIZE and one with WRITE_SIZE (KiB per
@@ -110,6 +120,59 @@ def _counter(d: str, counter: str):
     return per
 
 
+# resident waves per CU of the kernels whose occupancy is fixed by their
+# LDS and workgroup shape (one 1024-lane workgroup, or two of 512 lanes;
+# the permutation runs 8 four-wave workgroups per CU)
+RESIDENT_WAVES = [("k_classify<", 16), ("k_basecase_count<", 16), ("k_sample<0, 1024", 16),
+                  ("k_sample<1, 1024", 16), ("k_permute<", 32)]
+SQ_COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS"]
+
+
+def sq_table(pmc_dir: str, cus: int = 256, ghz: float = 2.4):
+    """{kernel: {dispatches, ms, counter sums, conflict/valu/ldswait shares}}."""
+    acc, spans = {}, {}
+    for r in csv.DictReader(open(_find(pmc_dir, "counter_collection.csv"))):
+        m = re.search(r"ips4o::(k_\w+<[^>]*>)", r["Kernel_Name"])
+        if not m:
+            continue
+        k = m.group(1)
+        a = acc.setdefault(k, {c: 0.0 for c in SQ_COUNTERS})
+        if r["Counter_Name"] in a:
+            a[r["Counter_Name"]] += float(r["Counter_Value"])
+        spans.setdefault(k, {})[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    out = {}
+    for k, a in acc.items():
+        ms = sum(spans[k].values())
+        cyc = ms * 1e-3 * ghz * 1e9
+        waves = next((w for pre, w in RESIDENT_WAVES if k.startswith(pre)), None)
+        out[k] = dict(a, dispatches=len(spans[k]), ms=ms,
+                      conflict=a["SQ_LDS_BANK_CONFLICT"] / (cus * cyc) if cyc else 0.0,
+                      valu=4 * a["SQ_INSTS_VALU"] / (cus * 4 * cyc) if cyc else 0.0,
+                      ldswait=a["SQ_WAIT_INST_LDS"] / (waves * cus * cyc) if cyc and waves else None)
+    return out
+
+
+def sq_summary(pmc_dir: str, command: str) -> str:
+    t = sq_table(pmc_dir)
+    out = ["# SQ counters per kernel (rocprofv3 --pmc)", "", "Command:", "", "```", command, "```", "",
+           "Counter sums over each kernel's dispatches in the run.  Shares of the kernel's time",
+           "(its dispatch durations, 256 CUs at 2.4 GHz): conflict = SQ_LDS_BANK_CONFLICT /",
+           "(256 x cycles), the part of each CU's time its LDS spent on bank conflicts; VALU =",
+           "4 x SQ_INSTS_VALU / (256 x 4 SIMDs x cycles), SIMD time issuing vector instructions",
+           "(a wave64 instruction holds its 16-lane SIMD for 4 cycles); LDS wait =",
+           "SQ_WAIT_INST_LDS / (resident waves per CU x 256 x cycles), for kernels whose",
+           "resident waves are fixed by their shape (16 per CU; 32 for the permutation).", "",
+           "| kernel | dispatches | ms | VALU insts | LDS insts | LDS bank-conflict cycles | "
+           "LDS-wait wave-cycles | conflict | VALU | LDS wait |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, v in sorted(t.items(), key=lambda kv: -kv[1]["ms"]):
+        lw = "–" if v["ldswait"] is None else f"{100 * v['ldswait']:.1f} %"
+        out.append(f"| `{k}` | {v['dispatches']} | {v['ms']:.2f} | {v['SQ_INSTS_VALU']:.3g} | "
+                   f"{v['SQ_INSTS_LDS']:.3g} | {v['SQ_LDS_BANK_CONFLICT']:.3g} | {v['SQ_WAIT_INST_LDS']:.3g} | "
+                   f"{100 * v['conflict']:.1f} % | {100 * v['valu']:.1f} % | {lw} |")
+    return "\n".join(out) + "\n"
+
+
 def traffic(fetch_dir: str, write_dir: str, copy_bytes: int):
     """Calibrated HBM bytes of every library kernel kind over the run.  Each
     counter is summed per kind over its own run; the two runs may differ by
@@ -144,6 +207,10 @@ def main(argv=None) -> int:
     s.add_argument("trace_dir")
     s.add_argument("out")
     s.add_argument("--command", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("pmc_dir")
+    q.add_argument("out")
+    q.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -154,6 +221,10 @@ def main(argv=None) -> int:
     if a.what == "stats":
         with open(a.out, "w") as f:
             f.write(stats_summary(a.trace_dir, a.command))
+        return 0
+    if a.what == "sq":
+        with open(a.out, "w") as f:
+            f.write(sq_summary(a.pmc_dir, a.command))
         return 0
     acc, sf, sw = traffic(a.fetch_dir, a.write_dir, a.copy_bytes)
     sha = source_sha()

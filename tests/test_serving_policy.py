@@ -60,3 +60,14 @@ def test_one_at_a_time_mode():
     s.queue.extend(reqs)
     assert s._take_batch()[0] == [reqs[0]]
     assert s._take_batch()[0] == [reqs[1]]
+
+
+def test_submit_refuses_tensors_it_cannot_serve():
+    """A tensor off the GPU or of an element type the server does not batch
+    is refused at submit, before anything is queued."""
+    s = server()
+    with pytest.raises(ValueError):
+        s.submit(torch.zeros(8, dtype=torch.int64), "u64")
+    with pytest.raises(ValueError):
+        s.submit(torch.zeros(8, dtype=torch.int64), "quartet")
+    assert not s.queue and s.rejected == 0

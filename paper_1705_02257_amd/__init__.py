@@ -31,9 +31,9 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",
-           "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters", "ips4o_sync",
-           "ips4o_status_string", "ips4o_last_stats", "ips4o_check_args", "ips4o_check_splitters",
-           "ips4o_last_kernel_stats"]
+           "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
+           "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
+           "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments"]
 
 
 class Ips4oError(RuntimeError):
@@ -248,6 +248,36 @@ def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np
     if like is not None:
         raw = raw.view(like.dtype).reshape((nu.value,) + like.shape[1:])
     return raw, bool(eq.value)
+
+
+def _raw_addr(x):
+    """Address for the argument checks, which only inspect it (NULL and
+    alignment): a tensor's data_ptr(), an int, or None."""
+    if x is None or isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def ips4o_check_args(data, n, dtype, params=None) -> int:
+    """The status ips4o_sort would return for these arguments (0 when they
+    are valid); no GPU needed."""
+    return _L().ips4o_check_args(_raw_addr(data), n, _dtype(dtype), _params(params))
+
+
+def ips4o_check_segments(data, dtype, offsets, params=None) -> int:
+    """The status ips4o_sort_segmented would return for these arguments."""
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nseg = max(offs.shape[0] - 1, 0)
+    return _L().ips4o_check_segments(_raw_addr(data), _dtype(dtype), offs.ctypes.data if nseg else None,
+                                     nseg, _params(params))
+
+
+def ips4o_check_splitters(splitters: np.ndarray, dtype, equality_buckets) -> int:
+    """The status ips4o_distribute / ips4o_classify would return for these
+    caller-given splitters (host array of num_splitters elements)."""
+    sp = np.ascontiguousarray(splitters)
+    m = sp.shape[0]
+    return _L().ips4o_check_splitters(sp.ctypes.data if m else None, m, _dtype(dtype), int(equality_buckets))
 
 
 def ips4o_sync(h, stream=None) -> None:

@@ -37,6 +37,14 @@ def test_library_exports_every_declared_symbol(ips):
         assert hasattr(lib, name), name
 
 
+def test_binding_lists_and_wraps_the_declared_api(ips):
+    """The binding's export list is the header's, and each name has a
+    Python function of the same name."""
+    assert sorted(ips.EXPORTS) == declared_functions()
+    for name in declared_functions():
+        assert callable(getattr(ips, name)), name
+
+
 def test_library_is_gfx950_code():
     """The offload bundle of the built library targets gfx950 only."""
     blob = open(os.path.join(ROOT, "paper_1705_02257_amd", "libips4o.so"), "rb").read()
@@ -159,3 +167,16 @@ def test_tensor_arguments_checked_before_the_library(ips):
         ips._addr(torch.zeros(4, dtype=torch.int64))
     with pytest.raises(ValueError):
         ips.ips4o_sort(None, torch.zeros(4, dtype=torch.int64), 4, "u64")
+
+
+def test_check_wrappers(ips):
+    """The Python check functions return the library's statuses."""
+    assert ips.ips4o_check_args(0x1000, 1 << 20, "u64") == 0
+    assert ips.ips4o_check_args(None, 5, "u64") == -1
+    assert ips.ips4o_check_args(0x1000, 100, "u64", {"k": 3}) == -1
+    assert ips.ips4o_check_segments(0x1000, "u64", [0, 50, 100]) == 0
+    assert ips.ips4o_check_segments(0x1000, "u64", [0, 50, 40, 100]) == -1
+    assert ips.ips4o_check_segments(None, "u64", []) == 0
+    assert ips.ips4o_check_splitters(np.array([1, 2, 2, 3], np.uint64), "u64", True) == 0
+    assert ips.ips4o_check_splitters(np.array([3, 1], np.uint64), "u64", False) == -1
+    assert ips.ips4o_check_splitters(np.array([], np.uint64), "u64", False) == -1

@@ -122,11 +122,6 @@ struct Carve {  // sequential sub-allocation with 256-byte alignment
     static size_t size_of(size_t off, size_t bytes) { return ((off + 255) & ~(size_t)255) + bytes; }
 };
 
-struct Seg {
-    uint64_t off, m;
-    uint32_t grp;     // input segment it belongs to (base-case bins never span two)
-};
-
 }  // namespace
 
 enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_BASE, KK_N };
@@ -803,29 +798,6 @@ int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>
     return rc;
 }
 
-// Base-case segments are packed into bins of at most `cap` consecutive
-// elements as a level lists them (in array order).  A bin spans whole
-// buckets of one level: the buckets of one partition hold disjoint key
-// ranges in ascending order, and whatever lies between two listed segments
-// of a level is already final (equality buckets, buckets of at most one
-// element) or is a bucket larger than `cap` (which no bin can span), so
-// sorting the span sorts each bucket in place exactly as sorting them one
-// by one would.  `first` is the index of the level's first bin.  A bin
-// holds buckets of one input segment only (`grp`, parallel to the bins).
-void add_to_bins(std::vector<SegD>& bins, std::vector<uint32_t>& grp, size_t first, uint64_t off, uint64_t len,
-                 uint32_t cap, uint32_t g) {
-    if (bins.size() > first && grp.back() == g) {
-        SegD& cur = bins.back();
-        const uint64_t end = off + len;
-        if (end - cur.off <= cap) {
-            cur.len = (uint32_t)(end - cur.off);
-            return;
-        }
-    }
-    bins.push_back(SegD{off, (uint32_t)len, 0});
-    grp.push_back(g);
-}
-
 // Base-case bins larger than half the capacity are sorted by one
 // workgroup of BNT threads per CU; the others by workgroups of BNT/2
 // threads holding half the LDS, two per CU, so that one workgroup's
@@ -962,13 +934,11 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     // subproblems within the base-case capacity go there at once, each in
     // a bin of its own
     std::vector<SegD> base;
-    std::vector<uint32_t> bgrp;
     std::vector<Seg> cur;
     for (const Seg& sg : init) {
         if (sg.m <= 1) continue;
         if (sg.m <= R.cap) {
             base.push_back(SegD{sg.off, (uint32_t)sg.m, 0});
-            bgrp.push_back(sg.grp);
             h->last.elements_base += sg.m;
         } else {
             cur.push_back(sg);
@@ -1024,35 +994,23 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         const TaskS* ts = (const TaskS*)(rp + 256);
         const uint64_t* bounds = (const uint64_t*)(rp + 256 + T * sizeof(TaskS));
         std::vector<Seg> next;
-        const size_t first_bin = base.size();
         base.reserve(base.size() + L.total_slots);
+        const uint64_t bin_cap = std::min(R.cap, small_bin_cap<DT>());
         for (size_t t = 0; t < T; ++t) {
             const TaskD& td = L.tasks[t];
             const uint64_t* bd = bounds + td.slot_begin + t;
             const uint32_t K = ts[t].K;
-            if (K == 0 || K > (uint32_t)KMAX || bd[0] != 0 || bd[K] != td.m) {
-                (void)check_device_error(h, st);
-                return IPS4O_ERR_DEVICE_FAULT;
-            }
             if (log_enabled() && t < 64)
                 std::fprintf(stderr, "[ips4o]   level %u task %zu off %llu m %llu k %u alpha %u K %u eq %u stripes %u\n",
                              level, t, (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, K,
                              ts[t].eq, td.nstripes);
-            for (uint32_t i = 0; i < K; ++i) {
-                if (bd[i + 1] < bd[i]) {
-                    (void)check_device_error(h, st);
-                    return IPS4O_ERR_DEVICE_FAULT;
-                }
-                const uint64_t sz = bd[i + 1] - bd[i];
-                if (sz <= 1) continue;
-                if (ts[t].eq && (i & 1)) continue;          // equality bucket: all keys equal
-                const uint64_t off = td.off + bd[i];
-                if (sz <= R.cap) {
-                    add_to_bins(base, bgrp, first_bin, off, sz, std::min(R.cap, small_bin_cap<DT>()), cur[t].grp);
-                    h->last.elements_base += sz;
-                }
-                else next.push_back(Seg{off, sz, cur[t].grp});
+            uint64_t eb = 0;
+            if (K > (uint32_t)KMAX ||
+                !split_task(td.off, td.m, cur[t].grp, K, ts[t].eq != 0, bd, R.cap, bin_cap, base, next, &eb)) {
+                (void)check_device_error(h, st);
+                return IPS4O_ERR_DEVICE_FAULT;
             }
+            h->last.elements_base += eb;
         }
         cur.swap(next);
         ++level;

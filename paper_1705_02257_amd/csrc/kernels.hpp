@@ -25,6 +25,7 @@
 #pragma once
 #include <type_traits>
 
+#include "planner.hpp"
 #include "traits.hpp"
 
 namespace ips4o {
@@ -1690,12 +1691,6 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
 // workgroup's LDS (u64/f64 sort the keys themselves, f64 through the
 // bijective totalOrder image; records sort (key, index) items and then
 // gather whole records from a per-workgroup scratch copy of the segment).
-struct SegD {
-    uint64_t off;
-    uint32_t len;
-    uint32_t pad;
-};
-
 template <class Key>
 struct KeyIdx {
     Key k;

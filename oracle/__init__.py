@@ -45,6 +45,8 @@ def _load():
         L.or_sort.argtypes = [vp, u64, i32]; L.or_sort.restype = i32
         L.or_compare.argtypes = [vp, vp, i32]; L.or_compare.restype = i32
         L.or_sort_segmented.argtypes = [vp, vp, u32, i32]; L.or_sort_segmented.restype = i32
+        L.or_sort_small_integers.argtypes = [vp, u64, i32, u64, vp]
+        L.or_sort_small_integers.restype = i32
         L.or_bucket.argtypes = [vp, i32, vp, u32, i32]; L.or_bucket.restype = u32
         L.or_num_buckets.argtypes = [i32, vp, u32, i32]; L.or_num_buckets.restype = u32
         L.or_classify.argtypes = [vp, u64, i32, vp, u32, i32, vp]; L.or_classify.restype = i32
@@ -87,6 +89,90 @@ def sort_segmented(arr: np.ndarray, offsets, dtype: str) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"or_sort_segmented: {rc}")
     return out
+
+
+def sort_small_integers(arr: np.ndarray, dtype: str, vmax: int) -> np.ndarray:
+    """Sorted copy of u64/f64 keys that are all integers in [0, vmax), by
+    counting (or_sort_small_integers); raises ValueError otherwise."""
+    out = np.ascontiguousarray(arr).copy()
+    counts = np.empty(max(int(vmax), 1), dtype=np.uint32)
+    rc = _load().or_sort_small_integers(_ptr(out), _n(out), DTYPES[dtype], int(vmax), counts.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"or_sort_small_integers: {rc}")
+    return out
+
+
+_TOP = np.uint64(1 << 63)
+_CHUNK = 1 << 24
+
+
+def sort_total_order_np(arr: np.ndarray, dtype: str) -> np.ndarray:
+    """Sorted copy of u64 or f64 keys with numpy's sort as the one library
+    step (fast enough for 2^30 keys).  u64: numpy's unsigned order.  f64:
+    IEEE 754 totalOrder through its order-preserving image as an unsigned
+    integer -- a negative-signed pattern has all its bits flipped (larger
+    magnitudes become smaller images), a positive-signed one only its sign
+    bit (placing it above every negative one) -- sorted, then mapped back;
+    a second statement of the order that or_compare writes out by cases."""
+    if dtype == "u64":
+        out = np.ascontiguousarray(arr, dtype=np.uint64).copy()
+        out.sort(kind="stable")
+        return out
+    if dtype != "f64":
+        raise ValueError(dtype)
+    bits = np.ascontiguousarray(arr).view(np.uint64)
+    img = np.empty_like(bits)
+    for a in range(0, bits.shape[0], _CHUNK):
+        x = bits[a:a + _CHUNK]
+        flip = (x.view(np.int64) >> np.int64(63)).view(np.uint64) | _TOP     # all ones, or the sign bit
+        np.bitwise_xor(x, flip, out=img[a:a + _CHUNK])
+    img.sort(kind="stable")
+    for a in range(0, img.shape[0], _CHUNK):
+        y = img[a:a + _CHUNK]
+        flip = (~(y.view(np.int64) >> np.int64(63))).view(np.uint64) | _TOP  # sign bit, or all ones
+        np.bitwise_xor(y, flip, out=y)
+    return img.view(np.float64)
+
+
+def _nondecreasing(keys: np.ndarray, dtype: str) -> bool:
+    if keys.shape[0] < 2:
+        return True
+    if dtype == "u64":
+        k = keys.view(np.uint64)
+    else:
+        b = keys.view(np.uint64)
+        k = b ^ ((b.view(np.int64) >> np.int64(63)).view(np.uint64) | _TOP)
+    for a in range(0, k.shape[0] - 1, _CHUNK):
+        seg = k[a:a + _CHUNK + 1]
+        if not bool(np.all(seg[1:] >= seg[:-1])):
+            return False
+    return True
+
+
+def expected_sorted(dist: str, dtype: str, n: int, seed: int) -> np.ndarray:
+    """The sorted arrangement of workloads.generate(dist, dtype, n, seed)
+    for u64/f64 keys by a route that stays fast at 2^30 keys (the inputs of
+    Section 5, Experimental Results):
+      uniform, exponential  numpy's sort (sort_total_order_np);
+      sorted, reverse, almost  ReverseSorted is Sorted read backwards and
+                  AlmostSorted is Sorted with pairs swapped, so the sorted
+                  arrangement of all three is the Sorted sequence of the same
+                  seed (checked to be non-decreasing here);
+      ones, rootdup, twodup, eightdup  integers below n: counting
+                  (sort_small_integers)."""
+    import workloads
+    if dtype not in ("u64", "f64"):
+        raise ValueError(dtype)
+    if dist in ("uniform", "exponential"):
+        return sort_total_order_np(workloads.generate(dist, dtype, n, seed), dtype)
+    if dist in ("sorted", "reverse", "almost"):
+        out = workloads.generate("sorted", dtype, n, seed)
+        if not _nondecreasing(out, dtype):
+            raise ValueError("the Sorted input is not non-decreasing")
+        return out
+    if dist in ("ones", "rootdup", "twodup", "eightdup"):
+        return sort_small_integers(workloads.generate(dist, dtype, n, seed), dtype, max(n, 2))
+    raise ValueError(dist)
 
 
 def compare(a: np.ndarray, b: np.ndarray, dtype: str) -> int:

@@ -101,6 +101,49 @@ int or_sort(void *data, uint64_t n, int dtype) {
     return 0;
 }
 
+/* The non-decreasing arrangement (Section 1) of n keys that are all
+ * integers in [0, vmax): u64 values, or f64 values whose bit pattern is that
+ * of such an integer converted to binary64 (so no -0, NaN or fraction).  Such
+ * keys compare as the integers they hold under either order, so the sorted
+ * arrangement holds every value v exactly count(v) times, in increasing v:
+ * count, then write out (no comparisons).  This is how the integer-valued
+ * inputs of Section 5 (Ones, RootDup, TwoDup, EightDup: values below n) are
+ * sorted at sizes where qsort takes minutes.  counts: caller buffer of vmax
+ * uint32.  Returns 0; -1 for a dtype other than u64/f64 or n >= 2^32; -2 when
+ * a key is not such an integer (the data is then unchanged). */
+int or_sort_small_integers(void *data, uint64_t n, int dtype, uint64_t vmax, uint32_t *counts) {
+    if ((dtype != OR_U64 && dtype != OR_F64) || n >= (1ULL << 32)) return -1;
+    unsigned char *d = (unsigned char *)data;
+    for (uint64_t v = 0; v < vmax; ++v) counts[v] = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t bits = ld64(d + 8 * i), v;
+        if (dtype == OR_U64) {
+            v = bits;
+            if (v >= vmax) return -2;
+        } else {
+            double x;
+            memcpy(&x, &bits, 8);
+            if (!(x >= 0.0 && x < (double)vmax)) return -2;
+            v = (uint64_t)x;
+            double back = (double)v;
+            uint64_t bb;
+            memcpy(&bb, &back, 8);
+            if (bb != bits) return -2;
+        }
+        counts[v]++;
+    }
+    uint64_t at = 0;
+    for (uint64_t v = 0; v < vmax; ++v) {
+        uint64_t bits = v;
+        if (dtype == OR_F64) {
+            double x = (double)v;
+            memcpy(&bits, &x, 8);
+        }
+        for (uint32_t c = 0; c < counts[v]; ++c, ++at) memcpy(d + 8 * at, &bits, 8);
+    }
+    return 0;
+}
+
 /* Many independent problems (the subproblems of Section 4, given by the
  * caller): segment i is A[offs[i] .. offs[i+1]), each sorted on its own by
  * the problem statement above; elements outside [offs[0], offs[nseg]) are

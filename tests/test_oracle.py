@@ -389,3 +389,87 @@ def test_generator_records_payload(workloads_mod):
     for j in range(2, 10):
         v = (v << np.uint64(8)) | b[:, j].astype(np.uint64)
     assert np.array_equal(v, np.arange(n, dtype=np.uint64) % math.isqrt(n))
+
+
+# ------------------------------------- fast routes to the sorted output
+# The full-size checks (2^30 keys) need the oracle's sorted arrangement in
+# seconds; these routes are pinned here against brute force, the totalOrder
+# listing, closed forms of the inputs and the qsort route.
+@pytest.mark.parametrize("dtype", ["u64", "f64"])
+def test_small_integers_brute_force(oracle_mod, dtype):
+    """Counting sort of small integers: every array over {0, 1, 2} up to
+    n = 5 and every permutation of 6 distinct values sorts to the one
+    non-decreasing arrangement brute force finds."""
+    def mk(vals):
+        a = np.array(vals, dtype=np.uint64)
+        return a if dtype == "u64" else a.astype(np.float64)
+    cases = [list(c) for n in range(0, 6) for c in itertools.product(range(3), repeat=n)]
+    cases += [list(p) for p in itertools.permutations([5, 0, 3, 9, 1, 7])][::37]
+    for vals in cases:
+        arr = mk(vals)
+        got = oracle_mod.sort_small_integers(arr, dtype, 10)
+        want = np.array(sorted(vals), dtype=np.uint64)
+        want = want if dtype == "u64" else want.astype(np.float64)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), vals
+        if len(vals) <= 5:
+            good, _ = _brute_force_sorted_set(dtype, arr)
+            assert tuple(_records(dtype, got)) in good and len(set(good)) == 1
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64"])
+@pytest.mark.parametrize("n", [2, 1000, 12345, 1 << 16])
+def test_small_integers_rootdup_closed_form(oracle_mod, workloads_mod, dtype, n):
+    """RootDup A[i] = i mod m, m = floor(sqrt(n)) (Section 5): the sorted
+    output holds value v exactly floor((n - 1 - v) / m) + 1 times, in order."""
+    m = math.isqrt(n)
+    inp = workloads_mod.generate("rootdup", dtype, n, 1)
+    got = oracle_mod.sort_small_integers(inp, dtype, n).view(np.uint64)
+    reps = [(n - 1 - v) // m + 1 for v in range(m)]
+    want = np.repeat(np.arange(m, dtype=np.uint64), reps)
+    if dtype == "f64":
+        want = want.astype(np.float64).view(np.uint64)
+    assert sum(reps) == n
+    assert np.array_equal(got, want)
+
+
+def test_small_integers_refuses_other_keys(oracle_mod):
+    """Keys that are not integers below vmax (a fraction, -0, NaN, a value
+    at vmax) are refused and the input is left as it was."""
+    for bad in ([1.0, 1.5], [0.0, -0.0], [2.0, float("nan")], [3.0, 10.0]):
+        arr = np.array(bad, dtype=np.float64)
+        with pytest.raises(ValueError):
+            oracle_mod.sort_small_integers(arr, "f64", 10)
+    with pytest.raises(ValueError):
+        oracle_mod.sort_small_integers(np.array([3, 10], dtype=np.uint64), "u64", 10)
+
+
+def test_total_order_np_listing(oracle_mod):
+    """The numpy totalOrder route puts the special binary64 values in the
+    order of the IEEE 754 totalOrder listing, from any starting order, and
+    agrees with brute force on permutations of six of them."""
+    listing = np.array(F64_ORDER, dtype=np.uint64)
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        shuffled = listing[rng.permutation(listing.shape[0])].view(np.float64)
+        got = oracle_mod.sort_total_order_np(shuffled, "f64").view(np.uint64)
+        assert np.array_equal(got, listing)
+    idx = [0, 3, len(F64_ORDER) // 2, len(F64_ORDER) - 4, len(F64_ORDER) - 1, 5]
+    for perm in itertools.permutations(idx):
+        arr = _mk("f64", list(perm))
+        good, _ = _brute_force_sorted_set("f64", arr)
+        got = oracle_mod.sort_total_order_np(arr, "f64")
+        assert tuple(_records("f64", got)) in good
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64"])
+@pytest.mark.parametrize("dist", ["uniform", "exponential", "sorted", "reverse", "almost", "ones",
+                                  "rootdup", "twodup", "eightdup"])
+@pytest.mark.parametrize("n", [1, 2, 1000, (1 << 16) + 3])
+def test_expected_sorted_matches_qsort(oracle_mod, workloads_mod, dtype, dist, n):
+    """For every input distribution of Section 5 the fast route to the
+    sorted output equals the qsort route (or_sort) bit for bit."""
+    seed = workloads_mod.seed_for(1, dist, dtype)
+    inp = workloads_mod.generate(dist, dtype, n, seed)
+    want = oracle_mod.sort(inp, dtype)
+    got = oracle_mod.expected_sorted(dist, dtype, n, seed)
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))

@@ -32,6 +32,7 @@ int or_select_splitters(const void *data, uint64_t n, int dtype, uint32_t k, uin
                         void *scratch, void *out, uint32_t *m_unique, int *eq);
 void or_tree(const uint64_t *s, uint32_t k, uint64_t *a);
 uint32_t or_tree_descend(const uint64_t *a, uint32_t k, uint64_t e);
+int or_sort_small_integers(void *data, uint64_t n, int dtype, uint64_t vmax, uint32_t *counts);
 
 static uint64_t st = 0x9E3779B97F4A7C15ull;
 static uint64_t rnd(void) { st ^= st << 13; st ^= st >> 7; st ^= st << 17; return st; }
@@ -113,6 +114,25 @@ int main(void) {
         }
         free(sp); free(a);
     }
+    /* counting sort of small integers (u64 and integer-valued f64), sizes
+       0 .. 1001 with vmax down to 1, and a refused key */
+    for (int dt = 0; dt < 2; ++dt)
+        for (size_t zi = 0; zi < sizeof sizes / sizeof sizes[0]; ++zi) {
+            const uint64_t n = sizes[zi], vmax = 1 + rnd() % 40;
+            uint64_t *d = malloc(n * 8 + 8);
+            uint32_t *cnt = malloc(vmax * sizeof *cnt);
+            for (uint64_t i = 0; i < n; ++i) {
+                const uint64_t v = rnd() % vmax;
+                if (dt == 0) d[i] = v; else { double x = (double)v; memcpy(&d[i], &x, 8); }
+            }
+            if (or_sort_small_integers(d, n, dt, vmax, cnt) != 0) FAIL("or_sort_small_integers");
+            if (!sorted((unsigned char *)d, n, 8, dt)) FAIL("small integers order");
+            if (n > 0) {
+                if (dt == 0) d[n - 1] = vmax; else { double x = 0.5; memcpy(&d[n - 1], &x, 8); }
+                if (or_sort_small_integers(d, n, dt, vmax, cnt) != -2) FAIL("a bad key accepted");
+            }
+            free(d); free(cnt);
+        }
     printf("ok\n");
     return 0;
 }

@@ -249,6 +249,25 @@ typedef struct {
 
 int ips4o_last_kernel_stats(const ips4o_handle *h, ips4o_kernel_stat *out);
 
+/* The same device time and algorithmic bytes per pass over the data of the
+ * most recent call made with IPS4O_FLAG_TIMING (none otherwise): one entry
+ * per distribution level (Section 4: sampling, classification, empty-block
+ * movement, permutation and cleanup of every subproblem of that level),
+ * then one for the base case if it ran (base_case = 1).  elements: the
+ * elements the pass partitioned or sorted.  Up to max_passes entries are
+ * written to out (host); *num_passes (host) receives the number of passes
+ * the call made. */
+typedef struct {
+    uint32_t launches;
+    uint32_t base_case;
+    double ms;
+    double alg_bytes;
+    uint64_t elements;
+} ips4o_pass_stat;
+
+int ips4o_last_pass_stats(const ips4o_handle *h, ips4o_pass_stat *out, uint32_t max_passes,
+                          uint32_t *num_passes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,7 +116,7 @@ def sort_total_order_np(arr: np.ndarray, dtype: str) -> np.ndarray:
     a second statement of the order that or_compare writes out by cases."""
     if dtype == "u64":
         out = np.ascontiguousarray(arr, dtype=np.uint64).copy()
-        out.sort(kind="stable")
+        out.sort()
         return out
     if dtype != "f64":
         raise ValueError(dtype)
@@ -126,7 +126,7 @@ def sort_total_order_np(arr: np.ndarray, dtype: str) -> np.ndarray:
         x = bits[a:a + _CHUNK]
         flip = (x.view(np.int64) >> np.int64(63)).view(np.uint64) | _TOP     # all ones, or the sign bit
         np.bitwise_xor(x, flip, out=img[a:a + _CHUNK])
-    img.sort(kind="stable")
+    img.sort()
     for a in range(0, img.shape[0], _CHUNK):
         y = img[a:a + _CHUNK]
         flip = (~(y.view(np.int64) >> np.int64(63))).view(np.uint64) | _TOP  # sign bit, or all ones

@@ -33,6 +33,7 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
+           "ips4o_last_pass_stats",
            "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments"]
 
 
@@ -65,6 +66,11 @@ class KernelStat(ctypes.Structure):
                 ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
 
 
+class PassStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint32), ("base_case", ctypes.c_uint32),
+                ("ms", ctypes.c_double), ("alg_bytes", ctypes.c_double), ("elements", ctypes.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -90,10 +96,11 @@ def _load():
     L.ips4o_status_string.restype = ctypes.c_char_p
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
+    L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
     for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
-                 "ips4o_last_kernel_stats"]:
+                 "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
         getattr(L, name).restype = i32
     return L
 
@@ -296,6 +303,16 @@ def ips4o_last_kernel_stats(h) -> dict:
     _check(_L().ips4o_last_kernel_stats(h, arr), "ips4o_last_kernel_stats")
     return {name: {"launches": arr[i].launches, "ms": arr[i].ms, "alg_bytes": arr[i].alg_bytes}
             for i, name in enumerate(KERNEL_KINDS)}
+
+
+def ips4o_last_pass_stats(h) -> list:
+    """[{launches, base_case, ms, alg_bytes, elements}] per pass of the last
+    timed call: each distribution level, then the base case."""
+    num = ctypes.c_uint32(0)
+    _check(_L().ips4o_last_pass_stats(h, None, 0, ctypes.byref(num)), "ips4o_last_pass_stats")
+    arr = (PassStat * max(1, num.value))()
+    _check(_L().ips4o_last_pass_stats(h, arr, num.value, ctypes.byref(num)), "ips4o_last_pass_stats")
+    return [{f: getattr(arr[i], f) for f, _ in PassStat._fields_} for i in range(num.value)]
 
 
 _handles = {}

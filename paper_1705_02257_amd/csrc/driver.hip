@@ -144,6 +144,7 @@ struct ips4o_handle {
     uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
+    std::vector<ips4o_pass_stat> pstats;   // per distribution level, then the base case
     std::vector<hipEvent_t> events;   // pool for IPS4O_FLAG_TIMING
     hipError_t last_hip = hipSuccess;
 };
@@ -157,12 +158,20 @@ struct Timer {
     bool on;
     struct Rec {
         int kind;
+        uint32_t pass;
         size_t e0;
         double bytes;
     };
     std::vector<Rec> recs;
     size_t used = 0;
+    uint32_t pass = 0;                 // distribution level of the launches recorded now
+    std::vector<uint64_t> pass_elems;  // elements partitioned / sorted per pass
     Timer(ips4o_handle* hh, hipStream_t s, bool enabled) : h(hh), st(s), on(enabled) {}
+    void set_pass(uint32_t p, uint64_t elements) {
+        pass = p;
+        if (pass_elems.size() <= p) pass_elems.resize(p + 1, 0);
+        pass_elems[p] += elements;
+    }
     hipEvent_t ev(size_t i) {
         while (h->events.size() <= i) {
             hipEvent_t e;
@@ -176,7 +185,7 @@ struct Timer {
         hipEvent_t e = ev(used);
         if (!e || !ev(used + 1)) { on = false; return -1; }
         (void)hipEventRecord(e, st);
-        recs.push_back(Rec{kind, used, 0.0});
+        recs.push_back(Rec{kind, pass, used, 0.0});
         used += 2;
         return (int)recs.size() - 1;
     }
@@ -191,7 +200,10 @@ struct Timer {
     // after the stream has been synchronized
     void finish() {
         for (auto& k : h->kstats) k = ips4o_kernel_stat{};
+        h->pstats.clear();
         if (!on) return;
+        h->pstats.resize(pass_elems.size());
+        for (size_t p = 0; p < pass_elems.size(); ++p) h->pstats[p].elements = pass_elems[p];
         for (const Rec& r : recs) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, h->events[r.e0], h->events[r.e0 + 1]) != hipSuccess) ms = 0.f;
@@ -199,6 +211,13 @@ struct Timer {
             k.launches += 1;
             k.ms += ms;
             k.alg_bytes += r.bytes;
+            if (r.pass < h->pstats.size()) {
+                ips4o_pass_stat& ps = h->pstats[r.pass];
+                ps.launches += 1;
+                ps.ms += ms;
+                ps.alg_bytes += r.bytes;
+                ps.base_case = r.kind == KK_BASE ? 1u : 0u;
+            }
         }
     }
 };
@@ -870,6 +889,7 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     c.data = (Elem*)d_data;
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
+    tm.set_pass((uint32_t)tm.pass_elems.size(), (uint64_t)elems);   // the pass after the last level
     SegD* d_segs = (SegD*)h->segs.p;
     SegD* fail = d_segs + list.size();
     uint32_t* nfail = (uint32_t*)((char*)h->misc.p + kFailCounts);
@@ -968,6 +988,11 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         carve_level<DT>(L, work.p, h->misc.p, d_data, R, level);
         rc = prepare_rflag<DT>(h, L, n_end, R.b, st);
         if (rc) return rc;
+        {
+            uint64_t lm = 0;
+            for (const Seg& sg : cur) lm += sg.m;
+            tm.set_pass(level, lm);
+        }
         marks.emplace_back();
         rc = launch_level_head<DT>(h, L, st, nullptr, tm, check, par ? &h->hdesc2 : &h->hdesc);
         if (rc) return rc;
@@ -1098,6 +1123,7 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     if (rc) return rc;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     LevelMarks mk;
+    tm.set_pass(0, n);
     rc = run_level<DT>(h, L, st, &ht, tm, mk, (R.flags & IPS4O_FLAG_CHECK) != 0);
     if (rc) return rc;
     std::vector<TaskS> ts;
@@ -1421,6 +1447,13 @@ const char* ips4o_status_string(int status) {
 int ips4o_last_kernel_stats(const ips4o_handle* h, ips4o_kernel_stat* out) {
     if (!h || !out) return IPS4O_ERR_INVALID_ARG;
     for (int i = 0; i < KK_N; ++i) out[i] = h->kstats[i];
+    return IPS4O_OK;
+}
+
+int ips4o_last_pass_stats(const ips4o_handle* h, ips4o_pass_stat* out, uint32_t max_passes, uint32_t* num_passes) {
+    if (!h || !num_passes || (max_passes > 0 && !out)) return IPS4O_ERR_INVALID_ARG;
+    *num_passes = (uint32_t)h->pstats.size();
+    for (uint32_t i = 0; i < max_passes && i < h->pstats.size(); ++i) out[i] = h->pstats[i];
     return IPS4O_OK;
 }
 

@@ -391,6 +391,26 @@ def test_generator_records_payload(workloads_mod):
     assert np.array_equal(v, np.arange(n, dtype=np.uint64) % math.isqrt(n))
 
 
+def test_generator_range_is_a_slice(workloads_mod):
+    """Chunked generation (used to upload inputs too large to hold whole on
+    the host) gives exactly the slice of the whole array; AlmostSorted, whose
+    swaps reach across the array, is refused in parts."""
+    n = 50021
+    for dist in workloads_mod.DISTRIBUTIONS:
+        for dtype in workloads_mod.DTYPES:
+            whole = workloads_mod.generate(dist, dtype, n, 31)
+            if dist == "almost":
+                with pytest.raises(ValueError):
+                    workloads_mod.generate_range(dist, dtype, n, 31, 1, 10)
+                assert np.array_equal(workloads_mod.generate_range(dist, dtype, n, 31, 0, n), whole)
+                continue
+            parts = [workloads_mod.generate_range(dist, dtype, n, 31, f, min(7001, n - f))
+                     for f in range(0, n, 7001)]
+            assert np.array_equal(np.concatenate(parts), whole), (dist, dtype)
+    with pytest.raises(ValueError):
+        workloads_mod.generate_range("uniform", "u64", n, 31, n - 5, 6)
+
+
 # ------------------------------------- fast routes to the sorted output
 # The full-size checks (2^30 keys) need the oracle's sorted arrangement in
 # seconds; these routes are pinned here against brute force, the totalOrder

@@ -49,6 +49,9 @@ def _load():
         lib.wl_generate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                     ctypes.c_uint64, ctypes.c_void_p]
         lib.wl_generate.restype = ctypes.c_int
+        lib.wl_generate_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+        lib.wl_generate_range.restype = ctypes.c_int
         lib.wl_splitmix64_at.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.wl_splitmix64_at.restype = ctypes.c_uint64
         _lib = lib
@@ -78,6 +81,20 @@ def generate(dist: str, dtype: str, n: int, seed: int, out: np.ndarray = None) -
                              arr.ctypes.data if n else None)
     if rc != 0:
         raise ValueError(f"wl_generate failed for {dist}/{dtype}/{n}")
+    return arr
+
+
+def generate_range(dist: str, dtype: str, n: int, seed: int, first: int, count: int,
+                   out: np.ndarray = None) -> np.ndarray:
+    """Elements first .. first+count-1 of generate(dist, dtype, n, seed),
+    produced without the rest (AlmostSorted only whole: its swaps reach
+    across the array)."""
+    arr = empty(dtype, count) if out is None else out
+    assert arr.flags["C_CONTIGUOUS"] and arr.nbytes == count * ELEM_BYTES[dtype]
+    rc = _load().wl_generate_range(DISTRIBUTIONS.index(dist), DTYPES[dtype], n, seed & (2**64 - 1), first,
+                                   count, arr.ctypes.data if count else None)
+    if rc != 0:
+        raise ValueError(f"wl_generate_range failed for {dist}/{dtype}/{n}/{first}+{count}")
     return arr
 
 

@@ -134,19 +134,26 @@ static size_t elem_size(int dtype) {
     return 0;
 }
 
-/* Fill out[0..n) (n elements of the dtype's size).  Returns 0, or -1 on a bad
- * argument.  The loop is embarrassingly parallel and split with OpenMP when
- * the library is built with it; values do not depend on the thread count. */
-int wl_generate(int dist, int dtype, uint64_t n, uint64_t seed, void *out) {
-    if (dist < 0 || dist >= WL_NDIST || elem_size(dtype) == 0 || (n && !out)) return -1;
-    if (n == 0) return 0;
+/* Fill out[0..count) with elements first .. first+count-1 of the n-element
+ * array (n elements of the dtype's size in all).  Every element depends only
+ * on n, the seed and its own index, except for AlmostSorted, whose swaps
+ * reach across the whole array: that one is produced only whole
+ * (first = 0, count = n).  Returns 0, or -1 on a bad argument.  The loop is
+ * embarrassingly parallel and split with OpenMP when the library is built
+ * with it; values do not depend on the thread count. */
+int wl_generate_range(int dist, int dtype, uint64_t n, uint64_t seed, uint64_t first, uint64_t count,
+                      void *out) {
+    if (dist < 0 || dist >= WL_NDIST || elem_size(dtype) == 0 || (count && !out)) return -1;
+    if (first > n || count > n - first) return -1;
+    if (dist == WL_ALMOST && count && (first != 0 || count != n)) return -1;
+    if (count == 0) return 0;
     size_t s = elem_size(dtype);
     unsigned char *base = (unsigned char *)out;
-    int64_t nn = (int64_t)n;
+    int64_t nn = (int64_t)count;
 #pragma omp parallel for schedule(static)
     for (int64_t ii = 0; ii < nn; ++ii) {
-        uint64_t i = (uint64_t)ii, p = src_index(dist, n, i);
-        unsigned char *e = base + i * s;
+        uint64_t i = first + (uint64_t)ii, p = src_index(dist, n, i);
+        unsigned char *e = base + (uint64_t)ii * s;
         if (dtype == WL_U64) {
             uint64_t v = value_u64(dist, n, seed, p); memcpy(e, &v, 8);
         } else if (dtype == WL_F64) {
@@ -179,4 +186,11 @@ int wl_generate(int dist, int dtype, uint64_t n, uint64_t seed, void *out) {
     }
     if (dist == WL_ALMOST) apply_swaps(base, n, s, seed);
     return 0;
+}
+
+/* Fill out[0..n) (n elements of the dtype's size).  Returns 0, or -1 on a bad
+ * argument. */
+int wl_generate(int dist, int dtype, uint64_t n, uint64_t seed, void *out) {
+    if (n && !out) return -1;
+    return wl_generate_range(dist, dtype, n, seed, 0, n, out);
 }

@@ -79,8 +79,8 @@ typedef enum {
  *   stripes     classification workgroups for the first level (default:
  *               chosen from n).
  *   workers     permutation workers (wavefronts) per level, rounded up to a
- *               multiple of four (default 8192: one round of the permutation
- *               kernel's workgroups on the device).  A level shares them
+ *               multiple of four, at most 16380 (default 8192: one round of
+ *               the permutation kernel's workgroups on the device).  A level shares them
  *               among its subproblems in groups of four, in proportion to
  *               their blocks, at least one group each (so a level with more
  *               subproblems than groups uses more).

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libips4o.so")
 SOURCES = [os.path.join(HERE, "csrc", "driver.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "traits.hpp"),
+           os.path.join(HERE, "csrc", "planner.hpp"), os.path.join(HERE, "csrc", "wrword.hpp"),
            os.path.join(ROOT, "include", "ips4o.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

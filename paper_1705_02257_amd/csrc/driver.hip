@@ -134,14 +134,12 @@ struct ips4o_handle {
     Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
-    Arena rflag;      // permutation read marks, one word per block of the array
     HostArena hbounds;    // pinned copy of a level's error word, task state and bounds (even levels)
     HostArena hbounds2;   // the same for odd levels
     HostArena hdesc;      // pinned staging of a level's descriptors (even levels)
     HostArena hdesc2;     // the same for odd levels
     hipEvent_t scanned[2] = {nullptr, nullptr};   // a level's bounds have reached the host
     HostArena hsegs;      // pinned staging of the base-case bin list
-    uint32_t epoch = 0;   // last mark handed out; rflag holds only smaller ones
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
     std::vector<ips4o_pass_stat> pstats;   // per distribution level, then the base case
@@ -259,6 +257,8 @@ int resolve(const ips4o_params* p, Resolved* r) {
     r->alpha_x100 = d.alpha_x100;
     r->stripes = d.stripes;
     if (d.stripes > STRIPES_PER_TASK_MAX) return IPS4O_ERR_INVALID_ARG;
+    // every worker of a task may count as a reader of one bucket at once
+    if (d.workers > (WR_MAX_READERS & ~3u)) return IPS4O_ERR_INVALID_ARG;
     r->workers = d.workers ? ((d.workers + 3) & ~3u) : kDefaultWorkers;
     r->flags = d.flags;
     r->spin = d.spin_limit ? d.spin_limit : kDefaultSpin;
@@ -775,26 +775,6 @@ int reset_misc(ips4o_handle* h, hipStream_t st) {
     return IPS4O_OK;
 }
 
-// Read marks for the permutation of one level: one word per block of the
-// n-element array (block index floor(off / b) + local block, plus the
-// partial blocks at segment ends).  A fresh buffer is zeroed and every level
-// takes the next epoch, so a mark equals the level's epoch only once that
-// level has read the block.
-template <int DT>
-int prepare_rflag(ips4o_handle* h, Level<DT>& L, uint64_t n, uint32_t b, hipStream_t st) {
-    const size_t need = (size_t)(n / b + 2) * sizeof(uint32_t);
-    const void* before = h->rflag.p;
-    int rc = h->rflag.ensure(need);
-    if (rc) return rc;
-    if (h->rflag.p != before || h->epoch == 0xffffffffu) {
-        HIP_TRY(hipMemsetAsync(h->rflag.p, 0, h->rflag.bytes, st));
-        h->epoch = 0;
-    }
-    L.c.rflag = (uint32_t*)h->rflag.p;
-    L.c.epoch = ++h->epoch;
-    return IPS4O_OK;
-}
-
 // Read back the per-task state and bounds of a finished level.
 template <int DT>
 int read_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, std::vector<TaskS>& ts,
@@ -986,8 +966,6 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         rc = work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
         carve_level<DT>(L, work.p, h->misc.p, d_data, R, level);
-        rc = prepare_rflag<DT>(h, L, n_end, R.b, st);
-        if (rc) return rc;
         {
             uint64_t lm = 0;
             for (const Seg& sg : cur) lm += sg.m;
@@ -1119,8 +1097,6 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
     carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
-    rc = prepare_rflag<DT>(h, L, n, R.b, st);
-    if (rc) return rc;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     LevelMarks mk;
     tm.set_pass(0, n);
@@ -1312,7 +1288,6 @@ void ips4o_destroy(ips4o_handle* h) {
     h->misc.release();
     h->segs.release();
     h->scratch.release();
-    h->rflag.release();
     h->hbounds.release();
     h->hsegs.release();
     delete h;
@@ -1320,7 +1295,7 @@ void ips4o_destroy(ips4o_handle* h) {
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
     if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
-    *bytes = h->work.bytes + h->work2.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes + h->rflag.bytes;
+    *bytes = h->work.bytes + h->work2.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
     return IPS4O_OK;
 }
 

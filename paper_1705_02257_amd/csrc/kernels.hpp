@@ -15,7 +15,7 @@
 //                 cross stripe ends so every bucket is [full | empty]
 //                 (Appendix A, empty block movement); sets (w_i, r_i)
 //   k_permute     wavefront workers: the block permutation with atomic
-//                 read/write pointers and per-block read marks (Section 4.2)
+//                 read/write pointers and per-bucket reader counts (Section 4.2)
 //   k_cleanup     one workgroup per bucket: heads, tails, partial buffers and
 //                 the overflow block (Section 4.3)
 // and k_basecase sorts small subproblems inside LDS.
@@ -27,6 +27,7 @@
 
 #include "planner.hpp"
 #include "traits.hpp"
+#include "wrword.hpp"
 
 namespace ips4o {
 
@@ -74,8 +75,9 @@ struct TaskS {                  // device-written per task
 // two buckets share at most a cache line, and a worker's scan over 64
 // buckets reads 4 KiB (wider slots made the scans of levels with many
 // buckets a large part of the permutation's memory traffic).
+//
 struct alignas(64) BucketSlot {
-    uint64_t wr;        // (w << 32) | (r + 2^31), block indices in the segment
+    uint64_t wr;        // w, r and readers, packed as above
     uint32_t unused;
     uint32_t flag;      // unused
     uint32_t rinit;     // r at the start of the permutation (last full block)
@@ -102,8 +104,6 @@ struct Ctx {
     uint32_t* counts;           // [stripes][KMAX]
     uint32_t* stripe_full;      // [stripes] full blocks after classification
     const uint32_t* order;      // [stripes] classification launch order (largest first)
-    uint32_t* rflag;            // per block of the array: epoch of the level that read it
-    uint32_t epoch;             // this level's mark in rflag (never reused while rflag lives)
     Elem* bufs;                 // stripe bucket buffers
     Elem* ovf;                  // [tasks][b]
     uint32_t* err;              // device error word (0 = ok)
@@ -1275,24 +1275,25 @@ __global__ __launch_bounds__(NT) void k_fix_empty(Ctx<DT> c, uint32_t task0) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t prefix = first_foreign;
-        uint64_t w = d0 + prefix, r = (uint64_t)(d0 + occ) - 1 + 0x80000000ull;
-        c.slots[td.slot_begin + j].wr = (w << 32) | (r & 0xffffffffull);
+        c.slots[td.slot_begin + j].wr = wr_pack((int64_t)d0 + prefix, (int64_t)d0 + occ - 1);
         c.slots[td.slot_begin + j].rinit = d0 + occ;   // one past the last full block
     }
 }
 
 // ------------------------------------------------------ block permutation
 // Wavefront workers (Section 4.2).  A worker takes an unprocessed block from
-// its primary bucket by decrementing r_p, loads it, and then marks the block
-// as read (rflag[block] = this level's epoch); it classifies the block's
-// first element to get its destination bucket and increments w_dest: if the
-// block at the old w_dest is unprocessed it swaps (reads that block, writes
-// its own) and continues with the block it read, unless that block already
-// belongs to dest, in which case it is left in place; if the old w_dest is
-// empty it writes its block there (after the block's reader has marked it,
-// when the position held a full block at the start) and goes back to the
-// primary bucket.  (w_i, r_i) live in one 64-bit word so that every
-// update sees a consistent pair.  A worker stops after a full cycle over the
+// its primary bucket by decrementing r_p and counting itself as a reader of
+// the bucket in the same atomic, loads the block and then leaves the reader
+// count; it classifies the block's first element to get its destination
+// bucket and increments w_dest: if the block at the old w_dest is
+// unprocessed it swaps (reads that block, writes its own) and continues with
+// the block it read, unless that block already belongs to dest, in which
+// case it is left in place; if the old w_dest is empty it writes its block
+// there (when the position held a full block at the start, only once no
+// worker is reading a block of dest any more: the reader of that position
+// may still be loading it) and goes back to the primary bucket.  w, r and
+// the reader count live in one 64-bit word so that every update sees a
+// consistent state.  A worker stops after a full cycle over the
 // buckets finds no unprocessed block.  The partial last block of a segment is
 // never written in place: the overflow block stands in for it.
 template <int DT, int WPL>
@@ -1369,20 +1370,22 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
     uint32_t p = (uint32_t)(((uint64_t)lw * K) / td.nworkers);
     unsigned long long moves = 0, skips = 0;
     const uint32_t limit = c.spin_limit;
-    const uint64_t fbase = td.off / b;          // rflag index of the segment's block 0
-    const uint32_t epoch = c.epoch;
-    // claim block r_q of bucket q; on success the block is in A and marked
+    // claim block r_q of bucket q; on success the block is in A and the
+    // worker no longer counts as a reader of q
     auto try_claim = [&](uint32_t q, uint32_t& dest) -> bool {
         uint64_t old = 0;
-        if (lane == 0) old = atom_add64(&sl[q].wr, ~0ull);
+        if (lane == 0) old = atom_add64(&sl[q].wr, WR_CLAIM);
         old = bcast_u64(old);
-        const int64_t w0 = (int64_t)(old >> 32), r0 = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
-        if (r0 < w0) return false;
+        const int64_t w0 = wr_w(old), r0 = wr_r(old);
+        if (r0 < w0) {
+            if (lane == 0) (void)atom_add64(&sl[q].wr, ~0ull);     // readers - 1
+            return false;
+        }
         load_block((uint32_t)r0, A);
         compiler_fence();
-        wait_vmem();          // the block is in registers before it is marked read
+        wait_vmem();          // the block is in registers before the worker stops reading
         compiler_fence();
-        if (lane == 0) atom_store32(&c.rflag[fbase + (uint64_t)r0], epoch);
+        if (lane == 0) (void)atom_add64(&sl[q].wr, ~0ull);         // readers - 1
         dest = first_bucket(A);
         return true;
     };
@@ -1400,9 +1403,8 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
             if (q >= K) q -= K;
             bool cand = false;
             if (lane < width && scanned + lane < K) {
-                uint64_t v = atom_load64(&sl[q].wr);
-                int64_t w = (int64_t)(v >> 32), r = (int64_t)(v & 0xffffffffull) - 0x80000000ll;
-                cand = r >= w;
+                const uint64_t v = atom_load64(&sl[q].wr);
+                cand = wr_r(v) >= wr_w(v);
             }
             uint64_t mask = __ballot(cand);
             if (mask == 0) {
@@ -1422,9 +1424,9 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
         // ---- place the block, swapping along the way
         while (true) {
             uint64_t old = 0;
-            if (lane == 0) old = atom_add64(&sl[destA].wr, 1ull << 32);
+            if (lane == 0) old = atom_add64(&sl[destA].wr, WR_WONE);
             old = bcast_u64(old);
-            int64_t x = (int64_t)(old >> 32), r = (int64_t)(old & 0xffffffffull) - 0x80000000ll;
+            const int64_t x = wr_w(old), r = wr_r(old);
             if (x >= (int64_t)dl[destA + 1] || x < 0) {   // cannot happen for consistent counts
                 if (lane == 0) raise_err(c.err, ERR_PERMUTE_RANGE);
                 break;
@@ -1450,21 +1452,22 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
                 continue;
             }
             // empty block at x.  If x was a full block when the permutation
-            // started, a reader took it and may still be loading it: wait
-            // until that reader has marked it (this happens where w and r
-            // cross, at most once per bucket); blocks that were empty from
+            // started, a reader took it (r passed x before this w did) and
+            // may still be loading it: wait until the bucket has no reader.
+            // Readers that claim after this point find r < w and read
+            // nothing, so the count only falls; blocks that were empty from
             // the start were never read.
             uint32_t spins = 0;
-            while ((uint32_t)x < sl[destA].rinit) {
-                uint32_t f = 0;
-                if (lane == 0) f = atom_load32(&c.rflag[fbase + (uint64_t)x]);
-                f = bcast_u32(f);
-                if (f == epoch) break;
+            uint64_t cur = old;
+            while ((uint32_t)x < sl[destA].rinit && wr_readers(cur) != 0) {
                 if (++spins > limit) {
                     if (lane == 0) raise_err(c.err, ERR_SPIN);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
+                uint64_t v = 0;
+                if (lane == 0) v = atom_load64(&sl[destA].wr);
+                cur = bcast_u64(v);
             }
             compiler_fence();
             store_block((uint32_t)x, A);
@@ -1511,7 +1514,7 @@ __device__ inline BucketGeom bucket_geom(const Ctx<DT>& c, uint32_t t, const Tas
     g.B0 = bd[j];
     g.B1 = bd[j + 1];
     g.cs = (uint64_t)dl[j] * b;
-    const uint64_t w = c.slots[td.slot_begin + j].wr >> 32;
+    const uint64_t w = (uint64_t)wr_w(c.slots[td.slot_begin + j].wr);
     g.ovf_case = st.ovf_bucket == j;
     // with blocks the bucket holds at least b elements, so cs < B1; without
     // them the block region is empty at cs
@@ -2283,7 +2286,7 @@ __global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c, uint32_t task0)
     const uint32_t b = c.b, lkt = ilog2(st.kt);
     load_tree<DT>(c, td, st.kt, st.nuniq, tr);
     const uint32_t d0 = c.delim[td.slot_begin + t + j];
-    const uint32_t w = (uint32_t)(c.slots[td.slot_begin + j].wr >> 32);
+    const uint32_t w = (uint32_t)wr_w(c.slots[td.slot_begin + j].wr);
     const bool partial = (td.m % b) != 0;
     const typename TR::Elem* seg = c.data + td.off;
     for (uint32_t q = d0; q < w; ++q) {

@@ -1,4 +1,6 @@
-"""The host-side recursion planner (csrc/planner.hpp) on the CPU: a C++
+"""CPU programs built with g++ and the host AddressSanitizer/UBSan.
+
+The host-side recursion planner (csrc/planner.hpp) on the CPU: a C++
 program built with g++ and the host AddressSanitizer/UBSan checks how one
 level's bucket bounds become base-case bins and next-level subproblems --
 bins pairwise disjoint (they are sorted at the same time), inside their task
@@ -22,3 +24,17 @@ def test_planner_bins(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "planner ok" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_permutation_word(tmp_path):
+    """The permutation's packed (w, r, readers) word (csrc/wrword.hpp): field
+    arithmetic at every extreme and a simulated claim/read/write
+    interleaving in which a writer of a block that was full at the start
+    always sees its reader counted."""
+    exe = str(tmp_path / "wrword_check")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-o", exe, os.path.join(HERE, "wrword_check.cpp")])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "wrword ok" in r.stdout

@@ -56,6 +56,9 @@ def _load():
         L.or_select_splitters.argtypes = [vp, u64, i32, u32, u32, u64, vp, vp,
                                           ctypes.POINTER(u32), ctypes.POINTER(i32)]
         L.or_select_splitters.restype = i32
+        L.or_select_splitters_capped.argtypes = [vp, u64, i32, u32, u32, u64, u32, vp, vp,
+                                                 ctypes.POINTER(u32), ctypes.POINTER(i32)]
+        L.or_select_splitters_capped.restype = i32
         L.or_tree.argtypes = [vp, u32, vp]; L.or_tree.restype = None
         L.or_tree_descend.argtypes = [vp, u32, u64]; L.or_tree_descend.restype = u32
         _lib = L
@@ -210,15 +213,18 @@ def splitmix64_at(seed: int, i: int) -> int:
     return int(_load().or_splitmix64_at(seed & (2**64 - 1), i))
 
 
-def select_splitters(arr: np.ndarray, dtype: str, k: int, alpha: int, seed: int):
-    """(unique splitters as elements, equality flag) for k buckets, oversampling alpha."""
+def select_splitters(arr: np.ndarray, dtype: str, k: int, alpha: int, seed: int, kcap: int = 0):
+    """(unique splitters as elements, equality flag) for k buckets, oversampling
+    alpha; with kcap > 0 the bucket count is kept within kcap as
+    or_select_splitters_capped states."""
     a = np.ascontiguousarray(arr)
     shape_tail = a.shape[1:]
     scratch = np.empty((alpha * k - 1,) + shape_tail, dtype=a.dtype)
     out = np.empty((k - 1,) + shape_tail, dtype=a.dtype)
     mu = ctypes.c_uint32(0); eq = ctypes.c_int(0)
-    rc = _load().or_select_splitters(_ptr(a), _n(a), DTYPES[dtype], k, alpha, seed & (2**64 - 1),
-                                     _ptr(scratch), _ptr(out), ctypes.byref(mu), ctypes.byref(eq))
+    rc = _load().or_select_splitters_capped(_ptr(a), _n(a), DTYPES[dtype], k, alpha, seed & (2**64 - 1),
+                                            int(kcap), _ptr(scratch), _ptr(out), ctypes.byref(mu),
+                                            ctypes.byref(eq))
     if rc != 0:
         raise ValueError("select_splitters: bad arguments")
     return out[:mu.value].copy(), bool(eq.value)

@@ -270,6 +270,25 @@ int or_select_splitters(const void *data, uint64_t n, int dtype, uint32_t k, uin
     return 0;
 }
 
+/* Splitter selection for a stripe whose buffers hold at most kcap buckets
+ * (kcap = 0: no limit).  With equality buckets (Section 4, "The Case of Many
+ * Identical Keys") u unique splitters make K = 2u + 1 buckets, which can
+ * exceed the k buffers of a thread; the paper does not say what happens
+ * then.  Reading taken: when 2u + 1 > kcap, every second pick of the same
+ * sorted sample is used instead -- k/2 buckets at twice the oversampling,
+ * which draws the very same alpha*k - 1 sample elements -- and equality
+ * buckets stay on, so K <= k - 1.  Otherwise the result is
+ * or_select_splitters'. */
+int or_select_splitters_capped(const void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha,
+                               uint64_t seed, uint32_t kcap, void *scratch, void *out, uint32_t *m_unique,
+                               int *eq) {
+    int rc = or_select_splitters(data, n, dtype, k, alpha, seed, scratch, out, m_unique, eq);
+    if (rc != 0 || kcap == 0 || !*eq || 2 * *m_unique + 1 <= kcap || k < 4) return rc;
+    rc = or_select_splitters(data, n, dtype, k / 2, 2 * alpha, seed, scratch, out, m_unique, eq);
+    *eq = 1;
+    return rc;
+}
+
 /* The implicit search tree of super scalar samplesort (Section 3,
  * Preliminaries): for k a power of two and splitters s_1..s_{k-1}, the array
  * a_1..a_{k-1} is the complete binary search tree in level order with

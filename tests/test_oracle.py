@@ -352,6 +352,36 @@ def test_select_splitters_duplicates_switch_on_equality(oracle_mod, workloads_mo
     assert oracle_mod.alpha_default(2**20) == 4 and oracle_mod.alpha_default(2**30) == 6
 
 
+def test_select_splitters_capped_reading(oracle_mod, workloads_mod):
+    """Equality buckets within the buffers (reading of Section 4, "The Case of
+    Many Identical Keys", where 2u + 1 buckets can exceed the k buffers):
+    re-derived from the sorted sample with numpy -- when 2u + 1 > kcap the
+    splitters are every second pick, sample[2i*alpha - 1], deduplicated, with
+    equality buckets on; otherwise the uncapped result -- and K <= kcap."""
+    cases = 0
+    for dist, n in [("rootdup", 20000), ("twodup", 4096), ("eightdup", 9000), ("uniform", 5000), ("ones", 777)]:
+        arr = workloads_mod.generate(dist, "u64", n, seed=4)
+        for k, alpha in [(4, 1), (16, 3), (64, 2), (256, 4)]:
+            seed = 1000 + k
+            pos = [(workloads_mod.splitmix64_at(seed, i) * n) >> 64 for i in range(alpha * k - 1)]
+            sample = np.sort(arr[pos])
+            picks = [int(sample[i * alpha - 1]) for i in range(1, k)]
+            u = sorted(set(picks))
+            eq_full = len(u) < k - 1
+            sp, eq = oracle_mod.select_splitters(arr, "u64", k, alpha, seed, kcap=k)
+            if eq_full and 2 * len(u) + 1 > k:
+                half = sorted(set(int(sample[2 * i * alpha - 1]) for i in range(1, k // 2)))
+                assert eq and [int(x) for x in sp] == half, (dist, k)
+                cases += 1
+            else:
+                assert eq == eq_full and [int(x) for x in sp] == u, (dist, k)
+            nb = 2 * sp.shape[0] + 1 if eq else sp.shape[0] + 1
+            assert nb <= k
+            sp2, eq2 = oracle_mod.select_splitters(arr, "u64", k, alpha, seed, kcap=2 * k - 1)
+            assert eq2 == eq_full and [int(x) for x in sp2] == u
+    assert cases >= 4       # the thinning was exercised
+
+
 # ---------------------------------------------------------- generators
 def test_generator_closed_forms(workloads_mod):
     n = 1 << 12

@@ -30,6 +30,8 @@ int or_bucket_bounds(const void *data, uint64_t n, int dtype, const void *splitt
                      uint64_t *counts, uint64_t *bounds);
 int or_select_splitters(const void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha, uint64_t seed,
                         void *scratch, void *out, uint32_t *m_unique, int *eq);
+int or_select_splitters_capped(const void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha, uint64_t seed,
+                               uint32_t kcap, void *scratch, void *out, uint32_t *m_unique, int *eq);
 void or_tree(const uint64_t *s, uint32_t k, uint64_t *a);
 uint32_t or_tree_descend(const uint64_t *a, uint32_t k, uint64_t e);
 int or_sort_small_integers(void *data, uint64_t n, int dtype, uint64_t vmax, uint32_t *counts);
@@ -94,6 +96,10 @@ int main(void) {
                         if (or_select_splitters(d, n, dt, k, alpha, 77 + k, scr, out, &mu, &eq) != 0)
                             FAIL("or_select_splitters");
                         if (mu < 1 || mu > k - 1 || !sorted(out, mu, s, dt)) FAIL("splitters");
+                        if (or_select_splitters_capped(d, n, dt, k, alpha, 77 + k, k, scr, out, &mu, &eq) != 0)
+                            FAIL("or_select_splitters_capped");
+                        if (mu < 1 || (eq ? 2 * mu + 1 : mu + 1) > k || !sorted(out, mu, s, dt))
+                            FAIL("capped splitters");
                         free(scr); free(out);
                     }
                 }

@@ -174,7 +174,10 @@ int ips4o_classify(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,
  * positions floor(h_i * n / 2^64), h_i the i-th output of splitmix64 started
  * at `seed` (params->seed, or the default); the sample is sorted and the
  * splitters s_i = sample[i*alpha - 1], i = 1..k-1, are picked; duplicates are
- * removed and equality buckets switched on when there were any.
+ * removed and equality buckets switched on when there were any.  The first
+ * level's buffers hold min(2k, 1024) buckets: should the u unique splitters
+ * need more (2u + 1 > min(2k, 1024), only for k = 1024), every second pick of
+ * the same sorted sample is used instead and equality buckets stay on.
  * h_splitters_out: host buffer of k - 1 elements of `dtype` (whole elements;
  * only the key fields are meaningful) receiving the u unique splitters;
  * *num_unique_out and *equality_out (host) receive u and the flag.

@@ -44,6 +44,7 @@ constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by
 constexpr size_t kExactOrder = 4096;         // stripes sorted exactly by cost for the launch order
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
+constexpr uint64_t kBufBudgetDiv = 8;        // stripe buffers: at most 1/8 of the elements sorted
 
 size_t elem_size(int dt) {
     switch (dt) {
@@ -76,6 +77,19 @@ struct Arena {  // grow-only device buffer
             return IPS4O_ERR_OUT_OF_MEMORY;
         }
         bytes = want;
+        return IPS4O_OK;
+    }
+    // grow to exactly `need` bytes (no slack), for the large regions
+    int ensure_exact(size_t need) {
+        if (need <= bytes) return IPS4O_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            p = nullptr;
+            return IPS4O_ERR_OUT_OF_MEMORY;
+        }
+        bytes = need;
         return IPS4O_OK;
     }
     void release() {
@@ -129,8 +143,9 @@ enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_B
 struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
-    Arena work;       // per-level workspace (even levels)
-    Arena work2;      // per-level workspace (odd levels: planned while the previous level runs)
+    Arena work;       // per-level descriptors and bucket state (even levels)
+    Arena work2;      // the same for odd levels (planned while the previous level runs)
+    Arena bufs;       // stripe buffers: partial buffers and side areas, shared by all levels
     Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
     Arena scratch;    // base-case record scratch
@@ -362,7 +377,7 @@ struct Level {
     std::vector<StripeD> stripes;
     std::vector<uint32_t> order;     // classification launch order
     uint32_t total_slots = 0, total_tree = 0, total_workers = 0;
-    uint64_t total_buf = 0;
+    uint64_t total_buf = 0, total_cnt = 0;
     Ctx<DT> c{};
 };
 
@@ -372,16 +387,25 @@ struct Level {
 // distinct keys then always repeats a splitter, equality buckets switch on
 // and the level makes progress (with a single splitter all keys could stay
 // in one bucket, level after level).
+// Below the first level k is at most kDeepK: the stripe buffers of a level
+// grow with k, and on the second level of 2^30 keys k = 1024 needed either
+// twice the buffers or half the stripes (its classification then took
+// 2.4 ms longer); with at most 512 buckets a small third level now and then
+// costs about 0.1 ms.
+constexpr uint32_t kDeepK = 512;
 uint32_t adaptive_k(uint64_t m, const Resolved& R) {
-    return std::min<uint32_t>((uint32_t)KT_MAX, std::max<uint32_t>(2u, next_pow2((2 * m + R.cap - 1) / R.cap)));
+    return std::min<uint32_t>(kDeepK, std::max<uint32_t>(2u, next_pow2((2 * m + R.cap - 1) / R.cap)));
 }
 
 // `first`: the top level of one array, whose k is the caller's (or the
 // default); `segmented`: the top level of many segments, each with the
 // adaptive k but at most the caller's.
+// `kbuf_given`: the bucket count of caller-given splitters (else a task's
+// buffers hold k buckets: sampling keeps K <= k).
 template <int DT>
 void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, uint32_t level,
-                bool first, uint32_t k_given, bool segmented = false) {
+                bool first, uint32_t k_given, bool segmented = false, uint32_t kbuf_given = 0,
+                uint64_t buf_budget = 0) {
     const uint32_t b = R.b;
     uint64_t total_m = 0, total_blocks = 0;
     for (const Seg& s : segs) {
@@ -428,21 +452,23 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
         for (size_t r = 0; given < G && r < rem.size(); ++r, ++given) wgroups[rem[r].second] += 1;
     }
-    uint32_t slot = 0, treeb = 0, wk = 0;
-    uint64_t bufoff = 0;
-    for (size_t i = 0; i < segs.size(); ++i) {
+    // bucket count, buffer count and stripes of every task
+    const size_t T = segs.size();
+    std::vector<uint32_t> kk(T), kb(T);
+    std::vector<uint64_t> nss(T), nsmin(T);
+    for (size_t i = 0; i < T; ++i) {
         const Seg& s = segs[i];
-        TaskD t{};
-        t.off = s.off;
-        t.m = s.m;
         uint32_t k;
         if (k_given) k = k_given;
         else if (segmented) k = std::min(R.k, adaptive_k(s.m, R));
         else if (first) k = R.k;
         else k = adaptive_k(s.m, R);
-        t.k = k;
-        t.alpha = alpha_for<DT>(s.m, R, k);
-        t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
+        kk[i] = k;
+        // buffers for k buckets; for 2k (up to KMAX) at the top level and
+        // where the keys are known to repeat, so that the sample's equality
+        // buckets (2u + 1 of them) need no thinning
+        kb[i] = kbuf_given ? kbuf_given
+                           : ((first || s.dup) ? std::min<uint32_t>(2 * k, (uint32_t)KMAX) : k);
         const uint64_t nb = (s.m + b - 1) / b;
         // stripes: the task's share, but enough blocks per stripe to keep
         // the partial buffers small (at least 8 buffer sets of k blocks each)
@@ -451,17 +477,69 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         if (first && R.stripes) ns = R.stripes;
         // the classification's block lists fit its LDS for stripes of up
         // to kStripeBlocksMax blocks
-        ns = std::max<uint64_t>(ns, (nb + kStripeBlocksMax - 1) / kStripeBlocksMax);
-        ns = std::min<uint64_t>(ns, std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
+        nsmin[i] = std::min<uint64_t>((nb + kStripeBlocksMax - 1) / kStripeBlocksMax,
+                                      std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
+        ns = std::max<uint64_t>(ns, nsmin[i]);
+        nss[i] = std::min<uint64_t>(ns, std::min<uint64_t>(nb, STRIPES_PER_TASK_MAX));
+        nsmin[i] = std::max<uint64_t>(1, nsmin[i]);
+    }
+    // memory budget of the stripe buffers (Theorem 2: O(k b) per
+    // workgroup): at most buf_budget elements, or what one stripe per task
+    // needs.  Over budget, the tasks with the largest buffers per stripe get
+    // fewer stripes first, then repeating-key tasks go back to k buffers
+    // (their sample then thins its equality buckets).
+    if (buf_budget) {
+        auto total = [&]() {
+            uint64_t t = 0;
+            for (size_t i = 0; i < T; ++i) t += nss[i] * 2 * kb[i] * (uint64_t)b;
+            return t;
+        };
+        uint64_t tot = total();
+        if (tot > buf_budget) {
+            std::vector<size_t> idx(T);
+            for (size_t i = 0; i < T; ++i) idx[i] = i;
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return kb[x] > kb[y]; });
+            for (size_t i : idx) {
+                if (tot <= buf_budget) break;
+                const uint64_t per = 2 * kb[i] * (uint64_t)b, over = tot - buf_budget;
+                const uint64_t cut = std::min<uint64_t>(nss[i] - nsmin[i], (over + per - 1) / per);
+                nss[i] -= cut;
+                tot -= cut * per;
+            }
+            for (size_t i : idx) {
+                if (tot <= buf_budget) break;
+                if (kb[i] > kk[i] && !kbuf_given) {
+                    tot -= nss[i] * 2 * (uint64_t)(kb[i] - kk[i]) * b;
+                    kb[i] = kk[i];
+                }
+            }
+        }
+    }
+    uint32_t slot = 0, treeb = 0, wk = 0;
+    uint64_t bufoff = 0, cntoff = 0;
+    for (size_t i = 0; i < segs.size(); ++i) {
+        const Seg& s = segs[i];
+        TaskD t{};
+        t.off = s.off;
+        t.m = s.m;
+        const uint32_t k = kk[i];
+        t.k = k;
+        t.kbuf = kb[i];
+        t.alpha = alpha_for<DT>(s.m, R, k);
+        t.seed = mix64(R.seed ^ mix64(((uint64_t)level << 48) ^ s.off));
+        const uint64_t nb = (s.m + b - 1) / b;
+        const uint64_t ns = nss[i];
         t.stripe_begin = (uint32_t)L.stripes.size();
         t.nstripes = (uint32_t)ns;
+        t.cnt_begin = (uint32_t)cntoff;
+        cntoff += ns * t.kbuf;
         for (uint64_t q = 0; q < ns; ++q) {
             StripeD sd{};
             sd.task = (uint32_t)i;
             sd.blk_begin = (uint32_t)(nb * q / ns);
             sd.blk_end = (uint32_t)(nb * (q + 1) / ns);
             sd.buf_off = bufoff;
-            bufoff += (uint64_t)4 * k * b;   // partial buffers (2k*b) and side area (2k*b)
+            bufoff += (uint64_t)2 * t.kbuf * b;   // partial buffers and side area, kbuf blocks each
             L.stripes.push_back(sd);
         }
         const uint64_t w = 4 * wgroups[i];
@@ -469,7 +547,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         t.nworkers = (uint32_t)w;
         wk += (uint32_t)w;
         t.slot_begin = slot;
-        slot += 2 * k;
+        slot += t.kbuf;
         t.tree_begin = treeb;
         treeb += k;
         L.tasks.push_back(t);
@@ -511,6 +589,7 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     L.total_tree = treeb;
     L.total_workers = wk;
     L.total_buf = bufoff;
+    L.total_cnt = cntoff;
 }
 
 template <int DT>
@@ -528,16 +607,16 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     add((L.total_slots + T) * sizeof(uint64_t));
     add((L.total_slots + T) * sizeof(uint32_t));
     add(L.total_slots * sizeof(BucketSlot));
-    add(S * (size_t)KMAX * sizeof(uint32_t));
+    add(L.total_cnt * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
-    add(L.total_buf * sizeof(Elem));
     add(T * (size_t)b * sizeof(Elem));
     return off + 256;
 }
 
 template <int DT>
-void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolved& R, uint32_t level = 0) {
+void carve_level(Level<DT>& L, void* base, void* misc, void* data, void* bufs, const Resolved& R,
+                 uint32_t level = 0) {
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     const size_t T = L.tasks.size(), S = L.stripes.size();
@@ -552,10 +631,10 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, const Resolve
     c.bounds = cv.take<uint64_t>(L.total_slots + T);
     c.delim = cv.take<uint32_t>(L.total_slots + T);
     c.slots = cv.take<BucketSlot>(L.total_slots);
-    c.counts = cv.take<uint32_t>(S * (size_t)KMAX);
+    c.counts = cv.take<uint32_t>(L.total_cnt);
     c.stripe_full = cv.take<uint32_t>(S);
     c.order = cv.take<uint32_t>(S);
-    c.bufs = cv.take<Elem>(L.total_buf);
+    c.bufs = (Elem*)bufs;
     c.ovf = cv.take<Elem>(T * (size_t)R.b);
     c.ntasks = (uint32_t)T;
     c.nstripes = (uint32_t)S;
@@ -686,7 +765,7 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
         uint32_t nsmax = 1, kmax = 0;
         for (const TaskD& t : L.tasks) {
             nsmax = std::max(nsmax, t.nstripes);
-            kmax = std::max(kmax, 2 * t.k);
+            kmax = std::max(kmax, t.kbuf);
         }
         for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
             const uint32_t nt = std::min<uint32_t>(65535, T - t0);
@@ -704,7 +783,7 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
     tm.end(mk.permute, 0.0);
     if (check) {
         uint32_t kmax = 0;
-        for (const TaskD& t : L.tasks) kmax = std::max(kmax, 2 * t.k);
+        for (const TaskD& t : L.tasks) kmax = std::max(kmax, t.kbuf);
         for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
             const uint32_t nt = std::min<uint32_t>(65535, T - t0);
             hipLaunchKernelGGL((k_check_permute<DT, 256>), dim3(kmax, nt), dim3(256), 0, st, c, t0);
@@ -716,7 +795,7 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
     // split over several workgroups
     uint32_t kmax = 0, nsmax = 1;
     for (const TaskD& t : L.tasks) {
-        kmax = std::max(kmax, 2 * t.k);
+        kmax = std::max(kmax, t.kbuf);
         nsmax = std::max(nsmax, t.nstripes);
     }
     const uint32_t parts = std::min<uint32_t>(32, std::max<uint32_t>(1, (nsmax + 2) / 16));
@@ -901,6 +980,19 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     return IPS4O_OK;
 }
 
+// The stripe buffers of a level in the arena all levels share.  A level
+// runs only after the previous one on the same stream, so one region
+// serves every level; when a level needs more than the arena holds, the
+// work in flight is waited for before it is replaced (the first sort of a
+// size only: the arena is kept).
+template <int DT>
+int ensure_bufs(ips4o_handle* h, const Level<DT>& L, hipStream_t st) {
+    const size_t need = (size_t)L.total_buf * sizeof(typename Traits<DT>::Elem);
+    if (need <= h->bufs.bytes) return IPS4O_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    return h->bufs.ensure_exact(need);
+}
+
 // Copies of a level's error word, task state and bounds into pinned memory,
 // enqueued right after its scan; `ev` fires when they have arrived.
 template <int DT>
@@ -944,6 +1036,11 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
             cur.push_back(sg);
         }
     }
+    // stripe buffers of a level: at most an eighth of the elements sorted
+    // (or one stripe per task, when that needs more)
+    uint64_t buf_budget = 0;
+    for (const Seg& sg : init) buf_budget += sg.m;
+    buf_budget = buf_budget / kBufBudgetDiv + 1;
     uint32_t level = 0;
     Level<DT> levels[2];
     std::vector<LevelMarks> marks;
@@ -962,10 +1059,12 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         Level<DT>& L = levels[par];
         Arena& work = par ? h->work2 : h->work;
         HostArena& rb = par ? h->hbounds2 : h->hbounds;
-        plan_level<DT>(L, cur, R, level, level == 0, 0, segmented && level == 0);
+        plan_level<DT>(L, cur, R, level, level == 0, 0, segmented && level == 0, 0, buf_budget);
         rc = work.ensure(level_bytes<DT>(L, R.b));
         if (rc) return rc;
-        carve_level<DT>(L, work.p, h->misc.p, d_data, R, level);
+        rc = ensure_bufs<DT>(h, L, st);
+        if (rc) return rc;
+        carve_level<DT>(L, work.p, h->misc.p, d_data, h->bufs.p, R, level);
         {
             uint64_t lm = 0;
             for (const Seg& sg : cur) lm += sg.m;
@@ -1008,7 +1107,7 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
                              level, t, (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, K,
                              ts[t].eq, td.nstripes);
             uint64_t eb = 0;
-            if (K > (uint32_t)KMAX ||
+            if (K > (uint32_t)KMAX || K > td.kbuf ||
                 !split_task(td.off, td.m, cur[t].grp, K, ts[t].eq != 0, bd, R.cap, bin_cap, base, next, &eb)) {
                 (void)check_device_error(h, st);
                 return IPS4O_ERR_DEVICE_FAULT;
@@ -1093,10 +1192,12 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     if (rc) return rc;
     Level<DT> L;
     std::vector<Seg> cur{Seg{0, n}};
-    plan_level<DT>(L, cur, R, 0, true, ht.ts.kt);
+    plan_level<DT>(L, cur, R, 0, true, ht.ts.kt, false, ht.ts.K, n / kBufBudgetDiv + 1);
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
-    carve_level<DT>(L, h->work.p, h->misc.p, d_data, R);
+    rc = ensure_bufs<DT>(h, L, st);
+    if (rc) return rc;
+    carve_level<DT>(L, h->work.p, h->misc.p, d_data, h->bufs.p, R);
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     LevelMarks mk;
     tm.set_pass(0, n);
@@ -1167,7 +1268,7 @@ int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_para
     L.tasks[0].seed = R.seed;   // the caller's stream, not a derived one
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
-    carve_level<DT>(L, h->work.p, h->misc.p, (void*)d_data, R);
+    carve_level<DT>(L, h->work.p, h->misc.p, (void*)d_data, nullptr, R);    // sampling only
     HIP_TRY(hipMemcpyAsync((void*)L.c.tasks, L.tasks.data(), sizeof(TaskD), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL((k_sample<DT, 1024>), dim3(1), dim3(1024), 0, st, L.c);
     HIP_TRY(hipGetLastError());
@@ -1280,6 +1381,7 @@ void ips4o_destroy(ips4o_handle* h) {
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->work.release();
     h->work2.release();
+    h->bufs.release();
     h->hbounds2.release();
     h->hdesc.release();
     h->hdesc2.release();
@@ -1295,7 +1397,7 @@ void ips4o_destroy(ips4o_handle* h) {
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
     if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
-    *bytes = h->work.bytes + h->work2.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
+    *bytes = h->work.bytes + h->work2.bytes + h->bufs.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
     return IPS4O_OK;
 }
 

@@ -50,15 +50,18 @@ struct TaskD {                  // host-planned, one per task
     uint32_t alpha;             // oversampling factor
     uint32_t stripe_begin, nstripes;
     uint32_t worker_begin, nworkers;
-    uint32_t slot_begin;        // first bucket slot (sum of 2k over earlier tasks)
+    uint32_t slot_begin;        // first bucket slot (sum of kbuf over earlier tasks)
     uint32_t tree_begin;        // first tree slot (sum of k over earlier tasks)
+    uint32_t kbuf;              // buckets the task's buffers, slots and counts hold (K <= kbuf)
+    uint32_t cnt_begin;         // counts of stripe stripe_begin + q at cnt_begin + q * kbuf
 };
 
 struct StripeD {                // host-planned, one per stripe
     uint32_t task;
     uint32_t blk_begin, blk_end;
     uint32_t pad;
-    uint64_t buf_off;           // element offset of this stripe's bucket buffers
+    uint64_t buf_off;           // element offset of this stripe's partial buffers (kbuf blocks;
+                                // during classification followed by its side area of kbuf blocks)
 };
 
 struct TaskS {                  // device-written per task
@@ -98,10 +101,10 @@ struct Ctx {
     TaskS* ts;
     Key* tree;                  // [sum k]: tree_begin + i, i in 1..kt-1
     Key* spl;                   // [sum k]: tree_begin + j, sorted splitters (padded)
-    uint64_t* bounds;           // [sum (2k+1)]: slot_begin + task + i
+    uint64_t* bounds;           // [sum (kbuf+1)]: slot_begin + task + i
     uint32_t* delim;            // same indexing as bounds
-    BucketSlot* slots;          // [sum 2k]: slot_begin + i
-    uint32_t* counts;           // [stripes][KMAX]
+    BucketSlot* slots;          // [sum kbuf]: slot_begin + i
+    uint32_t* counts;           // [stripes][kbuf of the stripe's task]
     uint32_t* stripe_full;      // [stripes] full blocks after classification
     const uint32_t* order;      // [stripes] classification launch order (largest first)
     Elem* bufs;                 // stripe bucket buffers
@@ -341,11 +344,14 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
     uint32_t kp = k, step = alpha;
     uint32_t nuniq = pick_unique(kp, step);
     // equality buckets double the bucket count: when 2 nuniq + 1 would
-    // exceed KMAX, every second pick is used instead (k/2 buckets, twice
-    // the oversampling)
-    if (nuniq < kp - 1 && 2 * nuniq + 1 > (uint32_t)KMAX) {
+    // exceed the kbuf buckets the task's buffers hold, every second pick is
+    // used instead (k/2 picks, twice the oversampling, the same sample),
+    // with equality buckets kept on, so K <= k - 1
+    bool thinned = false;
+    if (nuniq < kp - 1 && 2 * nuniq + 1 > td.kbuf) {
         kp = k / 2;
         step = 2 * alpha;
+        thinned = true;
         __syncthreads();
         nuniq = pick_unique(kp, step);
     }
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_sample(Ctx<DT> c) {
 #pragma unroll
     for (int q = 0; q < PPT; ++q)
         if (nw[q]) smp[isnew[1 + threadIdx.x + (uint32_t)q * NT]] = pk[q];
-    const uint32_t eq = nuniq < kp - 1 ? 1u : 0u;
+    const uint32_t eq = (thinned || nuniq < kp - 1) ? 1u : 0u;
     uint32_t kt = kp;
     if (eq) {
         kt = 2;
@@ -682,7 +688,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     const uint32_t E = (uint32_t)(s_end - s_begin);         // stripe elements
     Elem* sp = c.data + td.off + s_begin;                   // the stripe
     Elem* buf = c.bufs + sd.buf_off;                        // partial buffers, bucket j at j*b
-    Elem* side = buf + ((uint64_t)(2 * td.k) << lb);        // slots 0 .. K-1
+    Elem* side = buf + ((uint64_t)td.kbuf << lb);           // slots 0 .. K-1
     const int64_t KB = (int64_t)K << lb;
     // element e of slot space (slot e >> lb) in memory
     auto slot_elem = [&](int64_t e) -> Elem* { return e < KB ? side + e : sp + (e - KB); };
@@ -1018,7 +1024,7 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     }
     const uint32_t full_blocks = F;
     __syncthreads();
-    uint32_t* cnt_out = c.counts + (uint64_t)sid * KMAX;
+    uint32_t* cnt_out = c.counts + td.cnt_begin + (uint64_t)(sid - td.stripe_begin) * td.kbuf;
     for (uint32_t q = threadIdx.x; q < K; q += NT) cnt_out[q] = (L.nfull[q] << lb) + L.fill[q];
     if (threadIdx.x == 0) c.stripe_full[sid] = full_blocks;
 }
@@ -1041,7 +1047,7 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
         const uint32_t j = threadIdx.x % K, p = threadIdx.x / K;
         uint32_t s = 0;
         if (p < P)
-            for (uint32_t q = p; q < td.nstripes; q += P) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
+            for (uint32_t q = p; q < td.nstripes; q += P) s += c.counts[td.cnt_begin + (uint64_t)q * td.kbuf + j];
         part[threadIdx.x] = s;
         __syncthreads();
         if (threadIdx.x < K) {
@@ -1052,7 +1058,7 @@ __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
     } else {
         for (uint32_t j = threadIdx.x; j < K; j += NT) {
             uint32_t s = 0;
-            for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[(uint64_t)(td.stripe_begin + q) * KMAX + j];
+            for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[td.cnt_begin + (uint64_t)q * td.kbuf + j];
             tot[j] = s;
         }
     }
@@ -1543,7 +1549,7 @@ __global__ __launch_bounds__(NT) void k_overhang(Ctx<DT> c, uint32_t task0) {
         return;
     }
     const Elem* src = c.data + td.off + g.B1;
-    Elem* side = c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * c.b;
+    Elem* side = c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)td.kbuf + j) * c.b;
     for (uint32_t i = lane; i < g.ohn; i += 64) side[i] = src[i];
 }
 
@@ -1578,7 +1584,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint3
     for (uint32_t q = threadIdx.x; q < nq; q += NT) {
         uint32_t v;
         if (q == 0) v = (uint32_t)g.ohn;
-        else if (q <= ns) v = c.counts[(uint64_t)(td.stripe_begin + q - 1) * KMAX + j] % b;
+        else if (q <= ns) v = c.counts[td.cnt_begin + (uint64_t)(q - 1) * td.kbuf + j] % b;
         else v = g.ovf_case ? b : 0;
         pre[q] = v;
     }
@@ -1602,7 +1608,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint3
     for (uint32_t q = q0; q < q1; ++q) {
         const uint32_t x0 = pre[q], n = pre[q + 1] - x0;
         if (n == 0) continue;
-        const Elem* src = q == 0 ? c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * b
+        const Elem* src = q == 0 ? c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)td.kbuf + j) * b
                         : q <= ns ? c.bufs + c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b
                                   : c.ovf + (uint64_t)t * b;
         for (uint32_t o = threadIdx.x; o < n; o += NT) seg[fm(x0 + o)] = src[o];
@@ -1632,9 +1638,9 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
     uint64_t src_off = 0;                       // element offset in bufs (q <= ns)
     if (lane == 0) {
         v = (uint32_t)g.ohn;
-        src_off = c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.k + j) * b;
+        src_off = c.stripes[td.stripe_begin].buf_off + ((uint64_t)td.kbuf + j) * b;
     } else if (lane <= ns) {
-        v = c.counts[(uint64_t)(td.stripe_begin + lane - 1) * KMAX + j] % b;
+        v = c.counts[td.cnt_begin + (uint64_t)(lane - 1) * td.kbuf + j] % b;
         src_off = c.stripes[td.stripe_begin + lane - 1].buf_off + (uint64_t)j * b;
     } else if (lane == ns + 1) {
         v = g.ovf_case ? b : 0;
@@ -2257,7 +2263,7 @@ __global__ __launch_bounds__(NT) void k_check_classify(Ctx<DT> c) {
         if (bj != b0) raise_err_at(c.err, ERR_CHECK_BLOCK, (uint32_t)i, bj, b0);
         atomicAdd(&hist[bj], 1u);
     }
-    const uint32_t* cnt = c.counts + (uint64_t)blockIdx.x * KMAX;
+    const uint32_t* cnt = c.counts + td.cnt_begin + (uint64_t)(blockIdx.x - td.stripe_begin) * td.kbuf;
     for (uint32_t j = 0; j < K; ++j) {
         const uint32_t f = cnt[j] % b;
         for (uint32_t r = threadIdx.x; r < f; r += NT) {

@@ -22,10 +22,13 @@ struct SegD {
     uint32_t pad;
 };
 
-// A subproblem: elements [off, off+m); grp is the caller's segment it lies in.
+// A subproblem: elements [off, off+m); grp is the caller's segment it lies in;
+// dup: the task it came from used equality buckets (its keys repeat, so its
+// own sample likely repeats splitters too).
 struct Seg {
     uint64_t off, m;
     uint32_t grp;
+    uint32_t dup;
 };
 
 // The buckets of one finished task (a subproblem [off, off+m) of the level
@@ -41,7 +44,7 @@ struct Seg {
 // one would.  A bin never reaches beyond its task: between two tasks of a
 // level may lie buckets of an earlier level that already have bins of their
 // own, and two bins sorted at once must not overlap.
-// Larger buckets are appended to `next` (grp inherited).  Returns false when
+// Larger buckets are appended to `next` (grp inherited, dup = eq).  Returns false when
 // the bounds are inconsistent (bounds[0] != 0, bounds[K] != m, decreasing).
 inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool eq, const uint64_t* bounds,
                        uint64_t cap, uint64_t bin_cap, std::vector<SegD>& bins, std::vector<Seg>& next,
@@ -56,7 +59,7 @@ inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool 
         if (eq && (i & 1)) continue;             // equality bucket: one key value
         const uint64_t at = off + bounds[i];
         if (sz > cap) {
-            next.push_back(Seg{at, sz, grp});
+            next.push_back(Seg{at, sz, grp, eq ? 1u : 0u});
             continue;
         }
         *elements_base += sz;

@@ -119,6 +119,21 @@ void ips4o_destroy(ips4o_handle *h);
 /* Device bytes of workspace the handle holds after the calls so far. */
 int ips4o_workspace_bytes(const ips4o_handle *h, size_t *bytes);
 
+/* Upper bound of the device workspace (bytes, into *bytes on the host) that
+ * a fresh handle holds after ips4o_sort of n elements of `dtype` with these
+ * parameters, after ips4o_sort_segmented over n elements in all, or after
+ * ips4o_distribute of n elements; computed on the host from n, the element
+ * type and the parameters alone, before any device work (h may be NULL).
+ * Theorem 2 bounds the extra space by O(k b) per thread; here a level's
+ * stripe buffers stay within n/8 elements (or one stripe per subproblem,
+ * when that needs more), so for large n the bound is about n*s/8 plus
+ * O(n/base_cap) of per-bucket state.  A handle keeps what it has allocated:
+ * after several calls it holds at most the largest of their bounds.
+ * Errors: IPS4O_ERR_INVALID_ARG (NULL bytes, unknown dtype, bad params),
+ * IPS4O_ERR_NOT_SUPPORTED (n beyond the limit of ips4o_sort). */
+int ips4o_workspace_size(const ips4o_handle *h, int dtype, uint64_t n, const ips4o_params *params,
+                         size_t *bytes);
+
 /* Sort d_data[0..n) of `dtype` in place (the whole method: sampling,
  * classification, block permutation, cleanup, recursion, base case;
  * Sections 3 and 4).  d_data: device pointer to n elements. */

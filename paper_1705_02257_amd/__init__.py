@@ -30,7 +30,7 @@ DEFAULT_K = 256          # first-level buckets when params leave k at 0
 DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)
-EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_sort",
+EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
            "ips4o_last_pass_stats",
@@ -81,6 +81,7 @@ def _load():
     L.ips4o_destroy.argtypes = [vp]
     L.ips4o_destroy.restype = None
     L.ips4o_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.ips4o_workspace_size.argtypes = [vp, i32, u64, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
     L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
     L.ips4o_sort_segmented.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
     L.ips4o_distribute.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, ctypes.POINTER(u32),
@@ -97,7 +98,7 @@ def _load():
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
-    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
+    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
                  "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
@@ -196,6 +197,15 @@ def ips4o_destroy(h: int) -> None:
 def ips4o_workspace_bytes(h: int) -> int:
     v = ctypes.c_size_t()
     _check(_L().ips4o_workspace_bytes(h, ctypes.byref(v)), "ips4o_workspace_bytes")
+    return v.value
+
+
+def ips4o_workspace_size(dtype, n, params=None, h=None) -> int:
+    """Upper bound of the device workspace a fresh handle holds after
+    sorting n elements (no GPU needed)."""
+    v = ctypes.c_size_t()
+    _check(_L().ips4o_workspace_size(h, _dtype(dtype), int(n), _params(params), ctypes.byref(v)),
+           "ips4o_workspace_size")
     return v.value
 
 

@@ -44,6 +44,7 @@ constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by
 constexpr size_t kExactOrder = 4096;         // stripes sorted exactly by cost for the launch order
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
+constexpr uint64_t kMaxElements = 1ull << 32;  // n (and a segmented call's total) must stay below
 constexpr uint64_t kBufBudgetDiv = 8;        // stripe buffers: at most 1/8 of the elements sorted
 
 size_t elem_size(int dt) {
@@ -610,7 +611,6 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     add(L.total_cnt * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
-    add(T * (size_t)b * sizeof(Elem));
     return off + 256;
 }
 
@@ -635,7 +635,6 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, void* bufs, c
     c.stripe_full = cv.take<uint32_t>(S);
     c.order = cv.take<uint32_t>(S);
     c.bufs = (Elem*)bufs;
-    c.ovf = cv.take<Elem>(T * (size_t)R.b);
     c.ntasks = (uint32_t)T;
     c.nstripes = (uint32_t)S;
     char* m = (char*)misc;
@@ -889,6 +888,7 @@ constexpr uint32_t small_bin_cap() {
 }
 
 constexpr size_t kFailCounts = 256;     // misc: two base-case fallback counters
+constexpr size_t kBaseChunk = size_t(1) << 20;   // base-case bins per round of launches
 
 template <int DT, int NT>
 int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t grid,
@@ -909,12 +909,19 @@ int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t 
     return IPS4O_OK;
 }
 
+// One chunk of at most kBaseChunk bins (bins[0..count)).
 template <int DT>
-int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const Resolved& R,
-                 hipStream_t st, Timer& tm) {
+int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t count, hipStream_t st,
+                       Timer& tm) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
-    if (list.empty()) return IPS4O_OK;
+    struct {
+        const SegD* p;
+        size_t n;
+        const SegD* begin() const { return p; }
+        const SegD* end() const { return p + n; }
+        size_t size() const { return n; }
+    } const list{bins, count};
     constexpr int BNT = Shape<DT>::BNT, BVT = Shape<DT>::BVT;
     static_assert(BNT * BVT == TR::kBaseCap, "base-case capacity");
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
@@ -948,10 +955,10 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
     c.data = (Elem*)d_data;
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
-    tm.set_pass((uint32_t)tm.pass_elems.size(), (uint64_t)elems);   // the pass after the last level
     SegD* d_segs = (SegD*)h->segs.p;
     SegD* fail = d_segs + list.size();
     uint32_t* nfail = (uint32_t*)((char*)h->misc.p + kFailCounts);
+    HIP_TRY(hipMemsetAsync(nfail, 0, 2 * sizeof(uint32_t), st));     // bins handed back by this chunk
     int r = tm.begin(KK_BASE);
     if (nsmall) {
         rc = launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, g_small, scr, fail, nfail, st);
@@ -976,6 +983,24 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
         HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
         std::fprintf(stderr, "[ips4o] base case: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted), "
                      "%zu tiny\n", nsmall, nf[0], nlarge, nf[1], ntiny);
+    }
+    return IPS4O_OK;
+}
+
+// The base case over every bin of a sort, kBaseChunk bins per round of
+// launches, so that the device bin list stays within a fixed size.
+template <int DT>
+int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const Resolved& R,
+                 hipStream_t st, Timer& tm) {
+    (void)R;
+    if (list.empty()) return IPS4O_OK;
+    uint64_t elems = 0;
+    for (const SegD& sg : list) elems += sg.len;
+    tm.set_pass((uint32_t)tm.pass_elems.size(), elems);   // the pass after the last level
+    for (size_t a = 0; a < list.size(); a += kBaseChunk) {
+        const int rc = run_basecase_chunk<DT>(h, d_data, list.data() + a, std::min(kBaseChunk, list.size() - a),
+                                              st, tm);
+        if (rc) return rc;
     }
     return IPS4O_OK;
 }
@@ -1305,6 +1330,59 @@ int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_para
     return check_device_error(h, st);
 }
 
+// Upper bound of the device workspace a handle holds after sorting n
+// elements (ips4o_sort of n elements, ips4o_sort_segmented of n elements in
+// all, ips4o_distribute of n elements), derived from the planning rules
+// above; it does not depend on the keys.
+//   stripe buffers (exact arena): every level plans at most
+//     max(n/kBufBudgetDiv + 1, what one stripe per task with kbuf = k needs);
+//     the top level of one array needs 2 KMAX b per stripe, at least
+//     ceil(nb / kStripeBlocksMax) stripes; a deeper task of m > cap elements
+//     has k < 4m/cap (adaptive_k), so one stripe per task needs below
+//     8 b n / cap, plus 2 KT_MAX b per extra stripe of huge tasks.
+//   per-level descriptors (two arenas, 25 % slack): a deeper level has at
+//     most n/(cap+1) tasks, sum k <= 4n/cap + 2 per task, sum kbuf <= 2 sum k,
+//     at most kLevelStripes + tasks + nb/kStripeBlocksMax stripes, and counts
+//     for every stripe's kbuf buckets (at most the stripe buffers / 2b).
+//   base-case bin list: at most kBaseChunk bins at once, twice (with the bins
+//     handed to the merge sort); record scratch: one bin capacity per
+//     workgroup of the base-case grids; the error and counter words.
+template <int DT>
+size_t workspace_bound(uint64_t n, const Resolved& R) {
+    using TR = Traits<DT>;
+    const uint64_t s = sizeof(typename TR::Elem), ks = sizeof(typename TR::Key);
+    const uint64_t b = R.b, cap = R.cap;
+    if (n <= 1) return 0;
+    auto slack = [](uint64_t x) { return x + x / 4; };
+    auto al = [](uint64_t x) { return x + 256; };
+    const uint64_t nb = (n + b - 1) / b;
+    const uint64_t huge = nb / kStripeBlocksMax + 1;          // stripes forced by stripe length
+    uint64_t bufs = 0, work = 0;
+    if (n > cap) {
+        const uint64_t budget = n / kBufBudgetDiv + 1;
+        const uint64_t root = 2 * (uint64_t)KMAX * b * std::max<uint64_t>(huge, R.stripes);
+        const uint64_t deep = 8 * b * n / cap + 1 + 2 * (uint64_t)KT_MAX * b * huge;
+        bufs = std::max(budget, std::max(root, deep));
+        const uint64_t T = n / (cap + 1) + 1;
+        const uint64_t sumk = std::max<uint64_t>((uint64_t)KT_MAX, 4 * n / cap + 2 * T);
+        const uint64_t sumkb = 2 * sumk;
+        const uint64_t S = std::max<uint64_t>(STRIPES_PER_TASK_MAX, kLevelStripes + T + huge);
+        const uint64_t counts = bufs / (2 * b) + 1;
+        const uint64_t lv = al(T * sizeof(TaskD)) + al(S * sizeof(StripeD)) + al(T * sizeof(TaskS)) +
+                            2 * al(sumk * ks) + al((sumkb + T) * 8) + al((sumkb + T) * 4) +
+                            al(sumkb * sizeof(BucketSlot)) + al(counts * 4) + 2 * al(S * 4) + 256;
+        work = 2 * slack(lv);
+    }
+    const uint64_t misc = slack(kStatsOffset + (uint64_t)kStatLevels * kStatsBytes);
+    const uint64_t bins = std::min<uint64_t>(n / 2 + 1, kBaseChunk);
+    const uint64_t segs = slack(2 * bins * sizeof(SegD));
+    uint64_t scratch = 0;
+    if (DT != DT_U64 && DT != DT_F64)
+        scratch = slack(std::max(std::min<uint64_t>(bins, 2 * kBaseGrid) * small_bin_cap<DT>(),
+                                 std::min<uint64_t>(bins, kBaseGrid) * (uint64_t)TR::kBaseCap) * s);
+    return (size_t)(bufs * s + work + misc + segs + scratch);
+}
+
 int check_ptr(const void* p, uint64_t n, int dt) {
     if (n > 0 && !p) return IPS4O_ERR_INVALID_ARG;
     if (p && ((uintptr_t)p % elem_align(dt))) return IPS4O_ERR_INVALID_ARG;
@@ -1395,6 +1473,24 @@ void ips4o_destroy(ips4o_handle* h) {
     delete h;
 }
 
+int ips4o_workspace_size(const ips4o_handle* h, int dtype, uint64_t n, const ips4o_params* params, size_t* bytes) {
+    (void)h;
+    if (!bytes) return IPS4O_ERR_INVALID_ARG;
+    if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    int rc = check_params(params, dtype);
+    if (rc) return rc;
+    if (n >= kMaxElements) return IPS4O_ERR_NOT_SUPPORTED;
+    Resolved R;
+    switch (dtype) {
+    case DT_U64: resolve<DT_U64>(params, &R); *bytes = workspace_bound<DT_U64>(n, R); break;
+    case DT_F64: resolve<DT_F64>(params, &R); *bytes = workspace_bound<DT_F64>(n, R); break;
+    case DT_PAIR: resolve<DT_PAIR>(params, &R); *bytes = workspace_bound<DT_PAIR>(n, R); break;
+    case DT_QUARTET: resolve<DT_QUARTET>(params, &R); *bytes = workspace_bound<DT_QUARTET>(n, R); break;
+    default: resolve<DT_BYTES100>(params, &R); *bytes = workspace_bound<DT_BYTES100>(n, R); break;
+    }
+    return IPS4O_OK;
+}
+
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
     if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
     *bytes = h->work.bytes + h->work2.bytes + h->bufs.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
@@ -1478,7 +1574,7 @@ int ips4o_check_args(const void* d_data, uint64_t n, int dtype, const ips4o_para
     if (rc) return rc;
     rc = check_params(params, dtype);
     if (rc) return rc;
-    if (n >= (1ull << 32)) return IPS4O_ERR_NOT_SUPPORTED;
+    if (n >= kMaxElements) return IPS4O_ERR_NOT_SUPPORTED;
     return IPS4O_OK;
 }
 

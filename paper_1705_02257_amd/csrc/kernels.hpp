@@ -108,7 +108,6 @@ struct Ctx {
     uint32_t* stripe_full;      // [stripes] full blocks after classification
     const uint32_t* order;      // [stripes] classification launch order (largest first)
     Elem* bufs;                 // stripe bucket buffers
-    Elem* ovf;                  // [tasks][b]
     uint32_t* err;              // device error word (0 = ok)
     unsigned long long* stats;  // [0] block moves, [1] skips, [2] cleanup placements, [3] fix moves
     uint32_t b;                 // elements per block
@@ -118,6 +117,16 @@ struct Ctx {
     uint32_t skip_inplace;
     uint32_t vtile;             // classification: virtual tiles of 2 tiles (8-byte keys)
 };
+
+// The overflow block of task t (Section 4.2: the partial last block of a
+// segment is never written in place): the last side slot of the task's first
+// stripe, free from the end of classification on; the overhang slots of the
+// cleanup are slots 0 .. K-2 of the same side area (the last bucket, K-1,
+// ends at the segment end and has no overhang), and K <= kbuf.
+template <int DT>
+__device__ inline typename Traits<DT>::Elem* ovf_block(const Ctx<DT>& c, const TaskD& td) {
+    return c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)2 * td.kbuf - 1) * c.b;
+}
 
 enum ErrCode : uint32_t {
     ERR_SPIN = 1, ERR_CLEANUP_COUNT = 2, ERR_PERMUTE_RANGE = 4, ERR_FIX = 8,
@@ -1330,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_permute(Ctx<DT> c) {
     const uint32_t words = b * WPE;
     const bool partial = (td.m % b) != 0;
     const uint32_t last_blk = st.nblocks - 1;
-    Word* ovf = reinterpret_cast<Word*>(c.ovf + (uint64_t)t * b);
+    Word* ovf = reinterpret_cast<Word*>(ovf_block<DT>(c, td));
 
     // words of block blk that lie inside the segment (all of them except for
     // a partial last block, which is never unprocessed and so never read)
@@ -1610,7 +1619,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint3
         if (n == 0) continue;
         const Elem* src = q == 0 ? c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)td.kbuf + j) * b
                         : q <= ns ? c.bufs + c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b
-                                  : c.ovf + (uint64_t)t * b;
+                                  : ovf_block<DT>(c, td);
         for (uint32_t o = threadIdx.x; o < n; o += NT) seg[fm(x0 + o)] = src[o];
     }
 }
@@ -1664,7 +1673,7 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
     if (lane == 0) stat_add(c.stats, 2, nsrc, threadIdx.x / 64 + blockIdx.x + blockIdx.y);
     const FreeMap fm{g.B0, tb, nhead};
     Elem* seg = c.data + td.off;
-    const Elem* ovfp = c.ovf + (uint64_t)t * b;
+    const Elem* ovfp = ovf_block<DT>(c, td);
     // U elements per lane per round: all loads of a round are issued before
     // its stores, so a round costs one memory latency, not U
     constexpr int U = 8;
@@ -2296,7 +2305,7 @@ __global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c, uint32_t task0)
     const bool partial = (td.m % b) != 0;
     const typename TR::Elem* seg = c.data + td.off;
     for (uint32_t q = d0; q < w; ++q) {
-        const typename TR::Elem* blk = (partial && q == st.nblocks - 1) ? c.ovf + (uint64_t)t * b : seg + (uint64_t)q * b;
+        const typename TR::Elem* blk = (partial && q == st.nblocks - 1) ? ovf_block<DT>(c, td) : seg + (uint64_t)q * b;
         for (uint32_t r = threadIdx.x; r < b; r += NT) {
             const uint32_t bj = classify_key(TR::key(blk[r]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
             if (bj != j) raise_err_at(c.err, ERR_CHECK_PLACED, q, bj, j);

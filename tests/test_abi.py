@@ -180,3 +180,24 @@ def test_check_wrappers(ips):
     assert ips.ips4o_check_splitters(np.array([1, 2, 2, 3], np.uint64), "u64", True) == 0
     assert ips.ips4o_check_splitters(np.array([3, 1], np.uint64), "u64", False) == -1
     assert ips.ips4o_check_splitters(np.array([], np.uint64), "u64", False) == -1
+
+
+def test_workspace_size_query(ips):
+    """ips4o_workspace_size answers without a handle or a GPU: argument
+    checks, nothing for n <= 1, and at the 2^30-key configuration a bound
+    between the stripe buffers' share (n*s/8) and 0.18 n*s (the per-bucket
+    state adds O(n / base_cap))."""
+    import ctypes
+    L = ips._L()
+    v = ctypes.c_size_t()
+    assert L.ips4o_workspace_size(None, 0, 100, None, None) == -1
+    assert L.ips4o_workspace_size(None, 9, 100, None, ctypes.byref(v)) == -1
+    assert L.ips4o_workspace_size(None, 0, 100, ips.Params(k=3), ctypes.byref(v)) == -1
+    assert ips.ips4o_workspace_size("u64", 0) == 0 and ips.ips4o_workspace_size("u64", 1) == 0
+    n = 1 << 30
+    for dt, s in [("u64", 8), ("f64", 8), ("pair", 16)]:
+        w = ips.ips4o_workspace_size(dt, n)
+        assert n * s / 8 <= w <= 0.18 * n * s, (dt, w / (n * s))
+    # larger arrays need no more than proportionally more
+    a, b = ips.ips4o_workspace_size("u64", 1 << 28), ips.ips4o_workspace_size("u64", 1 << 29)
+    assert a < b <= 2 * a + (1 << 26)

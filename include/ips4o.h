@@ -136,7 +136,12 @@ int ips4o_workspace_size(const ips4o_handle *h, int dtype, uint64_t n, const ips
 
 /* Sort d_data[0..n) of `dtype` in place (the whole method: sampling,
  * classification, block permutation, cleanup, recursion, base case;
- * Sections 3 and 4).  d_data: device pointer to n elements. */
+ * Sections 3 and 4).  d_data: device pointer to n elements.
+ * Size limit: n < 2^40, and a subproblem must have fewer than 2^25 - 2^16
+ * blocks (the permutation's pointer word, Section 4.2): a level whose
+ * largest subproblem has more doubles its block size, up to 2048 words
+ * (16 KiB), so n stays below about 2^36 u64/f64 keys, 2^35 pairs, 2^34
+ * quartets and 2^31 100-byte records; beyond: IPS4O_ERR_NOT_SUPPORTED. */
 int ips4o_sort(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
                const ips4o_params *params, void *hip_stream);
 
@@ -153,7 +158,8 @@ int ips4o_sort(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
  * offsets, read before the call returns (NULL allowed when num_segments is
  * 0).  d_data: device pointer holding h_offsets[num_segments] elements.
  * Errors: IPS4O_ERR_INVALID_ARG for decreasing offsets or the checks of
- * ips4o_sort; IPS4O_ERR_NOT_SUPPORTED when h_offsets[num_segments] >= 2^32.
+ * ips4o_sort; IPS4O_ERR_NOT_SUPPORTED when h_offsets[num_segments] exceeds
+ * the size limit of ips4o_sort.
  * Same stream and handle rules as ips4o_sort. */
 int ips4o_sort_segmented(ips4o_handle *h, void *d_data, int dtype, const uint64_t *h_offsets,
                          uint32_t num_segments, const ips4o_params *params, void *hip_stream);

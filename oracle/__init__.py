@@ -178,6 +178,43 @@ def expected_sorted(dist: str, dtype: str, n: int, seed: int) -> np.ndarray:
     raise ValueError(dist)
 
 
+def expected_sorted_range(dist: str, dtype: str, n: int, seed: int, first: int, count: int) -> np.ndarray:
+    """Elements first .. first+count-1 of the sorted arrangement of
+    workloads.generate(dist, dtype, n, seed) for u64/f64 keys, computed
+    without the rest of the array (for inputs too large to hold on the host):
+      sorted, reverse  the Sorted sequence of the same seed, in chunks;
+      rootdup          A[i] = i mod m with m = floor(sqrt(n)) (Section 5):
+                       value v occurs floor((n - 1 - v) / m) + 1 times, so
+                       position p holds the v whose cumulative count first
+                       exceeds p;
+      ones             all ones."""
+    import math
+    import workloads
+    if dtype not in ("u64", "f64"):
+        raise ValueError(dtype)
+    if first < 0 or count < 0 or first + count > n:
+        raise ValueError("range outside the array")
+    if dist in ("sorted", "reverse"):
+        return workloads.generate_range("sorted", dtype, n, seed, first, count)
+    if dist == "ones":
+        return np.ones(count, dtype=np.uint64 if dtype == "u64" else np.float64)
+    if dist != "rootdup":
+        raise ValueError(dist)
+    m = math.isqrt(n)
+    v = np.arange(m, dtype=np.uint64)
+    occ = (np.uint64(n - 1) - v) // np.uint64(m) + np.uint64(1)
+    ends = np.cumsum(occ)                     # ends[v] = positions holding values <= v
+    if count == 0:
+        return np.empty(0, dtype=np.uint64 if dtype == "u64" else np.float64)
+    last = first + count                      # one past the range
+    vf = int(np.searchsorted(ends, np.uint64(first), side="right"))
+    vl = int(np.searchsorted(ends, np.uint64(last - 1), side="right"))
+    lo = np.maximum(ends[vf:vl + 1] - occ[vf:vl + 1], np.uint64(first))
+    hi = np.minimum(ends[vf:vl + 1], np.uint64(last))
+    vals = np.repeat(np.arange(vf, vl + 1, dtype=np.uint64), (hi - lo).astype(np.int64))
+    return vals if dtype == "u64" else vals.astype(np.float64)
+
+
 def compare(a: np.ndarray, b: np.ndarray, dtype: str) -> int:
     a = np.ascontiguousarray(a); b = np.ascontiguousarray(b)
     return int(_load().or_compare(_ptr(a), _ptr(b), DTYPES[dtype]))

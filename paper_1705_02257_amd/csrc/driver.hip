@@ -44,7 +44,7 @@ constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by
 constexpr size_t kExactOrder = 4096;         // stripes sorted exactly by cost for the launch order
 constexpr uint32_t kDefaultWorkers = 8192;   // permutation wavefronts per level
 constexpr uint32_t kBaseGrid = 1024;
-constexpr uint64_t kMaxElements = 1ull << 32;  // n (and a segmented call's total) must stay below
+constexpr uint64_t kMaxElements = 1ull << 40;  // n (and a segmented call's total) must stay below
 constexpr uint64_t kBufBudgetDiv = 8;        // stripe buffers: at most 1/8 of the elements sorted
 
 size_t elem_size(int dt) {
@@ -280,6 +280,21 @@ int resolve(const ips4o_params* p, Resolved* r) {
     r->spin = d.spin_limit ? d.spin_limit : kDefaultSpin;
     r->seed = d.seed ? d.seed : kDefaultSeed;
     return IPS4O_OK;
+}
+
+// Blocks of one subproblem must stay below WR_MAX_BLOCKS (the permutation's
+// packed pointer word): for a subproblem of m elements the block doubles
+// until they do, up to the largest block a permutation wave holds in its
+// registers (2048 words).  Returns false if even that block is too small.
+template <int DT>
+bool scale_block(Resolved* R, uint64_t m) {
+    using TR = Traits<DT>;
+    constexpr uint64_t wpe = sizeof(typename TR::Elem) / sizeof(typename TR::Word);
+    while ((m + R->b - 1) / R->b >= WR_MAX_BLOCKS) {
+        if ((uint64_t)R->b * 2 * wpe > 2048) return false;
+        R->b *= 2;
+    }
+    return true;
 }
 
 bool log_enabled() {
@@ -1069,7 +1084,7 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     uint32_t level = 0;
     Level<DT> levels[2];
     std::vector<LevelMarks> marks;
-    std::vector<uint32_t> level_tasks, level_stripes, level_workers;
+    std::vector<uint32_t> level_tasks, level_stripes, level_workers, level_b;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     const bool check = (R.flags & IPS4O_FLAG_CHECK) != 0;
     // host time (IPS4O_LOG): planning and enqueueing, waiting for a level's
@@ -1084,12 +1099,21 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         Level<DT>& L = levels[par];
         Arena& work = par ? h->work2 : h->work;
         HostArena& rb = par ? h->hbounds2 : h->hbounds;
-        plan_level<DT>(L, cur, R, level, level == 0, 0, segmented && level == 0, 0, buf_budget);
-        rc = work.ensure(level_bytes<DT>(L, R.b));
+        // the block size of this level: the caller's, doubled while its
+        // largest subproblem has too many blocks for the permutation word
+        Resolved RL = R;
+        {
+            uint64_t mmax = 0;
+            for (const Seg& sg : cur) mmax = std::max<uint64_t>(mmax, sg.m);
+            if (!scale_block<DT>(&RL, mmax)) return IPS4O_ERR_NOT_SUPPORTED;
+        }
+        level_b.push_back(RL.b);
+        plan_level<DT>(L, cur, RL, level, level == 0, 0, segmented && level == 0, 0, buf_budget);
+        rc = work.ensure(level_bytes<DT>(L, RL.b));
         if (rc) return rc;
         rc = ensure_bufs<DT>(h, L, st);
         if (rc) return rc;
-        carve_level<DT>(L, work.p, h->misc.p, d_data, h->bufs.p, R, level);
+        carve_level<DT>(L, work.p, h->misc.p, d_data, h->bufs.p, RL, level);
         {
             uint64_t lm = 0;
             for (const Seg& sg : cur) lm += sg.m;
@@ -1161,7 +1185,7 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
             for (int q = 0; q < 4; ++q)
                 for (int r = 0; r < STAT_SPREAD; ++r) now[q] += blk[r * 8 + q];
         }
-        account_level<DT>(tm, marks[l], now, zero, R.b);
+        account_level<DT>(tm, marks[l], now, zero, level_b[l]);
         h->last.block_moves += now[0];
         h->last.block_skips += now[1];
         if (log_enabled())
@@ -1179,7 +1203,7 @@ int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, h
     if (rc) return rc;
     h->last = ips4o_stats{};
     if (n <= 1) return IPS4O_OK;
-    return run_sort_list<DT>(h, d_data, n, std::vector<Seg>{Seg{0, n, 0}}, R, false, st);
+    return run_sort_list<DT>(h, d_data, n, std::vector<Seg>{Seg{0, n, 0, 0}}, R, false, st);
 }
 
 // Segment i is [offs[i], offs[i + 1]); the offsets were checked by the caller.
@@ -1191,9 +1215,17 @@ int run_sort_segmented(ips4o_handle* h, void* d_data, const uint64_t* offs, uint
     if (rc) return rc;
     h->last = ips4o_stats{};
     std::vector<Seg> segs;
+    uint64_t mmax = 0;
     for (uint32_t i = 0; i < nseg; ++i)
-        if (offs[i + 1] - offs[i] > 1) segs.push_back(Seg{offs[i], offs[i + 1] - offs[i], i});
+        if (offs[i + 1] - offs[i] > 1) {
+            segs.push_back(Seg{offs[i], offs[i + 1] - offs[i], i, 0});
+            mmax = std::max<uint64_t>(mmax, offs[i + 1] - offs[i]);
+        }
     if (segs.empty()) return IPS4O_OK;
+    {
+        Resolved RT = R;      // refuse before any device work if no block size fits
+        if (!scale_block<DT>(&RT, mmax)) return IPS4O_ERR_NOT_SUPPORTED;
+    }
     return run_sort_list<DT>(h, d_data, offs[nseg], std::move(segs), R, true, st);
 }
 
@@ -1203,6 +1235,7 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     Resolved R;
     int rc = resolve<DT>(p, &R);
     if (rc) return rc;
+    if (!scale_block<DT>(&R, n)) return IPS4O_ERR_NOT_SUPPORTED;
     HostTree<DT> ht;
     rc = build_host_tree<DT>(h_split, m, eq, n, R.b, &ht);
     if (rc) return rc;
@@ -1351,8 +1384,14 @@ template <int DT>
 size_t workspace_bound(uint64_t n, const Resolved& R) {
     using TR = Traits<DT>;
     const uint64_t s = sizeof(typename TR::Elem), ks = sizeof(typename TR::Key);
-    const uint64_t b = R.b, cap = R.cap;
+    const uint64_t b0 = R.b, cap = R.cap;
     if (n <= 1) return 0;
+    // block sizes: the top level's (scaled for n), and the deeper levels'
+    // (scaled only when a subproblem can be large enough to need it)
+    Resolved RT = R;
+    (void)scale_block<DT>(&RT, n);
+    const uint64_t b = RT.b;
+    const uint64_t bd = n >= WR_MAX_BLOCKS * b0 ? b : b0;
     auto slack = [](uint64_t x) { return x + x / 4; };
     auto al = [](uint64_t x) { return x + 256; };
     const uint64_t nb = (n + b - 1) / b;
@@ -1361,13 +1400,13 @@ size_t workspace_bound(uint64_t n, const Resolved& R) {
     if (n > cap) {
         const uint64_t budget = n / kBufBudgetDiv + 1;
         const uint64_t root = 2 * (uint64_t)KMAX * b * std::max<uint64_t>(huge, R.stripes);
-        const uint64_t deep = 8 * b * n / cap + 1 + 2 * (uint64_t)KT_MAX * b * huge;
+        const uint64_t deep = 8 * bd * n / cap + 1 + 2 * (uint64_t)KT_MAX * bd * huge;
         bufs = std::max(budget, std::max(root, deep));
         const uint64_t T = n / (cap + 1) + 1;
         const uint64_t sumk = std::max<uint64_t>((uint64_t)KT_MAX, 4 * n / cap + 2 * T);
         const uint64_t sumkb = 2 * sumk;
         const uint64_t S = std::max<uint64_t>(STRIPES_PER_TASK_MAX, kLevelStripes + T + huge);
-        const uint64_t counts = bufs / (2 * b) + 1;
+        const uint64_t counts = bufs / (2 * b0) + 1;
         const uint64_t lv = al(T * sizeof(TaskD)) + al(S * sizeof(StripeD)) + al(T * sizeof(TaskS)) +
                             2 * al(sumk * ks) + al((sumkb + T) * 8) + al((sumkb + T) * 4) +
                             al(sumkb * sizeof(BucketSlot)) + al(counts * 4) + 2 * al(S * 4) + 256;
@@ -1381,6 +1420,25 @@ size_t workspace_bound(uint64_t n, const Resolved& R) {
         scratch = slack(std::max(std::min<uint64_t>(bins, 2 * kBaseGrid) * small_bin_cap<DT>(),
                                  std::min<uint64_t>(bins, kBaseGrid) * (uint64_t)TR::kBaseCap) * s);
     return (size_t)(bufs * s + work + misc + segs + scratch);
+}
+
+// n elements fit the permutation's block indices with some block size.
+template <int DT>
+int check_blocks(uint64_t n, const ips4o_params* params) {
+    Resolved R;
+    int rc = resolve<DT>(params, &R);
+    if (rc) return rc;
+    return scale_block<DT>(&R, n) ? IPS4O_OK : IPS4O_ERR_NOT_SUPPORTED;
+}
+
+template <int DT>
+int workspace_query(uint64_t n, const ips4o_params* params, size_t* bytes) {
+    Resolved R;
+    int rc = resolve<DT>(params, &R);
+    if (rc) return rc;
+    if (!scale_block<DT>(&R, n)) return IPS4O_ERR_NOT_SUPPORTED;
+    *bytes = workspace_bound<DT>(n, R);
+    return IPS4O_OK;
 }
 
 int check_ptr(const void* p, uint64_t n, int dt) {
@@ -1480,15 +1538,7 @@ int ips4o_workspace_size(const ips4o_handle* h, int dtype, uint64_t n, const ips
     int rc = check_params(params, dtype);
     if (rc) return rc;
     if (n >= kMaxElements) return IPS4O_ERR_NOT_SUPPORTED;
-    Resolved R;
-    switch (dtype) {
-    case DT_U64: resolve<DT_U64>(params, &R); *bytes = workspace_bound<DT_U64>(n, R); break;
-    case DT_F64: resolve<DT_F64>(params, &R); *bytes = workspace_bound<DT_F64>(n, R); break;
-    case DT_PAIR: resolve<DT_PAIR>(params, &R); *bytes = workspace_bound<DT_PAIR>(n, R); break;
-    case DT_QUARTET: resolve<DT_QUARTET>(params, &R); *bytes = workspace_bound<DT_QUARTET>(n, R); break;
-    default: resolve<DT_BYTES100>(params, &R); *bytes = workspace_bound<DT_BYTES100>(n, R); break;
-    }
-    return IPS4O_OK;
+    DISPATCH(dtype, workspace_query<D>(n, params, bytes));
 }
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
@@ -1575,7 +1625,7 @@ int ips4o_check_args(const void* d_data, uint64_t n, int dtype, const ips4o_para
     rc = check_params(params, dtype);
     if (rc) return rc;
     if (n >= kMaxElements) return IPS4O_ERR_NOT_SUPPORTED;
-    return IPS4O_OK;
+    DISPATCH(dtype, check_blocks<D>(n, params));
 }
 
 int ips4o_check_segments(const void* d_data, int dtype, const uint64_t* h_offsets, uint32_t num_segments,

@@ -1045,45 +1045,62 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
 // stripes are summed by NT / K thread groups side by side.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_scan(Ctx<DT> c) {
-    __shared__ uint32_t tot[KMAX];
-    __shared__ uint32_t part[NT];
-    __shared__ uint32_t sh[NT / 64 + 1];
+    // bucket totals are 64-bit: a bucket of a subproblem of 2^32 or more
+    // elements (all-equal keys, say) can hold that many
+    __shared__ uint64_t tot[KMAX];
+    __shared__ uint64_t part[NT];
+    __shared__ uint64_t sh[NT / 64 + 1];
     const uint32_t t = blockIdx.x;
     const TaskD td = c.tasks[t];
     const uint32_t K = c.ts[t].K;
     const uint32_t P = K <= NT / 2 ? NT / K : 1u;
     if (P > 1) {
         const uint32_t j = threadIdx.x % K, p = threadIdx.x / K;
-        uint32_t s = 0;
+        uint64_t s = 0;
         if (p < P)
             for (uint32_t q = p; q < td.nstripes; q += P) s += c.counts[td.cnt_begin + (uint64_t)q * td.kbuf + j];
         part[threadIdx.x] = s;
         __syncthreads();
         if (threadIdx.x < K) {
-            uint32_t v = 0;
+            uint64_t v = 0;
             for (uint32_t q = 0; q < P; ++q) v += part[q * K + threadIdx.x];
             tot[threadIdx.x] = v;
         }
     } else {
         for (uint32_t j = threadIdx.x; j < K; j += NT) {
-            uint32_t s = 0;
+            uint64_t s = 0;
             for (uint32_t q = 0; q < td.nstripes; ++q) s += c.counts[td.cnt_begin + (uint64_t)q * td.kbuf + j];
             tot[j] = s;
         }
     }
     __syncthreads();
-    // 64-bit prefix: per-thread chunk sums fit 32 bits only if m < 2^32;
-    // segments are limited to < 2^32 elements by the planner.
-    uint32_t total = lds_excl_scan<NT>(tot, K, sh);
+    // exclusive prefix over the K totals, PER consecutive buckets a thread
+    constexpr uint32_t PER = (KMAX + NT - 1) / NT;
+    uint64_t loc = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) {
+        const uint32_t j = threadIdx.x * PER + i;
+        if (j < K) loc += tot[j];
+    }
+    uint64_t total;
+    uint64_t pre = block_excl_scan64<NT>(loc, sh, &total);
     (void)total;
     uint64_t* bd = c.bounds + td.slot_begin + t;
     uint32_t* dl = c.delim + td.slot_begin + t;
-    for (uint32_t j = threadIdx.x; j <= K; j += NT) {
-        uint64_t B = (j < K) ? (uint64_t)tot[j] : td.m;
-        bd[j] = B;
-        dl[j] = (uint32_t)((B + c.b - 1) / c.b);
+#pragma unroll
+    for (uint32_t i = 0; i < PER; ++i) {
+        const uint32_t j = threadIdx.x * PER + i;
+        if (j < K) {
+            bd[j] = pre;
+            dl[j] = (uint32_t)((pre + c.b - 1) / c.b);
+            pre += tot[j];
+        }
     }
-    if (threadIdx.x == 0) c.ts[t].ovf_bucket = NO_BUCKET;
+    if (threadIdx.x == 0) {
+        bd[K] = td.m;
+        dl[K] = (uint32_t)((td.m + c.b - 1) / c.b);
+        c.ts[t].ovf_bucket = NO_BUCKET;
+    }
 }
 
 // ------------------------------------------------------ empty-block fix

@@ -74,7 +74,11 @@ def test_check_args(ips):
     assert _check(ips, 0x1004, 5, ips.BYTES100) == ok           # 4-byte records
     assert _check(ips, 0x1002, 5, ips.BYTES100) == bad
     assert _check(ips, 0x1000, 5, 7) == bad                     # unknown dtype
-    assert _check(ips, 0x1000, 1 << 32, ips.U64) == unsup
+    assert _check(ips, 0x1000, 1 << 32, ips.U64) == ok          # beyond 32-bit sizes
+    assert _check(ips, 0x1000, 1 << 36, ips.U64) == unsup       # blocks beyond the pointer word
+    assert _check(ips, 0x1000, 1 << 40, ips.U64) == unsup
+    assert _check(ips, 0x1000, 1 << 31, ips.BYTES100) == unsup  # 64 records per block at most
+    assert _check(ips, 0x1000, 1 << 30, ips.BYTES100) == ok
     assert _check(ips, 0x1000, 100, ips.U64, k=3) == bad        # not a power of two
     assert _check(ips, 0x1000, 100, ips.U64, k=2048) == bad     # above 1024
     assert _check(ips, 0x1000, 100, ips.U64, k=1024) == ok
@@ -129,8 +133,10 @@ def test_check_segments(ips):
     assert lib.ips4o_check_segments(None, ips.U64, ok.ctypes.data, 4, None) == -1
     assert lib.ips4o_check_segments(ctypes.c_void_p(4100), ips.U64, ok.ctypes.data, 4, None) == -1
     assert lib.ips4o_check_segments(dev, 9, ok.ctypes.data, 4, None) == -1
-    huge = np.array([0, 1 << 32], dtype=np.uint64)
+    huge = np.array([0, 1 << 40], dtype=np.uint64)
     assert lib.ips4o_check_segments(dev, ips.U64, huge.ctypes.data, 1, None) == -4
+    big = np.array([0, 1 << 32], dtype=np.uint64)
+    assert lib.ips4o_check_segments(dev, ips.U64, big.ctypes.data, 1, None) == 0
     # offsets may start past 0 (the elements before are left alone)
     late = np.array([7, 9, 30], dtype=np.uint64)
     assert lib.ips4o_check_segments(dev, ips.PAIR, late.ctypes.data, 2, None) == 0

@@ -8,6 +8,8 @@
   inputs below n).  The oracle outputs are computed ahead in worker threads
   (its C and numpy calls release the interpreter lock), at most a few cells
   ahead so that the host holds a bounded number of 8 GiB arrays.
+* 2^32 u64 keys (RootDup, ReverseSorted), checked in chunks against the
+  oracle's chunkable closed forms.
 * Record configuration: 2^28 Pair, Quartet and 100Bytes records with Uniform
   and RootDup keys, generated and uploaded in chunks.  The payload of every
   input record is its index, so three device-side checks together pin the
@@ -116,6 +118,35 @@ def test_sort_2pow30_matches_oracle(env, ahead, dist, dtype):
     want = ahead.get((dist, dtype)).view(np.uint64)
     at = first_difference(out, want)
     assert at is None, f"{dtype} {dist}: first difference at {at}: GPU {int(out[at]):#x}, oracle {int(want[at]):#x}"
+
+
+N32 = 1 << 32
+
+
+@pytest.mark.parametrize("dist", ["rootdup", "reverse"])
+def test_sort_2pow32_u64(env, dist):
+    """2^32 u64 keys (32 GiB, the largest size of the paper's experiments;
+    beyond 32-bit element counts): generated and uploaded in chunks, sorted,
+    and compared chunk by chunk, element by element, with the oracle's
+    sorted arrangement (closed form for RootDup, the Sorted sequence for
+    ReverseSorted)."""
+    torch, ips, h = env
+    seed = workloads.seed_for(1, dist, "u64")
+    chunk = 1 << 26
+    print(f"[gpu] sort u64 {dist} n=2^32 seed={seed:#x}", flush=True)
+    d = torch.empty(N32, dtype=torch.int64, device="cuda:0")
+    for f in range(0, N32, chunk):
+        part = workloads.generate_range(dist, "u64", N32, seed, f, chunk)
+        d[f:f + chunk].copy_(torch.from_numpy(part.view(np.int64)))
+    ips.ips4o_sort(h, d, N32, "u64")
+    torch.cuda.synchronize()
+    for f in range(0, N32, chunk):
+        got = d[f:f + chunk].cpu().numpy().view(np.uint64)
+        want = oracle.expected_sorted_range(dist, "u64", N32, seed, f, chunk)
+        at = first_difference(got, want)
+        assert at is None, f"{dist}: first difference at {f + at}: GPU {int(got[at]):#x}, oracle {int(want[at]):#x}"
+    del d
+    torch.cuda.empty_cache()
 
 
 def upload_chunked(torch, dist, dtype, n, seed):

@@ -382,6 +382,24 @@ def test_select_splitters_capped_reading(oracle_mod, workloads_mod):
     assert cases >= 4       # the thinning was exercised
 
 
+@pytest.mark.parametrize("dtype", ["u64", "f64"])
+@pytest.mark.parametrize("dist", ["rootdup", "sorted", "reverse", "ones"])
+def test_expected_sorted_range_is_a_slice(oracle_mod, workloads_mod, dtype, dist):
+    """The chunked sorted arrangement (used for inputs too large for the
+    host) equals slices of the counting / qsort routes, for square and
+    non-square n, with chunks that split runs of equal keys."""
+    for n in (1000, 4096, 65537, 100003):
+        seed = 4242 + n
+        whole = oracle_mod.sort(workloads_mod.generate(dist, dtype, n, seed), dtype)
+        for first, count in [(0, n), (0, 1), (n - 1, 1), (17, 333), (n // 3, n // 2), (n, 0)]:
+            got = oracle_mod.expected_sorted_range(dist, dtype, n, seed, first, count)
+            assert np.array_equal(got.view(np.uint64), whole[first:first + count].view(np.uint64)), (n, first, count)
+        parts = [oracle_mod.expected_sorted_range(dist, dtype, n, seed, f, min(999, n - f)) for f in range(0, n, 999)]
+        assert np.array_equal(np.concatenate(parts).view(np.uint64), whole.view(np.uint64))
+    with pytest.raises(ValueError):
+        oracle_mod.expected_sorted_range(dist, dtype, 100, 1, 90, 11)
+
+
 # ---------------------------------------------------------- generators
 def test_generator_closed_forms(workloads_mod):
     n = 1 << 12

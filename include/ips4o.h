@@ -145,6 +145,24 @@ int ips4o_workspace_size(const ips4o_handle *h, int dtype, uint64_t n, const ips
 int ips4o_sort(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
                const ips4o_params *params, void *hip_stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ips4o_sort of a small
+ * array that allocates nothing.  d_data[0..n) (device) is sorted in place as
+ * one base-case bin, for n <= ips4o_small_max(dtype) elements (16384 u64/f64
+ * keys, 8192 pairs, 4096 quartets or 100-byte records); larger n returns
+ * IPS4O_ERR_NOT_SUPPORTED before any device work.  The bin list, the
+ * counters and the record scratch live in a fixed 512 KiB device array per
+ * GPU that the library holds until the process ends, set up by a kernel on
+ * `hip_stream` (no memset, no host staging); the call returns after
+ * enqueueing its kernels and makes no hipMalloc, hipFree or other
+ * allocating call.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (different streams or threads) race; calls on one
+ * stream are ordered and safe. */
+int ips4o_sort_small(ips4o_handle *h, void *d_data, uint64_t n, int dtype, void *hip_stream);
+
+/* Largest n ips4o_sort_small accepts for `dtype` (0 for an unknown dtype). */
+uint64_t ips4o_small_max(int dtype);
+
 /* Sort each of num_segments independent segments of one array in place:
  * segment i is d_data[h_offsets[i] .. h_offsets[i+1]).  The recursion of
  * Section 4 already treats the buckets of a level as independent

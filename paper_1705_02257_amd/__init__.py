@@ -31,6 +31,7 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort",
+           "ips4o_sort_small", "ips4o_small_max",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
            "ips4o_last_pass_stats",
@@ -83,6 +84,9 @@ def _load():
     L.ips4o_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     L.ips4o_workspace_size.argtypes = [vp, i32, u64, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
     L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
+    L.ips4o_sort_small.argtypes = [vp, vp, u64, i32, vp]
+    L.ips4o_small_max.argtypes = [i32]
+    L.ips4o_small_max.restype = u64
     L.ips4o_sort_segmented.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
     L.ips4o_distribute.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, ctypes.POINTER(u32),
                                    ctypes.POINTER(Params), vp]
@@ -98,7 +102,7 @@ def _load():
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
-    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
+    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort_small", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
                  "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
@@ -213,6 +217,20 @@ def ips4o_sort(h, data, n, dtype, params=None, stream=None) -> None:
     d = _dtype(dtype)
     _check(_L().ips4o_sort(h, _addr(data, n * ELEM_BYTES[d]), n, d, _params(params), _stream(stream)),
            "ips4o_sort", h)
+
+
+def ips4o_small_max(dtype) -> int:
+    """Largest element count ips4o_sort_small accepts for `dtype`."""
+    return int(_L().ips4o_small_max(_dtype(dtype)))
+
+
+def ips4o_sort_small(h, data, n, dtype, stream=None) -> None:
+    """Sort data[0:n] in place like ips4o_sort, for n <= ips4o_small_max(dtype),
+    with no allocation (the library's fixed per-GPU array; returns after
+    enqueue on `stream`)."""
+    d = _dtype(dtype)
+    _check(_L().ips4o_sort_small(h, _addr(data, n * ELEM_BYTES[d]), int(n), d, _stream(stream)),
+           "ips4o_sort_small", h)
 
 
 def ips4o_sort_segmented(h, data, offsets, dtype, params=None, stream=None) -> None:

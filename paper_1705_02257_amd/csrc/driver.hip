@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -144,12 +145,13 @@ enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_B
 struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
+    void* small = nullptr;    // this device's address of the file-scope array `scratch`
     Arena work;       // per-level descriptors and bucket state (even levels)
     Arena work2;      // the same for odd levels (planned while the previous level runs)
     Arena bufs;       // stripe buffers: partial buffers and side areas, shared by all levels
     Arena misc;       // error word, per-level counters
     Arena segs;       // base-case segment list
-    Arena scratch;    // base-case record scratch
+    Arena rscratch;   // base-case record scratch
     HostArena hbounds;    // pinned copy of a level's error word, task state and bounds (even levels)
     HostArena hbounds2;   // the same for odd levels
     HostArena hdesc;      // pinned staging of a level's descriptors (even levels)
@@ -961,9 +963,9 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     const uint32_t g_large = (uint32_t)std::min<size_t>(nlarge, kBaseGrid);
     Elem* scr = nullptr;
     if (!plain) {
-        rc = h->scratch.ensure(std::max((size_t)g_small * half, (size_t)g_large * TR::kBaseCap) * sizeof(Elem));
+        rc = h->rscratch.ensure(std::max((size_t)g_small * half, (size_t)g_large * TR::kBaseCap) * sizeof(Elem));
         if (rc) return rc;
-        scr = (Elem*)h->scratch.p;
+        scr = (Elem*)h->rscratch.p;
     }
     HIP_TRY(hipMemcpyAsync(h->segs.p, h->hsegs.p, list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
     Ctx<DT> c{};
@@ -1415,11 +1417,11 @@ size_t workspace_bound(uint64_t n, const Resolved& R) {
     const uint64_t misc = slack(kStatsOffset + (uint64_t)kStatLevels * kStatsBytes);
     const uint64_t bins = std::min<uint64_t>(n / 2 + 1, kBaseChunk);
     const uint64_t segs = slack(2 * bins * sizeof(SegD));
-    uint64_t scratch = 0;
+    uint64_t recs = 0;
     if (DT != DT_U64 && DT != DT_F64)
-        scratch = slack(std::max(std::min<uint64_t>(bins, 2 * kBaseGrid) * small_bin_cap<DT>(),
+        recs = slack(std::max(std::min<uint64_t>(bins, 2 * kBaseGrid) * small_bin_cap<DT>(),
                                  std::min<uint64_t>(bins, kBaseGrid) * (uint64_t)TR::kBaseCap) * s);
-    return (size_t)(bufs * s + work + misc + segs + scratch);
+    return (size_t)(bufs * s + work + misc + segs + recs);
 }
 
 // n elements fit the permutation's block indices with some block size.
@@ -1482,6 +1484,82 @@ int set_device(ips4o_handle* h) {
 
 }  // namespace
 
+// ---------------------------------------------------- sort without allocation
+// For callers that cannot allocate (code under graph capture, tight serving
+// loops): ips4o_sort_small sorts one base-case bin with its bin list, its
+// merge-sort hand-back counters and its record scratch in this file-scope
+// array, which every GPU the library runs on holds until the process ends.
+// Host code never uses the array's name as an address: ips4o_create asks
+// for the current device's address once per device (hipGetSymbolAddress)
+// and every launch gets that pointer.
+constexpr size_t kSmallBytes = 512 * 1024;
+constexpr size_t kSmallRecords = 256;       // offset of the record scratch
+static __device__ __align__(256) unsigned char scratch[kSmallBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_small_mu;
+void* g_small_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current), fetched once.
+int small_scratch(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_small_mu);
+    if (device < 0 || device >= kMaxDevices) return IPS4O_ERR_NOT_SUPPORTED;
+    if (!g_small_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IPS4O_ERR_HIP;
+        g_small_ptr[device] = p;
+    }
+    *out = g_small_ptr[device];
+    return IPS4O_OK;
+}
+
+// Bin list [0] = the whole array, hand-back counters cleared (a kernel
+// rather than a memset, so that the call can be captured in a graph).
+__global__ void k_small_setup(SegD* bins, uint32_t* nfail, uint64_t n) {
+    if (threadIdx.x == 0) {
+        SegD sd;
+        sd.off = 0;
+        sd.len = (uint32_t)n;
+        sd.pad = 0;
+        bins[0] = sd;
+        nfail[0] = 0;
+        nfail[1] = 0;
+    }
+}
+
+template <int DT>
+int run_sort_small(ips4o_handle* h, void* d_data, uint64_t n, hipStream_t st) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    constexpr int BNT = Shape<DT>::BNT;
+    constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
+    static_assert(kSmallRecords + (size_t)TR::kBaseCap * sizeof(Elem) <= kSmallBytes, "record scratch fits");
+    if (n > (uint64_t)TR::kBaseCap) return IPS4O_ERR_NOT_SUPPORTED;
+    if (n <= 1) return IPS4O_OK;
+    char* base = (char*)h->small;
+    SegD* bins = (SegD*)base;                      // [0] the bin, [1] handed back to the merge sort
+    uint32_t* nfail = (uint32_t*)(base + 64);
+    Elem* scr = plain ? nullptr : (Elem*)(base + kSmallRecords);
+    hipLaunchKernelGGL(k_small_setup, dim3(1), dim3(64), 0, st, bins, nfail, n);
+    HIP_TRY(hipGetLastError());
+    Ctx<DT> c{};
+    c.data = (Elem*)d_data;
+    if (plain && n <= kTinyBin) {
+        if constexpr (plain) {
+            hipLaunchKernelGGL((k_basecase_tiny<DT, kTinyBin / 64>), dim3(1), dim3(256), 0, st, c,
+                               (const SegD*)bins, 1u);
+            HIP_TRY(hipGetLastError());
+        }
+        return IPS4O_OK;
+    }
+    if (n <= small_bin_cap<DT>()) return launch_basecase<DT, BNT / 2>(h, c, bins, 1, 1, scr, bins + 1, nfail, st);
+    return launch_basecase<DT, BNT>(h, c, bins, 1, 1, scr, bins + 1, nfail + 1, st);
+}
+
+}  // namespace
+
 #define DISPATCH(dt, CALL)                                   \
     switch (dt) {                                            \
     case DT_U64: { constexpr int D = DT_U64; return CALL; }  \
@@ -1503,10 +1581,20 @@ int ips4o_create(int hip_device, ips4o_handle** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return IPS4O_ERR_HIP;
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return IPS4O_ERR_NOT_SUPPORTED;
+    // this device's address of the array ips4o_sort_small works in (set-up
+    // once per device, with the device current)
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return IPS4O_ERR_HIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return IPS4O_ERR_HIP;
+    void* small = nullptr;
+    const int rs = small_scratch(hip_device, &small);
+    (void)hipSetDevice(prev);
+    if (rs) return rs;
     ips4o_handle* h = new (std::nothrow) ips4o_handle();
     if (!h) return IPS4O_ERR_OUT_OF_MEMORY;
     h->device = hip_device;
     h->num_cus = prop.multiProcessorCount;
+    h->small = small;
     *out = h;
     return IPS4O_OK;
 }
@@ -1525,7 +1613,7 @@ void ips4o_destroy(ips4o_handle* h) {
         if (e) (void)hipEventDestroy(e);
     h->misc.release();
     h->segs.release();
-    h->scratch.release();
+    h->rscratch.release();
     h->hbounds.release();
     h->hsegs.release();
     delete h;
@@ -1543,7 +1631,7 @@ int ips4o_workspace_size(const ips4o_handle* h, int dtype, uint64_t n, const ips
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {
     if (!h || !bytes) return IPS4O_ERR_INVALID_ARG;
-    *bytes = h->work.bytes + h->work2.bytes + h->bufs.bytes + h->misc.bytes + h->segs.bytes + h->scratch.bytes;
+    *bytes = h->work.bytes + h->work2.bytes + h->bufs.bytes + h->misc.bytes + h->segs.bytes + h->rscratch.bytes;
     return IPS4O_OK;
 }
 
@@ -1557,6 +1645,31 @@ int ips4o_sort(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const ips4o
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     DISPATCH(dtype, run_sort<D>(h, d_data, n, params, st));
+}
+
+int ips4o_sort_small(ips4o_handle* h, void* d_data, uint64_t n, int dtype, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    int rc = check_ptr(d_data, n, dtype);
+    if (rc) return rc;
+    if (n > ips4o_small_max(dtype)) return IPS4O_ERR_NOT_SUPPORTED;
+    if (n <= 1) return IPS4O_OK;
+    if (!h->small) return IPS4O_ERR_HIP;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_sort_small<D>(h, d_data, n, st));
+}
+
+uint64_t ips4o_small_max(int dtype) {
+    switch (dtype) {
+    case DT_U64: return (uint64_t)Traits<DT_U64>::kBaseCap;
+    case DT_F64: return (uint64_t)Traits<DT_F64>::kBaseCap;
+    case DT_PAIR: return (uint64_t)Traits<DT_PAIR>::kBaseCap;
+    case DT_QUARTET: return (uint64_t)Traits<DT_QUARTET>::kBaseCap;
+    case DT_BYTES100: return (uint64_t)Traits<DT_BYTES100>::kBaseCap;
+    }
+    return 0;
 }
 
 int ips4o_sort_segmented(ips4o_handle* h, void* d_data, int dtype, const uint64_t* h_offsets, uint32_t num_segments,

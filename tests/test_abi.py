@@ -207,3 +207,12 @@ def test_workspace_size_query(ips):
     # larger arrays need no more than proportionally more
     a, b = ips.ips4o_workspace_size("u64", 1 << 28), ips.ips4o_workspace_size("u64", 1 << 29)
     assert a < b <= 2 * a + (1 << 26)
+
+
+def test_small_sort_limits(ips):
+    """The no-allocation sort's size limits are one base-case bin per type;
+    a NULL handle is refused."""
+    assert [ips.ips4o_small_max(d) for d in ("u64", "f64", "pair", "quartet", "bytes100")] == \
+        [16384, 16384, 8192, 4096, 4096]
+    assert ips.lib.ips4o_small_max(7) == 0
+    assert ips.lib.ips4o_sort_small(None, ctypes.c_void_p(4096), 10, ips.U64, None) == -1

@@ -27,10 +27,13 @@
  * 4 bytes for BYTES100.  The caller owns all arrays it passes.
  *
  * Streams: `hip_stream` is a hipStream_t (NULL = the null stream).  Work is
- * enqueued on that stream.  The recursion is planned on the host: a level's
- * bucket bounds are copied back as soon as they exist and the next level is
- * enqueued while the current one still runs; every call synchronizes the
- * stream before it returns.  A handle serves one call at a time (it owns
+ * enqueued on that stream, after whatever the caller enqueued before.  The
+ * recursion is planned on the host: a level's bucket bounds are copied back
+ * as soon as they exist and the next level is enqueued while the current
+ * one still runs.  Which calls return after enqueue: ips4o_sort_small only.
+ * The others (ips4o_sort, ips4o_sort_segmented[_dev], ips4o_distribute[_dev],
+ * ips4o_classify, ips4o_select_splitters) wait for their work on the stream
+ * before they return, so that device faults are reported by the call itself.  A handle serves one call at a time (it owns
  * the workspace and pinned staging buffers); use one handle per host thread.
  *
  * Errors: every call validates its arguments before touching the device and
@@ -182,6 +185,14 @@ uint64_t ips4o_small_max(int dtype);
 int ips4o_sort_segmented(ips4o_handle *h, void *d_data, int dtype, const uint64_t *h_offsets,
                          uint32_t num_segments, const ips4o_params *params, void *hip_stream);
 
+/* ips4o_sort_segmented with the offset table in device memory: d_offsets
+ * (device pointer, 8-byte aligned) holds num_segments + 1 non-decreasing
+ * element offsets; it is copied to the host in stream order (so earlier
+ * work on hip_stream may write it) before the recursion is planned there.
+ * Errors and return as for ips4o_sort_segmented. */
+int ips4o_sort_segmented_dev(ips4o_handle *h, void *d_data, int dtype, const uint64_t *d_offsets,
+                             uint32_t num_segments, const ips4o_params *params, void *hip_stream);
+
 /* One distribution step with caller-given splitters (Section 4: local
  * classification, block permutation, cleanup; no sampling, no recursion).
  * h_splitters: host pointer to num_splitters whole elements of `dtype`
@@ -199,6 +210,17 @@ int ips4o_distribute(ips4o_handle *h, void *d_data, uint64_t n, int dtype,
                      const void *h_splitters, uint32_t num_splitters, int equality_buckets,
                      uint64_t *h_bounds_out, uint32_t *num_buckets_out,
                      const ips4o_params *params, void *hip_stream);
+
+/* ips4o_distribute with the splitters and the results in device memory:
+ * d_splitters (device, aligned for dtype) holds num_splitters elements
+ * whose keys are non-decreasing (copied to the host in stream order, where
+ * the search tree is built); d_bounds_out (device, 8-byte aligned) receives
+ * K + 1 uint64 bucket boundaries -- room for 2 * num_splitters + 2 is
+ * enough -- and *d_num_buckets_out (device, may be NULL) receives K.  The
+ * call returns once they are written.  Errors as for ips4o_distribute. */
+int ips4o_distribute_dev(ips4o_handle *h, void *d_data, uint64_t n, int dtype, const void *d_splitters,
+                         uint32_t num_splitters, int equality_buckets, uint64_t *d_bounds_out,
+                         uint32_t *d_num_buckets_out, const ips4o_params *params, void *hip_stream);
 
 /* Bucket index of every element for caller-given splitters (the branchless
  * tree classification of Section 3 with the equality test of Section 4).

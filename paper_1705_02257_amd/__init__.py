@@ -31,7 +31,7 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort",
-           "ips4o_sort_small", "ips4o_small_max",
+           "ips4o_sort_small", "ips4o_small_max", "ips4o_sort_segmented_dev", "ips4o_distribute_dev",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
            "ips4o_last_pass_stats",
@@ -85,6 +85,8 @@ def _load():
     L.ips4o_workspace_size.argtypes = [vp, i32, u64, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
     L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
     L.ips4o_sort_small.argtypes = [vp, vp, u64, i32, vp]
+    L.ips4o_sort_segmented_dev.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
+    L.ips4o_distribute_dev.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp, ctypes.POINTER(Params), vp]
     L.ips4o_small_max.argtypes = [i32]
     L.ips4o_small_max.restype = u64
     L.ips4o_sort_segmented.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
@@ -102,7 +104,8 @@ def _load():
     L.ips4o_last_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
-    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort_small", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
+    for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort_small",
+                 "ips4o_sort_segmented_dev", "ips4o_distribute_dev", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
                  "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
@@ -254,6 +257,25 @@ def ips4o_distribute(h, data, n, dtype, splitters: np.ndarray, equality_buckets:
                                 int(bool(equality_buckets)), bounds.ctypes.data, ctypes.byref(K),
                                 _params(params), _stream(stream)), "ips4o_distribute", h)
     return bounds[:K.value + 1].copy()
+
+
+def ips4o_sort_segmented_dev(h, data, d_offsets, num_segments, dtype, params=None, stream=None) -> None:
+    """ips4o_sort_segmented with the offset table (num_segments + 1 uint64
+    offsets) in a device tensor."""
+    _check(_L().ips4o_sort_segmented_dev(h, _addr(data), _dtype(dtype),
+                                         _addr(d_offsets, 8 * (num_segments + 1), "offsets"), num_segments,
+                                         _params(params), _stream(stream)), "ips4o_sort_segmented_dev", h)
+
+
+def ips4o_distribute_dev(h, data, n, dtype, d_splitters, num_splitters, equality_buckets: bool, d_bounds,
+                         d_num_buckets=None, params=None, stream=None) -> None:
+    """ips4o_distribute with splitters, bounds and bucket count in device tensors."""
+    d = _dtype(dtype)
+    _check(_L().ips4o_distribute_dev(h, _addr(data, n * ELEM_BYTES[d]), n, d,
+                                     _addr(d_splitters, num_splitters * ELEM_BYTES[d], "splitters"), num_splitters,
+                                     int(bool(equality_buckets)), _addr(d_bounds, 8 * (2 * num_splitters + 2), "bounds"),
+                                     _addr(d_num_buckets, 4, "num_buckets"), _params(params), _stream(stream)),
+           "ips4o_distribute_dev", h)
 
 
 def ips4o_classify(h, data, n, dtype, splitters: np.ndarray, equality_buckets: bool, out,

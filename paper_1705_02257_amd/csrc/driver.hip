@@ -158,6 +158,7 @@ struct ips4o_handle {
     HostArena hdesc2;     // the same for odd levels
     hipEvent_t scanned[2] = {nullptr, nullptr};   // a level's bounds have reached the host
     HostArena hsegs;      // pinned staging of the base-case bin list
+    HostArena hstage;     // pinned copies of caller arrays given in device memory
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
     std::vector<ips4o_pass_stat> pstats;   // per distribution level, then the base case
@@ -1616,6 +1617,7 @@ void ips4o_destroy(ips4o_handle* h) {
     h->rscratch.release();
     h->hbounds.release();
     h->hsegs.release();
+    h->hstage.release();
     delete h;
 }
 
@@ -1699,6 +1701,54 @@ int ips4o_distribute(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const
     hipStream_t st = (hipStream_t)hip_stream;
     DISPATCH(dtype, run_distribute<D>(h, d_data, n, h_splitters, num_splitters, equality_buckets,
                                       h_bounds_out, num_buckets_out, params, st));
+}
+
+int ips4o_sort_segmented_dev(ips4o_handle* h, void* d_data, int dtype, const uint64_t* d_offsets,
+                             uint32_t num_segments, const ips4o_params* params, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    if (num_segments == 0) return IPS4O_OK;
+    if (!d_offsets || ((uintptr_t)d_offsets & 7)) return IPS4O_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t bytes = ((size_t)num_segments + 1) * sizeof(uint64_t);
+    rc = h->hstage.ensure(bytes);
+    if (rc) return rc;
+    // the table may be written by earlier work on the stream: copy in order
+    HIP_TRY(hipMemcpyAsync(h->hstage.p, d_offsets, bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ips4o_sort_segmented(h, d_data, dtype, (const uint64_t*)h->hstage.p, num_segments, params, hip_stream);
+}
+
+int ips4o_distribute_dev(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const void* d_splitters,
+                         uint32_t num_splitters, int equality_buckets, uint64_t* d_bounds_out,
+                         uint32_t* d_num_buckets_out, const ips4o_params* params, void* hip_stream) {
+    if (!h || !d_bounds_out || ((uintptr_t)d_bounds_out & 7)) return IPS4O_ERR_INVALID_ARG;
+    if (d_num_buckets_out && ((uintptr_t)d_num_buckets_out & 3)) return IPS4O_ERR_INVALID_ARG;
+    const size_t s = elem_size(dtype);
+    if (s == 0 || !d_splitters || ((uintptr_t)d_splitters % elem_align(dtype))) return IPS4O_ERR_INVALID_ARG;
+    if (num_splitters < 1 || num_splitters > (uint32_t)KGIVEN_MAX) return IPS4O_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    // splitters to the host (the search tree is built there), in stream order
+    const size_t sbytes = (size_t)num_splitters * s, bbytes = (size_t)(2 * KGIVEN_MAX + 2) * sizeof(uint64_t);
+    rc = h->hstage.ensure(sbytes + bbytes + 64);
+    if (rc) return rc;
+    char* stage = (char*)h->hstage.p;
+    HIP_TRY(hipMemcpyAsync(stage, d_splitters, sbytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    uint64_t* hb = (uint64_t*)(stage + ((sbytes + 63) & ~(size_t)63));
+    uint32_t K = 0;
+    rc = ips4o_distribute(h, d_data, n, dtype, stage, num_splitters, equality_buckets, hb, &K, params, hip_stream);
+    if (rc) return rc;
+    uint32_t* hk = (uint32_t*)(hb + K + 1);
+    *hk = K;
+    HIP_TRY(hipMemcpyAsync(d_bounds_out, hb, (size_t)(K + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    if (d_num_buckets_out)
+        HIP_TRY(hipMemcpyAsync(d_num_buckets_out, hk, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));      // the staging buffer is reused by the next call
+    return IPS4O_OK;
 }
 
 int ips4o_classify(ips4o_handle* h, const void* d_data, uint64_t n, int dtype, const void* h_splitters,

@@ -305,6 +305,32 @@ def test_distribute_parity(env, dtype, eq, m, n):
     assert same_multiset(out, inp)
 
 
+@pytest.mark.parametrize("dtype,eq", [("u64", False), ("f64", True), ("pair", True)])
+def test_distribute_device_arrays(env, dtype, eq):
+    """Splitters, bounds and bucket count in device memory
+    (ips4o_distribute_dev): the oracle's bounds and bucket contents."""
+    torch, ips, h = env
+    n, m = 200003, 63
+    dist = "rootdup" if eq else "uniform"
+    inp = workloads.generate(dist, dtype, n, 77)
+    sp = _splitters(inp, dtype, m, m, dup=eq)
+    counts, bounds = oracle.bucket_bounds(inp, sp, dtype, eq)
+    d = to_dev(torch, inp)
+    d_sp = to_dev(torch, sp)
+    d_bounds = torch.full((2 * m + 2,), -1, dtype=torch.int64, device="cuda:0")
+    d_k = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    print(f"[gpu] distribute (device arrays) {dtype} eq={eq}", flush=True)
+    ips.ips4o_distribute_dev(h, d, n, dtype, d_sp, m, eq, d_bounds, d_k)
+    torch.cuda.synchronize()
+    K = int(d_k.item())
+    assert K == counts.shape[0]
+    assert np.array_equal(d_bounds[:K + 1].cpu().numpy().view(np.uint64), bounds)
+    out = from_dev(d, inp)
+    ids = oracle.classify(out, sp, dtype, eq).astype(np.int64)
+    assert np.array_equal(ids, np.repeat(np.arange(K), counts.astype(np.int64)))
+    assert same_multiset(out, inp)
+
+
 @pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 513])
 def test_distribute_tiny(env, n):
     torch, ips, h = env

@@ -115,3 +115,24 @@ def test_segmented_rejects_decreasing_offsets(env):
     d = to_dev(torch, np.zeros(100, dtype=np.uint64))
     with pytest.raises(Exception):
         ips.ips4o_sort_segmented(h, d, [0, 50, 40, 100], "u64")
+
+
+@pytest.mark.parametrize("dtype", ["u64", "pair"])
+def test_segmented_device_offsets(env, dtype):
+    """The offset table in device memory (ips4o_sort_segmented_dev), written
+    by the caller's stream just before the call: the same result as the
+    oracle's per-segment sort."""
+    torch, ips, h = env
+    cap = BASE_CAP[dtype]
+    rng = np.random.default_rng(11)
+    sizes = list(rng.permutation([0, 1, 3, 900, cap, cap + 1, 5 * cap + 3, 17, 0]))
+    offs, n = _layout(sizes, lead=5, trail=7)
+    inp = workloads.generate("uniform", dtype, n, workloads.seed_for(3, "uniform", dtype) + 1)
+    d = to_dev(torch, inp)
+    d_offs = torch.zeros(len(offs), dtype=torch.int64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    d_offs.copy_(torch.from_numpy(offs.view(np.int64)), non_blocking=False)
+    print(f"[gpu] segmented (device offsets) {dtype} n={n}", flush=True)
+    ips.ips4o_sort_segmented_dev(h, d, d_offs, len(sizes), dtype, None, stream)
+    torch.cuda.synchronize()
+    assert_segments_like_oracle(from_dev(d, inp), inp, offs, dtype)

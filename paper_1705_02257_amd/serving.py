@@ -2,8 +2,10 @@
 
 Requests are device tensors (u64, f64 or pair records) to be sorted in
 place.  A request is admitted once the device memory it needs (its bytes,
-twice over when it is staged with others) fits the pool budget beside the
-batches in flight; admitted requests of one element type are gathered into
+twice over when it is staged with others, plus the library workspace the
+batch may add to its worker's handle, from ips4o_workspace_size) fits the
+pool budget beside the batches in flight and the workspace the workers'
+handles already hold; admitted requests of one element type are gathered into
 a batch, copied end to end into a staging buffer, sorted by one
 ips4o_sort_segmented call and copied back (a batch of one request is sorted
 where it lies).  Several workers, each with its own library handle and HIP
@@ -26,7 +28,8 @@ import time
 
 import numpy as np
 
-from . import ips4o_create, ips4o_destroy, ips4o_sort, ips4o_sort_segmented, n_elements
+from . import (ips4o_create, ips4o_destroy, ips4o_sort, ips4o_sort_segmented, ips4o_workspace_bytes,
+               ips4o_workspace_size, n_elements)
 
 ELEM_BYTES = {"u64": 8, "f64": 8, "pair": 16}
 
@@ -57,15 +60,18 @@ class Request:
 class SortServer:
     """A request loop: submit() enqueues, worker threads batch and sort.
 
-    pool_bytes: device bytes of requests in flight the server admits at once,
-    counting a batched request twice (its staging copy); a request larger
-    than the pool is rejected at submit; max_batch_bytes
+    pool_bytes: device bytes the server lets its work hold at once: the
+    requests in flight, a batched request twice (its staging copy), and with
+    count_workspace the library workspace of the workers' handles (what each
+    holds, plus what a batch may add: its ips4o_workspace_size bound beyond
+    what its worker holds); a request larger than the pool is rejected at
+    submit; max_batch_bytes
     and max_batch: limits of one batch; workers: concurrent batches, one
     handle and stream each; batching=False sorts every request on its own,
     first come first served (the one-at-a-time reference)."""
 
     def __init__(self, device=0, pool_bytes=64 << 30, workers=2, max_batch_bytes=8 << 30, max_batch=4096,
-                 batching=True, queue_limit=1 << 20):
+                 batching=True, queue_limit=1 << 20, count_workspace=True):
         import torch
         self.torch = torch
         self.device = device
@@ -76,6 +82,8 @@ class SortServer:
         self.queue = collections.deque()
         self.cond = threading.Condition()
         self.inflight = 0
+        self.count_workspace = count_workspace
+        self.resident = 0               # workspace the workers' handles hold between batches
         self.closed = False
         self.rejected = 0
         self.batches = 0
@@ -123,17 +131,25 @@ class SortServer:
             raise self._errors[0]
 
     # ------------------------------------------------------------ workers
-    def _take_batch(self):
+    def _growth(self, dtype, n, ws_have):
+        """Workspace a batch of n elements may add to a handle holding ws_have."""
+        if not self.count_workspace:
+            return 0
+        return max(0, ips4o_workspace_size(dtype, n) - ws_have)
+
+    def _take_batch(self, ws_have=0):
         """Called with the lock held: the head request plus the queue's later
         requests of its element type that fit the batch and pool limits, and
         the pool bytes the batch holds (its requests, twice over when they
-        are staged together), or None when the head must wait for memory."""
+        are staged together, plus the workspace it may add to a handle that
+        holds ws_have), or None when the head must wait for memory."""
         if not self.queue:
             return None
         head = self.queue[0]
-        if self.inflight > 0 and self.inflight + head.nbytes > self.pool_bytes:
+        busy = self.inflight + self.resident
+        if self.inflight > 0 and busy + head.nbytes + self._growth(head.dtype, head.n, ws_have) > self.pool_bytes:
             return None
-        batch, total = [self.queue.popleft()], head.nbytes
+        batch, total, elems = [self.queue.popleft()], head.nbytes, head.n
         keep = collections.deque()
         while self.queue and len(batch) < self.max_batch:
             r = self.queue[0]
@@ -141,12 +157,13 @@ class SortServer:
                 keep.append(self.queue.popleft())
                 continue
             t2 = total + r.nbytes
-            if t2 > self.max_batch_bytes or self.inflight + 2 * t2 > self.pool_bytes:
+            if t2 > self.max_batch_bytes or busy + 2 * t2 + self._growth(head.dtype, elems + r.n, ws_have) > \
+                    self.pool_bytes:
                 break
             batch.append(self.queue.popleft())
-            total = t2
+            total, elems = t2, elems + r.n
         self.queue.extendleft(reversed(keep))
-        held = 2 * total if len(batch) > 1 else total
+        held = (2 * total if len(batch) > 1 else total) + self._growth(head.dtype, elems, ws_have)
         self.inflight += held
         return batch, held
 
@@ -163,11 +180,12 @@ class SortServer:
 
     def _serve(self, h, stream):
         torch = self.torch
+        ws_have = 0                     # workspace this worker's handle holds
         while True:
             with self.cond:
                 got = None
                 while got is None:
-                    got = self._take_batch()
+                    got = self._take_batch(ws_have)
                     if got is None:
                         if self.closed and not self.queue:
                             return
@@ -185,11 +203,14 @@ class SortServer:
                 self._errors.append(e)
                 for r in batch:
                     r.error = str(e)
+            ws_now = ips4o_workspace_bytes(h)
             with self.cond:
                 self.inflight -= held
+                self.resident += ws_now - ws_have
                 self.batches += 1
                 self.completed.extend(batch)
                 self.cond.notify_all()
+            ws_have = ws_now
             for r in batch:
                 r._done.set()
 

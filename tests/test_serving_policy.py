@@ -17,6 +17,7 @@ def fake(n, dtype="u64"):
 
 
 def server(**kw):
+    kw.setdefault("count_workspace", False)
     return SortServer(workers=0, **kw)
 
 
@@ -71,3 +72,32 @@ def test_submit_refuses_tensors_it_cannot_serve():
     with pytest.raises(ValueError):
         s.submit(torch.zeros(8, dtype=torch.int64), "quartet")
     assert not s.queue and s.rejected == 0
+
+
+def test_admission_counts_workspace():
+    """With workspace counting a batch also holds what the library may add to
+    its worker's handle (ips4o_workspace_size beyond what the handle holds),
+    and the workspace handles keep between batches counts against the pool."""
+    from paper_1705_02257_amd import ips4o_workspace_size
+    n = 1 << 20
+    bound = ips4o_workspace_size("u64", n)
+    s = server(count_workspace=True, pool_bytes=1 << 40)
+    s.queue.append(fake(n))
+    batch, held = s._take_batch()
+    assert held == n * 8 + bound
+    s.inflight = 0
+    s.queue.append(fake(n))
+    batch, held = s._take_batch(ws_have=bound)      # the handle already holds enough
+    assert held == n * 8
+    # bytes fit the pool, bytes plus workspace do not: wait while others run
+    s2 = server(count_workspace=True, pool_bytes=n * 8 + bound - 1)
+    s2.inflight = 1
+    s2.queue.append(fake(n))
+    assert s2._take_batch() is None
+    s2.inflight, s2.resident = 0, 0
+    assert s2._take_batch() is not None             # alone it goes anyway
+    s3 = server(count_workspace=True, pool_bytes=4 * n * 8 + 2 * bound)
+    s3.resident = 4 * n * 8 + 2 * bound - 10        # workers hold nearly all of it
+    s3.inflight = 1
+    s3.queue.append(fake(1000))
+    assert s3._take_batch() is None

@@ -222,8 +222,11 @@ int ips4o_distribute_dev(ips4o_handle *h, void *d_data, uint64_t n, int dtype, c
                          uint32_t num_splitters, int equality_buckets, uint64_t *d_bounds_out,
                          uint32_t *d_num_buckets_out, const ips4o_params *params, void *hip_stream);
 
-/* Bucket index of every element for caller-given splitters (the branchless
- * tree classification of Section 3 with the equality test of Section 4).
+/* Bucket index of every element for caller-given splitters: #{s_i <= e}
+ * (Section 3), with the equality test of Section 4, computed by the same
+ * code the distribution step classifies with (a table over the splitters'
+ * leading words narrows each key to a few splitters, a branch-free binary
+ * search finishes; the result is the implicit search tree's).
  * Splitter rules as for ips4o_distribute.  d_bucket_out: device pointer to n
  * uint32 values.  d_data is not modified. */
 int ips4o_classify(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,

@@ -300,6 +300,17 @@ bool scale_block(Resolved* R, uint64_t m) {
     return true;
 }
 
+// IPS4O_CLASSIFY_TREE=1: classification by the implicit search tree
+// (Section 3) instead of the lookup table, for 8-byte keys (an A/B switch).
+bool tree_cls_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = std::getenv("IPS4O_CLASSIFY_TREE");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
+}
+
 bool log_enabled() {
     static int on = -1;
     if (on < 0) {
@@ -668,6 +679,7 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, void* bufs, c
     // (level 2 of 2^30 keys 7.7 -> 7.0 ms); on the first level (k = 256,
     // runs of 32) they gain nothing and slow presorted inputs down
     c.vtile = level >= 1 ? 1u : 0u;
+    c.tree_cls = tree_cls_on() ? 1u : 0u;
 }
 
 // Kernel shapes per element type.

@@ -116,6 +116,8 @@ struct Ctx {
     uint32_t total_slots;
     uint32_t skip_inplace;
     uint32_t vtile;             // classification: virtual tiles of 2 tiles (8-byte keys)
+    uint32_t tree_cls;          // classification by the search-tree descent instead of the table
+                                // (8-byte keys; for timing the two against each other)
 };
 
 // The overflow block of task t (Section 4.2: the partial last block of a
@@ -437,6 +439,7 @@ struct LutParams {
     uint64_t w_lo;      // leading word of the smallest splitter
     uint32_t sh;        // cell = (w - w_lo) >> sh, clamped to [0, LUT_N)
     uint32_t steps;     // binary-search steps
+    uint32_t tree;      // the table area holds the level-order search tree instead
 };
 
 // Builds lut[] from the sorted splitters spl[0..nuniq) in LDS; every thread
@@ -630,7 +633,11 @@ __device__ inline void classify_rank(ClassifyLds<DT, NT, EPT>& L, const typename
     typename TR::Key kk[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) kk[e] = TR::key(x[e]);
-    classify_lut_batch<typename TR::Key, EPT>(kk, bk, L.spl, L.lut, L.lp, st.nuniq, st.eq);
+    if (sizeof(typename TR::Key) == 8 && L.lp.tree)
+        classify_batch<typename TR::Key, EPT>(kk, bk, reinterpret_cast<const typename TR::Key*>(L.lut), L.spl, lkt,
+                                              st.nuniq, st.eq);
+    else
+        classify_lut_batch<typename TR::Key, EPT>(kk, bk, L.spl, L.lut, L.lp, st.nuniq, st.eq);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const uint32_t p = e * NT + threadIdx.x;
@@ -687,8 +694,16 @@ __global__ __launch_bounds__(NT) void k_classify(Ctx<DT> c) {
     const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (uint32_t i = threadIdx.x; i < st.nuniq; i += NT) L.spl[i] = c.spl[td.tree_begin + i];
     __syncthreads();
-    {
-        const LutParams P = build_lut<typename TR::Key, NT>(L.spl, st.nuniq, L.lut, L.holes);
+    if (sizeof(typename TR::Key) == 8 && c.tree_cls) {
+        // the search tree a_1 .. a_{kt-1} (level order) in the table's place
+        typename TR::Key* t = reinterpret_cast<typename TR::Key*>(L.lut);
+        static_assert(sizeof(L.lut) >= KT_MAX * 8, "tree fits the table area");
+        for (uint32_t i = 1 + threadIdx.x; i < st.kt; i += NT) t[i] = c.tree[td.tree_begin + i];
+        if (threadIdx.x == 0) L.lp = LutParams{0, 0, 0, 1u};
+        __syncthreads();
+    } else {
+        LutParams P = build_lut<typename TR::Key, NT>(L.spl, st.nuniq, L.lut, L.holes);
+        P.tree = 0;
         if (threadIdx.x == 0) L.lp = P;
     }
 
@@ -2331,15 +2346,27 @@ __global__ __launch_bounds__(NT) void k_check_permute(Ctx<DT> c, uint32_t task0)
 }
 
 // --------------------------------------------------- bucket ids (classify)
+// The bucket of every element by the classification k_classify performs:
+// the lookup table over the splitters' leading words, then the binary search
+// and the equality rule (classify_lut_batch), one element per lane.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_bucket_ids(Ctx<DT> c, uint64_t n, uint32_t* out) {
     using TR = Traits<DT>;
-    __shared__ TreeLds<DT> tr;
+    using Key = typename TR::Key;
+    __shared__ Key spl[KT_MAX];
+    __shared__ uint32_t lut[LUT_N];
+    __shared__ uint32_t red[NT / 64 + 1];
     const TaskS st = c.ts[0];
-    load_tree<DT>(c, c.tasks[0], st.kt, st.nuniq, tr);
-    const uint32_t lkt = ilog2(st.kt);
-    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * NT)
-        out[i] = classify_key(TR::key(c.data[i]), tr.tree, tr.spl, lkt, st.nuniq, st.eq);
+    const TaskD td = c.tasks[0];
+    for (uint32_t i = threadIdx.x; i < st.nuniq; i += NT) spl[i] = c.spl[td.tree_begin + i];
+    __syncthreads();
+    const LutParams P = build_lut<Key, NT>(spl, st.nuniq, lut, red);
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * NT) {
+        const Key k[1] = {TR::key(c.data[i])};
+        uint32_t bk[1];
+        classify_lut_batch<Key, 1>(k, bk, spl, lut, P, st.nuniq, st.eq);
+        out[i] = bk[0];
+    }
 }
 
 }  // namespace ips4o

@@ -30,10 +30,12 @@
  * enqueued on that stream, after whatever the caller enqueued before.  The
  * recursion is planned on the host: a level's bucket bounds are copied back
  * as soon as they exist and the next level is enqueued while the current
- * one still runs.  Which calls return after enqueue: ips4o_sort_small only.
- * The others (ips4o_sort, ips4o_sort_segmented[_dev], ips4o_distribute[_dev],
- * ips4o_classify, ips4o_select_splitters) wait for their work on the stream
- * before they return, so that device faults are reported by the call itself.  A handle serves one call at a time (it owns
+ * one still runs.  Which calls return after enqueue: ips4o_sort_small and
+ * ips4o_sort_segmented_small.  The others (ips4o_sort,
+ * ips4o_sort_segmented[_dev], ips4o_distribute[_dev], ips4o_classify,
+ * ips4o_select_splitters) wait for their work on the stream before they
+ * return, so that device faults are reported by the call itself.  A handle
+ * serves one call at a time (it owns
  * the workspace and pinned staging buffers); use one handle per host thread.
  *
  * Errors: every call validates its arguments before touching the device and
@@ -166,6 +168,22 @@ int ips4o_sort_small(ips4o_handle *h, void *d_data, uint64_t n, int dtype, void 
 /* Largest n ips4o_sort_small accepts for `dtype` (0 for an unknown dtype). */
 uint64_t ips4o_small_max(int dtype);
 
+/* Segmented sort of many small segments planned on the device, so that it
+ * can be captured in a HIP graph and replayed (the recursion of Section 4
+ * reduced to its base case: every segment is one bin).  Segment i is
+ * d_data[d_offsets[i] .. d_offsets[i+1]) (d_offsets: device, 8-byte aligned,
+ * num_segments + 1 offsets), each at most ips4o_small_max(dtype) elements.
+ * Kernels on hip_stream turn the table into bins and sort them; the call
+ * returns after enqueue, with no host round trip.  A segment above the
+ * capacity, or a decreasing pair of offsets, is left as it is and the next
+ * ips4o_sync(h, hip_stream) returns IPS4O_ERR_DEVICE_FAULT with fault bit 128
+ * (ips4o_last_stats).  The first call for a segment count allocates the bin
+ * lists (and, for records, the scratch) on the handle: make it outside a
+ * capture; calls for as many segments or fewer then allocate nothing.  One
+ * handle serves one call at a time. */
+int ips4o_sort_segmented_small(ips4o_handle *h, void *d_data, int dtype, const uint64_t *d_offsets,
+                               uint32_t num_segments, void *hip_stream);
+
 /* Sort each of num_segments independent segments of one array in place:
  * segment i is d_data[h_offsets[i] .. h_offsets[i+1]).  The recursion of
  * Section 4 already treats the buckets of a level as independent
@@ -282,7 +300,8 @@ const char *ips4o_status_string(int status);
  *                  pointer left its bucket, 8 empty-block fix counts
  *                  disagreed; with IPS4O_FLAG_CHECK also 16 a full block
  *                  mixed buckets, 32 recounted buckets differed, 64 a placed
- *                  block held another bucket
+ *                  block held another bucket; 128 ips4o_sort_segmented_small got a
+ *                  segment above the capacity or decreasing offsets
  *   block_moves    blocks written by the permutations (all levels)
  *   block_skips    blocks found already in place and left there
  *   elements_base  elements sorted by the base case

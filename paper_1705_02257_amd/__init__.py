@@ -32,6 +32,7 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort",
            "ips4o_sort_small", "ips4o_small_max", "ips4o_sort_segmented_dev", "ips4o_distribute_dev",
+           "ips4o_sort_segmented_small",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
            "ips4o_last_pass_stats",
@@ -86,6 +87,7 @@ def _load():
     L.ips4o_sort.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp]
     L.ips4o_sort_small.argtypes = [vp, vp, u64, i32, vp]
     L.ips4o_sort_segmented_dev.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
+    L.ips4o_sort_segmented_small.argtypes = [vp, vp, i32, vp, u32, vp]
     L.ips4o_distribute_dev.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp, ctypes.POINTER(Params), vp]
     L.ips4o_small_max.argtypes = [i32]
     L.ips4o_small_max.restype = u64
@@ -105,7 +107,7 @@ def _load():
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
     for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort_small",
-                 "ips4o_sort_segmented_dev", "ips4o_distribute_dev", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
+                 "ips4o_sort_segmented_dev", "ips4o_distribute_dev", "ips4o_sort_segmented_small", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
                  "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
@@ -265,6 +267,15 @@ def ips4o_sort_segmented_dev(h, data, d_offsets, num_segments, dtype, params=Non
     _check(_L().ips4o_sort_segmented_dev(h, _addr(data), _dtype(dtype),
                                          _addr(d_offsets, 8 * (num_segments + 1), "offsets"), num_segments,
                                          _params(params), _stream(stream)), "ips4o_sort_segmented_dev", h)
+
+
+def ips4o_sort_segmented_small(h, data, d_offsets, num_segments, dtype, stream=None) -> None:
+    """Segments of at most ips4o_small_max(dtype) elements, planned on the
+    device from a device offset table; returns after enqueue (capturable in a
+    HIP graph once a first call has sized the handle's bin lists)."""
+    _check(_L().ips4o_sort_segmented_small(h, _addr(data), _dtype(dtype),
+                                           _addr(d_offsets, 8 * (num_segments + 1), "offsets"), num_segments,
+                                           _stream(stream)), "ips4o_sort_segmented_small", h)
 
 
 def ips4o_distribute_dev(h, data, n, dtype, d_splitters, num_splitters, equality_buckets: bool, d_bounds,

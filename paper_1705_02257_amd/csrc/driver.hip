@@ -922,7 +922,8 @@ constexpr size_t kBaseChunk = size_t(1) << 20;   // base-case bins per round of 
 
 template <int DT, int NT>
 int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t grid,
-                    typename Traits<DT>::Elem* scr, SegD* fail, uint32_t* nfail, hipStream_t st) {
+                    typename Traits<DT>::Elem* scr, SegD* fail, uint32_t* nfail, hipStream_t st,
+                    const uint32_t* dev_nseg = nullptr) {
     constexpr int BVT = Shape<DT>::BVT;
     using LB = BaseLds<DT, NT, BVT>;
     const size_t lds_count = LB::bytes(), lds_merge = LB::xchg_at + NT * sizeof(uint32_t);
@@ -931,7 +932,7 @@ int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t 
     HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, NT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_merge));
     hipLaunchKernelGGL((k_basecase_count<DT, NT, BVT>), dim3(grid), dim3(NT), lds_count, st, c, segs, (uint32_t)nseg,
-                       scr, fail, nfail);
+                       scr, fail, nfail, dev_nseg);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_basecase<DT, NT, BVT>), dim3(grid), dim3(NT), lds_merge, st, c, (const SegD*)fail, 0u, scr,
                        (const uint32_t*)nfail);
@@ -1002,7 +1003,7 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
         if (ntiny) {
             const uint32_t g = (uint32_t)std::min<size_t>((ntiny + 3) / 4, 4 * kBaseGrid);
             hipLaunchKernelGGL((k_basecase_tiny<DT, kTinyBin / 64>), dim3(g), dim3(256), 0, st, c,
-                               (const SegD*)(d_segs + nsmall + nlarge), (uint32_t)ntiny);
+                               (const SegD*)(d_segs + nsmall + nlarge), (uint32_t)ntiny, (const uint32_t*)nullptr);
             HIP_TRY(hipGetLastError());
         }
     }
@@ -1562,7 +1563,7 @@ int run_sort_small(ips4o_handle* h, void* d_data, uint64_t n, hipStream_t st) {
     if (plain && n <= kTinyBin) {
         if constexpr (plain) {
             hipLaunchKernelGGL((k_basecase_tiny<DT, kTinyBin / 64>), dim3(1), dim3(256), 0, st, c,
-                               (const SegD*)bins, 1u);
+                               (const SegD*)bins, 1u, (const uint32_t*)nullptr);
             HIP_TRY(hipGetLastError());
         }
         return IPS4O_OK;
@@ -1572,6 +1573,57 @@ int run_sort_small(ips4o_handle* h, void* d_data, uint64_t n, hipStream_t st) {
 }
 
 }  // namespace
+
+// Segmented sort of segments within the base-case capacity, planned on the
+// device (bins from the caller's device offsets, launches that read their
+// bin counts from device memory): no host round trip, so the call can be
+// captured in a HIP graph.  The first call for a segment count allocates the
+// bin lists; later calls for as many segments or fewer allocate nothing.
+template <int DT>
+int run_sort_small_segments(ips4o_handle* h, void* d_data, const uint64_t* d_offs, uint32_t nseg, hipStream_t st) {
+    using TR = Traits<DT>;
+    using Elem = typename TR::Elem;
+    constexpr int BNT = Shape<DT>::BNT;
+    constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
+    const uint32_t half = small_bin_cap<DT>();
+    int rc = h->misc.ensure(kStatsOffset + kStatLevels * kStatsBytes);
+    if (rc) return rc;
+    // lists of the three classes, then the hand-back lists of the two
+    // counting-sort classes, then eight counters
+    const size_t list_bytes = 5 * (size_t)nseg * sizeof(SegD) + 64;
+    rc = h->segs.ensure(list_bytes);
+    if (rc) return rc;
+    Elem* scr = nullptr;
+    if (!plain) {
+        rc = h->rscratch.ensure(std::max((size_t)2 * kBaseGrid * half, (size_t)kBaseGrid * TR::kBaseCap) * sizeof(Elem));
+        if (rc) return rc;
+        scr = (Elem*)h->rscratch.p;
+    }
+    SegD* lists = (SegD*)h->segs.p;
+    uint32_t* cnt = (uint32_t*)((char*)h->segs.p + 5 * (size_t)nseg * sizeof(SegD));
+    uint32_t* err = (uint32_t*)h->misc.p;
+    hipLaunchKernelGGL((k_small_segments_setup<DT>), dim3(1), dim3(256), 0, st, cnt, err);
+    HIP_TRY(hipGetLastError());
+    const uint32_t gb = std::max<uint32_t>(1, std::min<uint32_t>((nseg + 255) / 256, 4096));
+    hipLaunchKernelGGL((k_small_segments_bins<DT>), dim3(gb), dim3(256), 0, st, d_offs, nseg, half,
+                       (uint32_t)TR::kBaseCap, plain ? kTinyBin : 0u, lists, cnt, err);
+    HIP_TRY(hipGetLastError());
+    Ctx<DT> c{};
+    c.data = (Elem*)d_data;
+    SegD* fail = lists + 3 * (size_t)nseg;
+    const uint32_t g_small = std::min<uint32_t>(nseg, 2 * kBaseGrid), g_large = std::min<uint32_t>(nseg, kBaseGrid);
+    rc = launch_basecase<DT, BNT / 2>(h, c, lists, 0, g_small, scr, fail, cnt + 3, st, cnt + 0);
+    if (rc) return rc;
+    rc = launch_basecase<DT, BNT>(h, c, lists + nseg, 0, g_large, scr, fail + nseg, cnt + 4, st, cnt + 1);
+    if (rc) return rc;
+    if constexpr (plain) {
+        const uint32_t g = std::min<uint32_t>((nseg + 3) / 4, 4 * kBaseGrid);
+        hipLaunchKernelGGL((k_basecase_tiny<DT, kTinyBin / 64>), dim3(g), dim3(256), 0, st, c,
+                           (const SegD*)(lists + 2 * (size_t)nseg), 0u, (const uint32_t*)(cnt + 2));
+        HIP_TRY(hipGetLastError());
+    }
+    return IPS4O_OK;
+}
 
 #define DISPATCH(dt, CALL)                                   \
     switch (dt) {                                            \
@@ -1673,6 +1725,19 @@ int ips4o_sort_small(ips4o_handle* h, void* d_data, uint64_t n, int dtype, void*
     if (rc) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     DISPATCH(dtype, run_sort_small<D>(h, d_data, n, st));
+}
+
+int ips4o_sort_segmented_small(ips4o_handle* h, void* d_data, int dtype, const uint64_t* d_offsets,
+                               uint32_t num_segments, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    if (elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    if (num_segments == 0) return IPS4O_OK;
+    if (!d_offsets || ((uintptr_t)d_offsets & 7)) return IPS4O_ERR_INVALID_ARG;
+    if (!d_data || ((uintptr_t)d_data % elem_align(dtype))) return IPS4O_ERR_INVALID_ARG;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_sort_small_segments<D>(h, d_data, d_offsets, num_segments, st));
 }
 
 uint64_t ips4o_small_max(int dtype) {

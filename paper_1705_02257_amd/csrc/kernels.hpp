@@ -135,7 +135,8 @@ enum ErrCode : uint32_t {
     // phase invariant checks (debug flag)
     ERR_CHECK_BLOCK = 16,   // a full block after classification mixes buckets
     ERR_CHECK_COUNT = 32,   // recounted buckets differ from the stored counts
-    ERR_CHECK_PLACED = 64   // after the permutation a block in [d_i, w_i) is not of bucket i
+    ERR_CHECK_PLACED = 64,  // after the permutation a block in [d_i, w_i) is not of bucket i
+    ERR_SEGMENT = 128       // a small-segment sort got a segment above the capacity, or decreasing offsets
 };
 
 __device__ inline void raise_err(uint32_t* err, uint32_t code) {
@@ -1860,7 +1861,7 @@ struct BaseLds {
 template <int DT, int NT, int VT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
                                                        typename Traits<DT>::Elem* scratch, SegD* fail,
-                                                       uint32_t* nfail) {
+                                                       uint32_t* nfail, const uint32_t* dev_nseg) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     using BI = BaseItem<DT>;
@@ -1899,6 +1900,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             sg = segs[s2];
         }
     };
+    if (dev_nseg) nseg = *dev_nseg;             // the count written by an earlier kernel
     if (blockIdx.x < nseg) fetch(blockIdx.x);
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
         const uint32_t len = sg.len;
@@ -2111,8 +2113,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // lanes through shuffles (each lane keeps the minimum or the maximum), then
 // written back.  No LDS and no barrier, so many bins run per CU at once.
 template <int DT, int R>
-__global__ __launch_bounds__(256) void k_basecase_tiny(Ctx<DT> c, const SegD* segs, uint32_t nseg) {
+__global__ __launch_bounds__(256) void k_basecase_tiny(Ctx<DT> c, const SegD* segs, uint32_t nseg,
+                                                       const uint32_t* dev_nseg) {
     static_assert(DT == DT_U64 || DT == DT_F64, "plain keys only");
+    if (dev_nseg) nseg = *dev_nseg;
     using TR = Traits<DT>;
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
@@ -2273,6 +2277,42 @@ __global__ __launch_bounds__(NT) void k_basecase(Ctx<DT> c, const SegD* segs, ui
             else seg[i] = scr[items[pidx(i)].i];
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------ segmented sort of small segments
+// Bins straight from a device offset table (segment i = [offs[i], offs[i+1]),
+// each within the base-case capacity): every segment of 2 or more elements
+// goes to the list of its size class (0: at most `half`, the small counting
+// sort; 1: larger, the large one; 2: at most `tiny`, one wave), in any order;
+// cnt[0..3) receive the list lengths (cleared beforehand by
+// k_small_segments_setup).  A decreasing pair of offsets or a segment above
+// `cap` raises ERR_SEGMENT and that segment is left as it is.
+template <int DT>
+__global__ __launch_bounds__(256) void k_small_segments_setup(uint32_t* cnt, uint32_t* err) {
+    if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) err[0] = 0;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_small_segments_bins(const uint64_t* offs, uint32_t nseg, uint32_t half,
+                                                             uint32_t cap, uint32_t tiny, SegD* lists, uint32_t* cnt,
+                                                             uint32_t* err) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nseg; i += gridDim.x * 256) {
+        const uint64_t a = offs[i], e = offs[i + 1];
+        if (e < a || e - a > cap) {
+            raise_err_at(err, ERR_SEGMENT, i, (uint32_t)(e - a), cap);
+            continue;
+        }
+        const uint32_t len = (uint32_t)(e - a);
+        if (len <= 1) continue;
+        const uint32_t cls = len <= tiny ? 2u : (len <= half ? 0u : 1u);
+        const uint32_t at = atomicAdd(&cnt[cls], 1u);
+        SegD sd;
+        sd.off = a;
+        sd.len = len;
+        sd.pad = 0;
+        lists[(uint64_t)cls * nseg + at] = sd;
     }
 }
 

@@ -136,3 +136,78 @@ def test_segmented_device_offsets(env, dtype):
     ips.ips4o_sort_segmented_dev(h, d, d_offs, len(sizes), dtype, None, stream)
     torch.cuda.synchronize()
     assert_segments_like_oracle(from_dev(d, inp), inp, offs, dtype)
+
+
+def _small_layout(dtype, nseg, seed):
+    cap = BASE_CAP[dtype]
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(2.0 ** rng.uniform(0, np.log2(cap), nseg)).astype(np.int64)
+    sizes[:6] = [0, 1, 2, cap // 2, cap // 2 + 1, cap]       # every size class and its edges
+    rng.shuffle(sizes)
+    return _layout(list(sizes), lead=3, trail=4)
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "bytes100"])
+def test_segmented_small_device_planned(env, dtype):
+    """ips4o_sort_segmented_small: bins made on the device from the device
+    offsets, every segment sorted on its own like the oracle's."""
+    torch, ips, h = env
+    offs, n = _small_layout(dtype, 3000 if dtype in ("u64", "f64") else 600, 5)
+    inp = workloads.generate("twodup", dtype, n, workloads.seed_for(3, "twodup", dtype) + 2)
+    d = to_dev(torch, inp)
+    d_offs = torch.from_numpy(offs.view(np.int64).copy()).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    print(f"[gpu] segmented small {dtype} n={n} segments={len(offs) - 1}", flush=True)
+    ips.ips4o_sort_segmented_small(h, d, d_offs, len(offs) - 1, dtype, stream)
+    ips.ips4o_sync(h, stream)
+    assert_segments_like_oracle(from_dev(d, inp), inp, offs, dtype)
+
+
+def test_segmented_small_graph_replays(env):
+    """The small-segment sort captured once in a HIP graph (torch.cuda.CUDAGraph)
+    and replayed several times, the input restored and the result checked
+    against the oracle between replays (eager work in between)."""
+    torch, ips, h = env
+    offs, n = _small_layout("u64", 5000, 9)
+    inp = workloads.generate("uniform", "u64", n, 31)
+    pristine = to_dev(torch, inp)
+    d = pristine.clone()
+    d_offs = torch.from_numpy(offs.view(np.int64).copy()).to("cuda:0")
+    want = oracle.sort_segmented(inp, offs, "u64")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ips.ips4o_sort_segmented_small(h, d, d_offs, len(offs) - 1, "u64", s)   # sizes the bin lists
+    s.synchronize()
+    d.copy_(pristine)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    print(f"[gpu] capture small-segment sort, {len(offs) - 1} segments", flush=True)
+    with torch.cuda.graph(g, stream=s):
+        ips.ips4o_sort_segmented_small(h, d, d_offs, len(offs) - 1, "u64", s)
+    for rep in range(3):
+        d.copy_(pristine)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = d.cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, want.view(np.uint64)), f"replay {rep}"
+    ips.ips4o_sync(h, None)
+
+
+def test_segmented_small_oversize_reported(env):
+    torch, ips, h = env
+    cap = BASE_CAP["u64"]
+    offs = np.array([0, 100, 100 + cap + 1, 200 + cap + 1], dtype=np.uint64)
+    inp = workloads.generate("uniform", "u64", int(offs[-1]), 3)
+    d = to_dev(torch, inp)
+    d_offs = torch.from_numpy(offs.view(np.int64).copy()).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    ips.ips4o_sort_segmented_small(h, d, d_offs, 3, "u64", stream)
+    with pytest.raises(ips.Ips4oError) as e:
+        ips.ips4o_sync(h, stream)
+    assert e.value.status == -5 and ips.ips4o_last_stats(h)["fault_bits"] & 128
+    out = from_dev(d, inp).view(np.uint64)
+    src = inp.view(np.uint64)
+    assert np.array_equal(out[:100], np.sort(src[:100]))                     # the others are sorted
+    assert np.array_equal(out[100 + cap + 1:], np.sort(src[100 + cap + 1:]))
+    assert np.array_equal(out[100:100 + cap + 1], src[100:100 + cap + 1])    # the oversized one is untouched

@@ -121,6 +121,14 @@ int ips4o_create(int hip_device, ips4o_handle **out);
 /* Release the handle and its workspace.  NULL is ignored. */
 void ips4o_destroy(ips4o_handle *h);
 
+/* Default parameters of the handle for one element type (an autotuner's
+ * choice): every later call on h for that type takes a parameter field the
+ * call leaves 0 (or passes no params) from here, before the library's own
+ * default; flags are never defaulted.  params = NULL clears them.  Errors:
+ * IPS4O_ERR_INVALID_ARG for a NULL handle, an unknown dtype or parameters
+ * ips4o_sort would refuse. */
+int ips4o_set_default_params(ips4o_handle *h, int dtype, const ips4o_params *params);
+
 /* Device bytes of workspace the handle holds after the calls so far. */
 int ips4o_workspace_bytes(const ips4o_handle *h, size_t *bytes);
 
@@ -128,9 +136,10 @@ int ips4o_workspace_bytes(const ips4o_handle *h, size_t *bytes);
  * a fresh handle holds after ips4o_sort of n elements of `dtype` with these
  * parameters, after ips4o_sort_segmented over n elements in all, or after
  * ips4o_distribute of n elements; computed on the host from n, the element
- * type and the parameters alone, before any device work (h may be NULL).
- * Theorem 2 bounds the extra space by O(k b) per thread; here a level's
- * stripe buffers stay within n/8 elements (or one stripe per subproblem,
+ * type and the parameters (with h, its default parameters and CU count;
+ * h may be NULL: 256 CUs), before any device work.  Theorem 2 bounds the
+ * extra space by O(k b) per thread; here a level's stripe buffers stay
+ * within max(n/8 elements, 2 k b per CU) (or one stripe per subproblem,
  * when that needs more), so for large n the bound is about n*s/8 plus
  * O(n/base_cap) of per-bucket state.  A handle keeps what it has allocated:
  * after several calls it holds at most the largest of their bounds.
@@ -260,8 +269,9 @@ int ips4o_classify(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,
  * level's buffers hold min(2k, 1024) buckets: should the u unique splitters
  * need more (2u + 1 > min(2k, 1024), only for k = 1024), every second pick of
  * the same sorted sample is used instead and equality buckets stay on.
- * h_splitters_out: host buffer of k - 1 elements of `dtype` (whole elements;
- * only the key fields are meaningful) receiving the u unique splitters;
+ * h_splitters_out: host buffer of k - 1 elements of `dtype` (k: the call's,
+ * else the handle's default from ips4o_set_default_params; whole elements,
+ * only the key fields meaningful) receiving the u unique splitters;
  * *num_unique_out and *equality_out (host) receive u and the flag.
  * d_data is not modified.  Requires n >= 1. */
 int ips4o_select_splitters(ips4o_handle *h, const void *d_data, uint64_t n, int dtype,

@@ -32,7 +32,7 @@ DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 #: C symbols the library exports (as declared in include/ips4o.h)
 EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort",
            "ips4o_sort_small", "ips4o_small_max", "ips4o_sort_segmented_dev", "ips4o_distribute_dev",
-           "ips4o_sort_segmented_small",
+           "ips4o_sort_segmented_small", "ips4o_set_default_params",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
            "ips4o_last_pass_stats",
@@ -88,6 +88,7 @@ def _load():
     L.ips4o_sort_small.argtypes = [vp, vp, u64, i32, vp]
     L.ips4o_sort_segmented_dev.argtypes = [vp, vp, i32, vp, u32, ctypes.POINTER(Params), vp]
     L.ips4o_sort_segmented_small.argtypes = [vp, vp, i32, vp, u32, vp]
+    L.ips4o_set_default_params.argtypes = [vp, i32, ctypes.POINTER(Params)]
     L.ips4o_distribute_dev.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp, ctypes.POINTER(Params), vp]
     L.ips4o_small_max.argtypes = [i32]
     L.ips4o_small_max.restype = u64
@@ -107,7 +108,8 @@ def _load():
     L.ips4o_last_kernel_stats.argtypes = [vp, ctypes.POINTER(KernelStat)]
     L.ips4o_last_pass_stats.argtypes = [vp, ctypes.POINTER(PassStat), u32, ctypes.POINTER(u32)]
     for name in ["ips4o_create", "ips4o_workspace_bytes", "ips4o_workspace_size", "ips4o_sort_small",
-                 "ips4o_sort_segmented_dev", "ips4o_distribute_dev", "ips4o_sort_segmented_small", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
+                 "ips4o_sort_segmented_dev", "ips4o_distribute_dev", "ips4o_sort_segmented_small",
+                 "ips4o_set_default_params", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
                  "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
@@ -269,6 +271,12 @@ def ips4o_sort_segmented_dev(h, data, d_offsets, num_segments, dtype, params=Non
                                          _params(params), _stream(stream)), "ips4o_sort_segmented_dev", h)
 
 
+def ips4o_set_default_params(h, dtype, params=None) -> None:
+    """Parameters every later call on h for `dtype` uses where it leaves a
+    field 0 (None clears them)."""
+    _check(_L().ips4o_set_default_params(h, _dtype(dtype), _params(params)), "ips4o_set_default_params")
+
+
 def ips4o_sort_segmented_small(h, data, d_offsets, num_segments, dtype, stream=None) -> None:
     """Segments of at most ips4o_small_max(dtype) elements, planned on the
     device from a device offset table; returns after enqueue (capturable in a
@@ -302,9 +310,7 @@ def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np
     """Returns (unique splitters as a host array shaped like one element row of
     `like` (or raw bytes rows), equality flag)."""
     d = _dtype(dtype)
-    k = 256
-    if params is not None:
-        k = (params.k if isinstance(params, Params) else params.get("k", 0)) or 256
+    k = 1024                # room for any k (the call's, the handle default's or the library's)
     s = ELEM_BYTES[d]
     out = np.zeros((k - 1) * s, dtype=np.uint8)
     nu = ctypes.c_uint32(0)

@@ -6,11 +6,16 @@ machine and on the input.  Tuner times candidate parameter sets with
 ips4o_sort on synthetic device-resident inputs of a size class (powers of
 two) and element type, and keeps the fastest set per (element type, size
 class) in a JSON cache.  params() looks a size up in the cache (the nearest
-tuned class of the same element type), so callers can pass the result to
-ips4o_sort or ips4o_sort_segmented.
+tuned class of the same element type); apply() installs it as the handle's
+default (ips4o_set_default_params), so that every later call on that handle
+that passes no parameters uses it.
 
-The workgroup shapes of the kernels are fixed per element type when the
-library is built; the tuner covers the parameters the C ABI exposes.
+search_space() spans the bucket count k, the block size, the number of
+classification workgroups of the first level (stripes) and the base-case
+capacity, which also picks the base-case workgroup shape: at half the
+capacity every bin goes to the 512-lane instance that runs two workgroups
+per CU, at the full capacity the larger bins go to the 1024-lane one.  Tile
+sizes are fixed per element type when the library is built.
 """
 import json
 import math
@@ -24,6 +29,21 @@ DEFAULT_CANDIDATES = [
     {"k": 256, "block_bytes": 1024},
     {"k": 256, "block_bytes": 4096},
 ]
+
+
+def search_space(dtype: str):
+    """Every combination of k in {128, 256, 512}, 1, 2 or 4 KiB blocks,
+    planner-chosen or 256 first-level stripes, and half or all of the
+    base-case capacity."""
+    from . import ips4o_small_max
+    cap = ips4o_small_max(dtype)
+    out = []
+    for k in (128, 256, 512):
+        for bb in (1024, 2048, 4096):
+            for stripes in (0, 256):
+                for bc in (cap // 2, cap):
+                    out.append({"k": k, "block_bytes": bb, "stripes": stripes, "base_cap": bc})
+    return out
 
 
 def size_class(n: int) -> int:
@@ -80,6 +100,15 @@ class Tuner:
         self.save()
         return dict(p_best)
 
+    def apply(self, h, dtype: str, n: int):
+        """Installs the tuned parameters of n's nearest size class as the
+        defaults of handle h for `dtype`; returns them (None: nothing tuned)."""
+        from . import ips4o_set_default_params
+        p = self.params(dtype, n)
+        if p is not None:
+            ips4o_set_default_params(h, dtype, p)
+        return p
+
     def save(self):
         if self.cache_path:
             tmp = self.cache_path + ".tmp"
@@ -118,3 +147,30 @@ class Tuner:
         ips4o_sort(h, work, n, dtype, None, stream)      # first call allocates the workspace
         torch.cuda.synchronize()
         return timer, done
+
+
+#: parameters tuned on an MI355X (python -m paper_1705_02257_amd.autotune), shipped with the package
+TUNED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def main(argv=None) -> int:
+    """Tune the search space for the given element types and sizes on GPU 0
+    and write the table (default: the shipped tuned.json)."""
+    import argparse
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--out", default=TUNED)
+    ap.add_argument("--dtype", nargs="+", default=["u64"])
+    ap.add_argument("--log2n", type=int, nargs="+", default=[20, 24, 27, 30])
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args(argv)
+    t = Tuner(cache_path=a.out)
+    for dt in a.dtype:
+        for lg in a.log2n:
+            best = t.tune(dt, 1 << lg, candidates=search_space(dt), reps=a.reps)
+            rec = t.table[Tuner.key(dt, 1 << lg)]
+            print(f"[tune] {dt} 2^{lg}: {best} {rec['ms']:.3f} ms", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

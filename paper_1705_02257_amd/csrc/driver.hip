@@ -146,6 +146,7 @@ struct ips4o_handle {
     int device = 0;
     int num_cus = 256;
     void* small = nullptr;    // this device's address of the file-scope array `scratch`
+    ips4o_params dflt[5]{};   // per element type: parameters for the fields a call leaves 0
     Arena work;       // per-level descriptors and bucket state (even levels)
     Arena work2;      // the same for odd levels (planned while the previous level runs)
     Arena bufs;       // stripe buffers: partial buffers and side areas, shared by all levels
@@ -285,6 +286,13 @@ int resolve(const ips4o_params* p, Resolved* r) {
     return IPS4O_OK;
 }
 
+// The budget of a level's stripe buffers never falls below what one stripe
+// per CU needs with buffers for k buckets (Theorem 2: O(k b) per thread), so
+// that mid-size sorts keep a classification workgroup per CU.
+uint64_t budget_floor(const ips4o_handle* h, const Resolved& R) {
+    return 2ull * R.k * R.b * (uint64_t)(h ? h->num_cus : 256);
+}
+
 // Blocks of one subproblem must stay below WR_MAX_BLOCKS (the permutation's
 // packed pointer word): for a subproblem of m elements the block doubles
 // until they do, up to the largest block a permutation wave holds in its
@@ -309,6 +317,23 @@ bool tree_cls_on() {
         on = (e && e[0] == '1') ? 1 : 0;
     }
     return on == 1;
+}
+
+// The caller's parameters with every zero field (flags aside) taken from the
+// handle's defaults for the element type (ips4o_set_default_params).
+const ips4o_params* merged_params(const ips4o_handle* h, int dt, const ips4o_params* p, ips4o_params* tmp) {
+    if (!h || dt < 0 || dt > 4) return p;
+    const ips4o_params& d = h->dflt[dt];
+    *tmp = p ? *p : ips4o_params{};
+    if (!tmp->k) tmp->k = d.k;
+    if (!tmp->block_bytes) tmp->block_bytes = d.block_bytes;
+    if (!tmp->base_cap) tmp->base_cap = d.base_cap;
+    if (!tmp->alpha_x100) tmp->alpha_x100 = d.alpha_x100;
+    if (!tmp->stripes) tmp->stripes = d.stripes;
+    if (!tmp->workers) tmp->workers = d.workers;
+    if (!tmp->seed) tmp->seed = d.seed;
+    if (!tmp->spin_limit) tmp->spin_limit = d.spin_limit;
+    return tmp;
 }
 
 bool log_enabled() {
@@ -515,9 +540,10 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     }
     // memory budget of the stripe buffers (Theorem 2: O(k b) per
     // workgroup): at most buf_budget elements, or what one stripe per task
-    // needs.  Over budget, the tasks with the largest buffers per stripe get
-    // fewer stripes first, then repeating-key tasks go back to k buffers
-    // (their sample then thins its equality buckets).
+    // needs.  Over budget, first the top level's tasks go back to k buffers,
+    // then the tasks with the largest buffers per stripe get fewer stripes,
+    // then repeating-key tasks go back to k buffers (their sample then thins
+    // its equality buckets).
     if (buf_budget) {
         auto total = [&]() {
             uint64_t t = 0;
@@ -529,20 +555,31 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             std::vector<size_t> idx(T);
             for (size_t i = 0; i < T; ++i) idx[i] = i;
             std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return kb[x] > kb[y]; });
-            for (size_t i : idx) {
-                if (tot <= buf_budget) break;
-                const uint64_t per = 2 * kb[i] * (uint64_t)b, over = tot - buf_budget;
-                const uint64_t cut = std::min<uint64_t>(nss[i] - nsmin[i], (over + per - 1) / per);
-                nss[i] -= cut;
-                tot -= cut * per;
-            }
-            for (size_t i : idx) {
-                if (tot <= buf_budget) break;
-                if (kb[i] > kk[i] && !kbuf_given) {
-                    tot -= nss[i] * 2 * (uint64_t)(kb[i] - kk[i]) * b;
-                    kb[i] = kk[i];
+            auto cut_kbuf = [&](bool dup) {
+                for (size_t i : idx) {
+                    if (tot <= buf_budget) break;
+                    if (kb[i] > kk[i] && !kbuf_given && (segs[i].dup != 0) == dup) {
+                        tot -= nss[i] * 2 * (uint64_t)(kb[i] - kk[i]) * b;
+                        kb[i] = kk[i];
+                    }
                 }
-            }
+            };
+            auto cut_stripes = [&]() {
+                for (size_t i : idx) {
+                    if (tot <= buf_budget) break;
+                    const uint64_t per = 2 * kb[i] * (uint64_t)b, over = tot - buf_budget;
+                    const uint64_t cut = std::min<uint64_t>(nss[i] - nsmin[i], (over + per - 1) / per);
+                    nss[i] -= cut;
+                    tot -= cut * per;
+                }
+            };
+            // the top level's 2k buffers are insurance against repeated
+            // keys: they go first (2^27 u64 Uniform 4.57 -> 4.42 ms); a
+            // subproblem whose keys are known to repeat keeps them longer
+            // than its stripes (2^30 u64 EightDup 34.3 -> 32.5 ms)
+            cut_kbuf(false);
+            cut_stripes();
+            cut_kbuf(true);
         }
     }
     uint32_t slot = 0, treeb = 0, wk = 0;
@@ -1096,7 +1133,7 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     // (or one stripe per task, when that needs more)
     uint64_t buf_budget = 0;
     for (const Seg& sg : init) buf_budget += sg.m;
-    buf_budget = buf_budget / kBufBudgetDiv + 1;
+    buf_budget = std::max<uint64_t>(buf_budget / kBufBudgetDiv + 1, budget_floor(h, R));
     uint32_t level = 0;
     Level<DT> levels[2];
     std::vector<LevelMarks> marks;
@@ -1215,6 +1252,8 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
 template <int DT>
 int run_sort(ips4o_handle* h, void* d_data, uint64_t n, const ips4o_params* p, hipStream_t st) {
     Resolved R;
+    ips4o_params pm;
+    p = merged_params(h, DT, p, &pm);
     int rc = resolve<DT>(p, &R);
     if (rc) return rc;
     h->last = ips4o_stats{};
@@ -1227,6 +1266,8 @@ template <int DT>
 int run_sort_segmented(ips4o_handle* h, void* d_data, const uint64_t* offs, uint32_t nseg, const ips4o_params* p,
                        hipStream_t st) {
     Resolved R;
+    ips4o_params pm;
+    p = merged_params(h, DT, p, &pm);
     int rc = resolve<DT>(p, &R);
     if (rc) return rc;
     h->last = ips4o_stats{};
@@ -1249,6 +1290,8 @@ template <int DT>
 int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_split, uint32_t m, int eq,
                    uint64_t* h_bounds, uint32_t* nb_out, const ips4o_params* p, hipStream_t st) {
     Resolved R;
+    ips4o_params pm;
+    p = merged_params(h, DT, p, &pm);
     int rc = resolve<DT>(p, &R);
     if (rc) return rc;
     if (!scale_block<DT>(&R, n)) return IPS4O_ERR_NOT_SUPPORTED;
@@ -1266,7 +1309,8 @@ int run_distribute(ips4o_handle* h, void* d_data, uint64_t n, const void* h_spli
     if (rc) return rc;
     Level<DT> L;
     std::vector<Seg> cur{Seg{0, n}};
-    plan_level<DT>(L, cur, R, 0, true, ht.ts.kt, false, ht.ts.K, n / kBufBudgetDiv + 1);
+    plan_level<DT>(L, cur, R, 0, true, ht.ts.kt, false, ht.ts.K,
+                   std::max<uint64_t>(n / kBufBudgetDiv + 1, budget_floor(h, R)));
     rc = h->work.ensure(level_bytes<DT>(L, R.b));
     if (rc) return rc;
     rc = ensure_bufs<DT>(h, L, st);
@@ -1332,6 +1376,8 @@ int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_para
     using Key = typename Traits<DT>::Key;
     using Elem = typename Traits<DT>::Elem;
     Resolved R;
+    ips4o_params pm;
+    p = merged_params(h, DT, p, &pm);
     int rc = resolve<DT>(p, &R);
     if (rc) return rc;
     rc = reset_misc(h, st);
@@ -1384,7 +1430,8 @@ int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_para
 // all, ips4o_distribute of n elements), derived from the planning rules
 // above; it does not depend on the keys.
 //   stripe buffers (exact arena): every level plans at most
-//     max(n/kBufBudgetDiv + 1, what one stripe per task with kbuf = k needs);
+//     max(n/kBufBudgetDiv + 1, one stripe of k buckets per CU, what one
+//     stripe per task with kbuf = k needs);
 //     the top level of one array needs 2 KMAX b per stripe, at least
 //     ceil(nb / kStripeBlocksMax) stripes; a deeper task of m > cap elements
 //     has k < 4m/cap (adaptive_k), so one stripe per task needs below
@@ -1397,7 +1444,7 @@ int run_select(ips4o_handle* h, const void* d_data, uint64_t n, const ips4o_para
 //     handed to the merge sort); record scratch: one bin capacity per
 //     workgroup of the base-case grids; the error and counter words.
 template <int DT>
-size_t workspace_bound(uint64_t n, const Resolved& R) {
+size_t workspace_bound(uint64_t n, const Resolved& R, uint32_t num_cus) {
     using TR = Traits<DT>;
     const uint64_t s = sizeof(typename TR::Elem), ks = sizeof(typename TR::Key);
     const uint64_t b0 = R.b, cap = R.cap;
@@ -1414,7 +1461,7 @@ size_t workspace_bound(uint64_t n, const Resolved& R) {
     const uint64_t huge = nb / kStripeBlocksMax + 1;          // stripes forced by stripe length
     uint64_t bufs = 0, work = 0;
     if (n > cap) {
-        const uint64_t budget = n / kBufBudgetDiv + 1;
+        const uint64_t budget = std::max<uint64_t>(n / kBufBudgetDiv + 1, 2ull * R.k * b0 * (uint64_t)num_cus);
         const uint64_t root = 2 * (uint64_t)KMAX * b * std::max<uint64_t>(huge, R.stripes);
         const uint64_t deep = 8 * bd * n / cap + 1 + 2 * (uint64_t)KT_MAX * bd * huge;
         bufs = std::max(budget, std::max(root, deep));
@@ -1448,12 +1495,12 @@ int check_blocks(uint64_t n, const ips4o_params* params) {
 }
 
 template <int DT>
-int workspace_query(uint64_t n, const ips4o_params* params, size_t* bytes) {
+int workspace_query(uint64_t n, const ips4o_params* params, uint32_t num_cus, size_t* bytes) {
     Resolved R;
     int rc = resolve<DT>(params, &R);
     if (rc) return rc;
     if (!scale_block<DT>(&R, n)) return IPS4O_ERR_NOT_SUPPORTED;
-    *bytes = workspace_bound<DT>(n, R);
+    *bytes = workspace_bound<DT>(n, R, num_cus);
     return IPS4O_OK;
 }
 
@@ -1692,7 +1739,22 @@ int ips4o_workspace_size(const ips4o_handle* h, int dtype, uint64_t n, const ips
     int rc = check_params(params, dtype);
     if (rc) return rc;
     if (n >= kMaxElements) return IPS4O_ERR_NOT_SUPPORTED;
-    DISPATCH(dtype, workspace_query<D>(n, params, bytes));
+    ips4o_params pm;
+    params = merged_params(h, dtype, params, &pm);
+    DISPATCH(dtype, workspace_query<D>(n, params, h ? (uint32_t)h->num_cus : 256u, bytes));
+}
+
+int ips4o_set_default_params(ips4o_handle* h, int dtype, const ips4o_params* params) {
+    if (!h || elem_size(dtype) == 0) return IPS4O_ERR_INVALID_ARG;
+    if (!params) {
+        h->dflt[dtype] = ips4o_params{};
+        return IPS4O_OK;
+    }
+    const int rc = check_params(params, dtype);
+    if (rc) return rc;
+    h->dflt[dtype] = *params;
+    h->dflt[dtype].flags = 0;
+    return IPS4O_OK;
 }
 
 int ips4o_workspace_bytes(const ips4o_handle* h, size_t* bytes) {

@@ -26,3 +26,17 @@ def test_fastest_candidate_recorded(tmp_path):
 
 def test_size_class():
     assert size_class(1) == 1 and size_class(1 << 20) == 20 and size_class(3 << 19) == 21
+
+
+def test_search_space_spans_shapes_and_capacity():
+    from paper_1705_02257_amd.autotune import search_space
+    sp = search_space("u64")
+    assert len(sp) == 36
+    assert {p["base_cap"] for p in sp} == {8192, 16384}
+    assert {p["k"] for p in sp} == {128, 256, 512} and {p["stripes"] for p in sp} == {0, 256}
+    assert {p["base_cap"] for p in search_space("bytes100")} == {2048, 4096}
+
+
+def test_default_params_need_a_handle():
+    import paper_1705_02257_amd as ips
+    assert ips.lib.ips4o_set_default_params(None, 0, None) == -1

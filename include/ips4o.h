@@ -110,6 +110,12 @@ typedef struct {
 #define IPS4O_FLAG_TIMING  2u   /* time every kernel launch with HIP events on the call's stream */
 #define IPS4O_FLAG_CHECK   4u   /* debug: verify the phase invariants on the device after
                                    classification and after the permutation (slow) */
+#define IPS4O_FLAG_FUSE    8u   /* the base-case kernels clean the buckets of the bins they sort,
+                                   instead of a cleanup pass over every bucket of the level (Section
+                                   4, Implementation Details: a bucket is sorted as soon as its
+                                   cleanup is done).  Same results; slower on gfx950 (the cleanup of
+                                   a bin is a chain of dependent memory accesses inside one
+                                   workgroup), so it is off by default */
 
 typedef struct ips4o_handle ips4o_handle;
 

@@ -26,6 +26,7 @@ U64, F64, PAIR, QUARTET, BYTES100 = 0, 1, 2, 3, 4
 DTYPES = {"u64": U64, "f64": F64, "pair": PAIR, "quartet": QUARTET, "bytes100": BYTES100}
 ELEM_BYTES = {U64: 8, F64: 8, PAIR: 16, QUARTET: 32, BYTES100: 100}
 FLAG_NO_SKIP = 1
+FLAG_FUSE = 8            # base-case kernels clean the buckets of their bins (off by default)
 DEFAULT_K = 256          # first-level buckets when params leave k at 0
 DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 

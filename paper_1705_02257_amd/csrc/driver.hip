@@ -159,6 +159,7 @@ struct ips4o_handle {
     HostArena hdesc2;     // the same for odd levels
     hipEvent_t scanned[2] = {nullptr, nullptr};   // a level's bounds have reached the host
     HostArena hsegs;      // pinned staging of the base-case bin list
+    HostArena hfused;     // pinned staging of a level's fused-cleanup bucket flags
     HostArena hstage;     // pinned copies of caller arrays given in device memory
     ips4o_stats last{};
     ips4o_kernel_stat kstats[KK_N]{};
@@ -214,6 +215,12 @@ struct Timer {
     }
     void set_bytes(int idx, double bytes) {
         if (on && idx >= 0) recs[idx].bytes = bytes;
+    }
+    void add_bytes(int idx, double bytes) {
+        if (on && idx >= 0) recs[idx].bytes += bytes;
+    }
+    void move_to_pass(int idx, uint32_t p) {
+        if (on && idx >= 0) recs[idx].pass = p;
     }
     // after the stream has been synchronized
     void finish() {
@@ -310,6 +317,17 @@ bool scale_block(Resolved* R, uint64_t m) {
 
 // IPS4O_CLASSIFY_TREE=1: classification by the implicit search tree
 // (Section 3) instead of the lookup table, for 8-byte keys (an A/B switch).
+// IPS4O_FUSE=1: every call cleans base-case buckets inside the base case
+// (as IPS4O_FLAG_FUSE; comparison timing)
+bool fuse_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = std::getenv("IPS4O_FUSE");
+        on = (e && e[0] == '1') ? 1 : 0;
+    }
+    return on == 1;
+}
+
 bool tree_cls_on() {
     static int on = -1;
     if (on < 0) {
@@ -434,6 +452,7 @@ struct Level {
     uint32_t total_slots = 0, total_tree = 0, total_workers = 0;
     uint64_t total_buf = 0, total_cnt = 0;
     Ctx<DT> c{};
+    uint8_t* fused_flags = nullptr;  // [total_slots]: set in c.fused when the base case cleans buckets
 };
 
 // Bucket count for a subproblem of m elements: enough leaves that the
@@ -677,6 +696,7 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     add(L.total_cnt * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
+    add(L.total_slots);
     return off + 256;
 }
 
@@ -700,6 +720,8 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, void* bufs, c
     c.counts = cv.take<uint32_t>(L.total_cnt);
     c.stripe_full = cv.take<uint32_t>(S);
     c.order = cv.take<uint32_t>(S);
+    L.fused_flags = cv.take<uint8_t>(L.total_slots);
+    c.fused = nullptr;
     c.bufs = (Elem*)bufs;
     c.ntasks = (uint32_t)T;
     c.nstripes = (uint32_t)S;
@@ -819,9 +841,45 @@ int launch_level_head(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostT
     return IPS4O_OK;
 }
 
-// Second half of a level: empty-block fix, block permutation, cleanup.
+// Cleanup of a level: overhangs to the side area, then the free positions
+// of every bucket filled, except the buckets flagged in c.fused (cleaned by
+// the fused base case).
 template <int DT>
-int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, LevelMarks& mk, bool check) {
+int launch_level_cleanup(Level<DT>& L, hipStream_t st, Timer& tm, LevelMarks& mk, hipError_t* herr) {
+    Ctx<DT>& c = L.c;
+    const uint32_t T = (uint32_t)L.tasks.size();
+    // a bucket has a source (under a block) per stripe, plus the overhang
+    // and the overflow block; with many stripes the sources are split over
+    // several workgroups
+    uint32_t kmax = 0, nsmax = 1;
+    for (const TaskD& t : L.tasks) {
+        kmax = std::max(kmax, t.kbuf);
+        nsmax = std::max(nsmax, t.nstripes);
+    }
+    const uint32_t parts = std::min<uint32_t>(32, std::max<uint32_t>(1, (nsmax + 2) / 16));
+    mk.cleanup = tm.begin(KK_CLEANUP);
+    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+        hipLaunchKernelGGL((k_overhang<DT, 256>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
+        if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
+    }
+    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+        if (nsmax + 2 <= 64)
+            hipLaunchKernelGGL((k_cleanup_narrow<DT>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
+        else
+            hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(kmax * parts, nt), dim3(256), 0, st, c, parts, t0);
+        if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
+    }
+    tm.end(mk.cleanup, 0.0);
+    return IPS4O_OK;
+}
+
+// Second half of a level: empty-block fix, block permutation and (unless
+// the caller enqueues it later, with launch_level_cleanup) the cleanup.
+template <int DT>
+int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, LevelMarks& mk, bool check,
+                      bool cleanup = true) {
     Ctx<DT>& c = L.c;
     const uint32_t T = (uint32_t)L.tasks.size();
     mk.fix = tm.begin(KK_FIX);
@@ -856,31 +914,8 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
             HIP_TRY(hipGetLastError());
         }
     }
-    // cleanup: a bucket has a source (under a block) per stripe, plus the
-    // overhang and the overflow block; with many stripes the sources are
-    // split over several workgroups
-    uint32_t kmax = 0, nsmax = 1;
-    for (const TaskD& t : L.tasks) {
-        kmax = std::max(kmax, t.kbuf);
-        nsmax = std::max(nsmax, t.nstripes);
-    }
-    const uint32_t parts = std::min<uint32_t>(32, std::max<uint32_t>(1, (nsmax + 2) / 16));
-    mk.cleanup = tm.begin(KK_CLEANUP);
-    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
-        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
-        hipLaunchKernelGGL((k_overhang<DT, 256>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
-        HIP_TRY(hipGetLastError());
-    }
-    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
-        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
-        if (nsmax + 2 <= 64)
-            hipLaunchKernelGGL((k_cleanup_narrow<DT>), dim3((kmax + 3) / 4, nt), dim3(256), 0, st, c, t0);
-        else
-            hipLaunchKernelGGL((k_cleanup<DT, 256>), dim3(kmax * parts, nt), dim3(256), 0, st, c, parts, t0);
-        HIP_TRY(hipGetLastError());
-    }
-    tm.end(mk.cleanup, 0.0);
-    return IPS4O_OK;
+    if (!cleanup) return IPS4O_OK;
+    return launch_level_cleanup<DT>(L, st, tm, mk, &h->last_hip);
 }
 
 template <int DT>
@@ -957,19 +992,21 @@ constexpr uint32_t small_bin_cap() {
 constexpr size_t kFailCounts = 256;     // misc: two base-case fallback counters
 constexpr size_t kBaseChunk = size_t(1) << 20;   // base-case bins per round of launches
 
-template <int DT, int NT>
+// With `bsrc` (FUSED) the bins come from the level whose context `c` is,
+// and the counting sort cleans each bin's buckets before it reads the bin.
+template <int DT, int NT, bool FUSED = false>
 int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t nseg, uint32_t grid,
                     typename Traits<DT>::Elem* scr, SegD* fail, uint32_t* nfail, hipStream_t st,
-                    const uint32_t* dev_nseg = nullptr) {
+                    const uint32_t* dev_nseg = nullptr, const BinSrc* bsrc = nullptr) {
     constexpr int BVT = Shape<DT>::BVT;
     using LB = BaseLds<DT, NT, BVT>;
     const size_t lds_count = LB::bytes(), lds_merge = LB::xchg_at + NT * sizeof(uint32_t);
-    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase_count<DT, NT, BVT>,
+    HIP_TRY(hipFuncSetAttribute((const void*)k_basecase_count<DT, NT, BVT, FUSED>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_count));
     HIP_TRY(hipFuncSetAttribute((const void*)k_basecase<DT, NT, BVT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds_merge));
-    hipLaunchKernelGGL((k_basecase_count<DT, NT, BVT>), dim3(grid), dim3(NT), lds_count, st, c, segs, (uint32_t)nseg,
-                       scr, fail, nfail, dev_nseg);
+    hipLaunchKernelGGL((k_basecase_count<DT, NT, BVT, FUSED>), dim3(grid), dim3(NT), lds_count, st, c, segs,
+                       (uint32_t)nseg, scr, fail, nfail, dev_nseg, bsrc);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((k_basecase<DT, NT, BVT>), dim3(grid), dim3(NT), lds_merge, st, c, (const SegD*)fail, 0u, scr,
                        (const uint32_t*)nfail);
@@ -977,10 +1014,14 @@ int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t 
     return IPS4O_OK;
 }
 
-// One chunk of at most kBaseChunk bins (bins[0..count)).
+// One chunk of at most kBaseChunk bins (bins[0..count)).  With `srcs`
+// (srcs[i] the buckets of bins[i], none of them tiny) and `lc` (the context
+// of the level that made the bins) the counting sort cleans the buckets
+// first; `mark` receives the timer record of the chunk.
 template <int DT>
 int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t count, hipStream_t st,
-                       Timer& tm) {
+                       Timer& tm, const BinSrc* srcs = nullptr, const Ctx<DT>* lc = nullptr,
+                       int* mark = nullptr) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     struct {
@@ -996,19 +1037,27 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     const uint32_t half = small_bin_cap<DT>();
     // small bins first, then the large ones, then (u64/f64) the tiny ones
     // that one wave sorts in registers, staged in pinned memory
-    auto cls = [&](const SegD& sg) { return plain && sg.len <= kTinyBin ? 2 : sg.len <= half ? 0 : 1; };
+    const bool fused = srcs != nullptr;
+    auto cls = [&](const SegD& sg) { return plain && !fused && sg.len <= kTinyBin ? 2 : sg.len <= half ? 0 : 1; };
     size_t ncls[3] = {0, 0, 0};
     for (const SegD& sg : list) ++ncls[cls(sg)];
     const size_t nsmall = ncls[0], nlarge = ncls[1], ntiny = ncls[2];
-    int rc = h->hsegs.ensure(list.size() * sizeof(SegD));
+    const size_t srcb = fused ? list.size() * sizeof(BinSrc) : 0;
+    int rc = h->hsegs.ensure(list.size() * sizeof(SegD) + srcb);
     if (rc) return rc;
     {
         SegD* hs = (SegD*)h->hsegs.p;
+        BinSrc* hb = (BinSrc*)(hs + list.size());
         size_t at[3] = {0, nsmall, nsmall + nlarge};
-        for (const SegD& sg : list) hs[at[cls(sg)]++] = sg;
+        for (size_t i = 0; i < list.size(); ++i) {
+            const size_t to = at[cls(bins[i])]++;
+            hs[to] = bins[i];
+            if (fused) hb[to] = srcs[i];
+        }
     }
-    // the list, then room for the bins each size class hands back
-    rc = h->segs.ensure(2 * list.size() * sizeof(SegD));
+    // the list, then room for the bins each size class hands back, then
+    // (fused) the bins' buckets
+    rc = h->segs.ensure(2 * list.size() * sizeof(SegD) + srcb);
     if (rc) return rc;
     const uint32_t g_small = (uint32_t)std::min<size_t>(nsmall, 2 * kBaseGrid);
     const uint32_t g_large = (uint32_t)std::min<size_t>(nlarge, kBaseGrid);
@@ -1019,7 +1068,13 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
         scr = (Elem*)h->rscratch.p;
     }
     HIP_TRY(hipMemcpyAsync(h->segs.p, h->hsegs.p, list.size() * sizeof(SegD), hipMemcpyHostToDevice, st));
+    const BinSrc* d_src = nullptr;
+    if (fused) {
+        d_src = (const BinSrc*)((SegD*)h->segs.p + 2 * list.size());
+        HIP_TRY(hipMemcpyAsync((void*)d_src, (SegD*)h->hsegs.p + list.size(), srcb, hipMemcpyHostToDevice, st));
+    }
     Ctx<DT> c{};
+    if (lc) c = *lc;
     c.data = (Elem*)d_data;
     double elems = 0;
     for (const SegD& sg : list) elems += sg.len;
@@ -1028,12 +1083,18 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     uint32_t* nfail = (uint32_t*)((char*)h->misc.p + kFailCounts);
     HIP_TRY(hipMemsetAsync(nfail, 0, 2 * sizeof(uint32_t), st));     // bins handed back by this chunk
     int r = tm.begin(KK_BASE);
+    if (mark) *mark = r;
     if (nsmall) {
-        rc = launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, g_small, scr, fail, nfail, st);
+        rc = fused ? launch_basecase<DT, BNT / 2, true>(h, c, d_segs, nsmall, g_small, scr, fail, nfail, st,
+                                                         nullptr, d_src)
+                   : launch_basecase<DT, BNT / 2>(h, c, d_segs, nsmall, g_small, scr, fail, nfail, st);
         if (rc) return rc;
     }
     if (nlarge) {
-        rc = launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, g_large, scr, fail + nsmall, nfail + 1, st);
+        rc = fused ? launch_basecase<DT, BNT, true>(h, c, d_segs + nsmall, nlarge, g_large, scr, fail + nsmall,
+                                                     nfail + 1, st, nullptr, d_src + nsmall)
+                   : launch_basecase<DT, BNT>(h, c, d_segs + nsmall, nlarge, g_large, scr, fail + nsmall,
+                                              nfail + 1, st);
         if (rc) return rc;
     }
     if constexpr (plain) {
@@ -1049,8 +1110,8 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     if (log_enabled()) {
         uint32_t nf[2] = {0, 0};
         HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
-        std::fprintf(stderr, "[ips4o] base case: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted), "
-                     "%zu tiny\n", nsmall, nf[0], nlarge, nf[1], ntiny);
+        std::fprintf(stderr, "[ips4o] base case%s: %zu small bins (%u merge-sorted), %zu large (%u merge-sorted), "
+                     "%zu tiny\n", fused ? " (fused cleanup)" : "", nsmall, nf[0], nlarge, nf[1], ntiny);
     }
     return IPS4O_OK;
 }
@@ -1059,12 +1120,12 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
 // launches, so that the device bin list stays within a fixed size.
 template <int DT>
 int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const Resolved& R,
-                 hipStream_t st, Timer& tm) {
+                 hipStream_t st, Timer& tm, uint32_t pass) {
     (void)R;
     if (list.empty()) return IPS4O_OK;
     uint64_t elems = 0;
     for (const SegD& sg : list) elems += sg.len;
-    tm.set_pass((uint32_t)tm.pass_elems.size(), elems);   // the pass after the last level
+    tm.set_pass(pass, elems);          // the pass after the last level
     for (size_t a = 0; a < list.size(); a += kBaseChunk) {
         const int rc = run_basecase_chunk<DT>(h, d_data, list.data() + a, std::min(kBaseChunk, list.size() - a),
                                               st, tm);
@@ -1137,6 +1198,14 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     uint32_t level = 0;
     Level<DT> levels[2];
     std::vector<LevelMarks> marks;
+    // base case that cleans the buckets of its bins (Section 4,
+    // Implementation Details), on request
+    constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
+    const bool fuse = (R.flags & IPS4O_FLAG_FUSE) || fuse_on();
+    std::vector<BinSrc> srcs, fs;
+    std::vector<SegD> fb;
+    uint64_t fused_elems = 0;
+    std::vector<int> fused_marks;
     std::vector<uint32_t> level_tasks, level_stripes, level_workers, level_b;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     const bool check = (R.flags & IPS4O_FLAG_CHECK) != 0;
@@ -1177,7 +1246,9 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         if (rc) return rc;
         rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
         if (rc) return rc;
-        rc = launch_level_tail<DT>(h, L, st, tm, marks.back(), check);
+        // the cleanup waits for the bounds when the base case cleans the
+        // buckets of the level's bins
+        rc = launch_level_tail<DT>(h, L, st, tm, marks.back(), check, !fuse);
         if (rc) return rc;
         level_tasks.push_back((uint32_t)L.tasks.size());
         level_stripes.push_back((uint32_t)L.stripes.size());
@@ -1199,6 +1270,8 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         const uint64_t* bounds = (const uint64_t*)(rp + 256 + T * sizeof(TaskS));
         std::vector<Seg> next;
         base.reserve(base.size() + L.total_slots);
+        const size_t base_before = base.size();
+        srcs.clear();
         const uint64_t bin_cap = std::min(R.cap, small_bin_cap<DT>());
         for (size_t t = 0; t < T; ++t) {
             const TaskD& td = L.tasks[t];
@@ -1210,19 +1283,66 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
                              ts[t].eq, td.nstripes);
             uint64_t eb = 0;
             if (K > (uint32_t)KMAX || K > td.kbuf ||
-                !split_task(td.off, td.m, cur[t].grp, K, ts[t].eq != 0, bd, R.cap, bin_cap, base, next, &eb)) {
+                !split_task(td.off, td.m, cur[t].grp, K, ts[t].eq != 0, bd, R.cap, bin_cap, base, next, &eb, &srcs,
+                            (uint32_t)t)) {
                 (void)check_device_error(h, st);
                 return IPS4O_ERR_DEVICE_FAULT;
             }
             h->last.elements_base += eb;
         }
+        // the level's bins (but the ones one wave sorts) go to the fused
+        // base case, which cleans their buckets; the cleanup kernels skip
+        // those buckets
+        fb.clear();
+        fs.clear();
+        if (fuse) {
+            size_t keep = base_before;
+            for (size_t i = base_before; i < base.size(); ++i) {
+                const SegD sg = base[i];
+                if (!plain || sg.len > kTinyBin) {
+                    fb.push_back(sg);
+                    fs.push_back(srcs[i - base_before]);
+                } else {
+                    base[keep++] = sg;
+                }
+            }
+            base.resize(keep);
+        }
+        if (!fb.empty()) {
+            rc = h->hfused.ensure(L.total_slots);
+            if (rc) return rc;
+            uint8_t* fl = (uint8_t*)h->hfused.p;
+            std::memset(fl, 0, L.total_slots);
+            for (const BinSrc& b : fs)
+                for (uint32_t j = b.j0; j <= b.j1; ++j) fl[L.tasks[b.task].slot_begin + j] = 1;
+            HIP_TRY(hipMemcpyAsync(L.fused_flags, fl, L.total_slots, hipMemcpyHostToDevice, st));
+            L.c.fused = L.fused_flags;
+        }
+        if (fuse) {
+            rc = launch_level_cleanup<DT>(L, st, tm, marks.back(), &h->last_hip);
+            if (rc) return rc;
+        }
+        if (!fb.empty()) {
+            for (const SegD& sg : fb) fused_elems += sg.len;
+            for (size_t a = 0; a < fb.size(); a += kBaseChunk) {
+                int mk = -1;
+                rc = run_basecase_chunk<DT>(h, d_data, fb.data() + a, std::min(kBaseChunk, fb.size() - a), st, tm,
+                                            fs.data() + a, &L.c, &mk);
+                if (rc) return rc;
+                fused_marks.push_back(mk);
+            }
+        }
+        L.c.fused = nullptr;
         cur.swap(next);
         ++level;
         t_next += since(t2);
     }
     h->last.levels = level;
     const auto t3 = clk::now();
-    rc = run_basecase<DT>(h, d_data, base, R, st, tm);       // ends with a stream synchronize
+    // the base-case pass follows the last level; the fused launches count there
+    for (int mk : fused_marks) tm.move_to_pass(mk, level);
+    if (fused_elems) tm.set_pass(level, fused_elems);
+    rc = run_basecase<DT>(h, d_data, base, R, st, tm, level);       // ends with a stream synchronize
     if (rc) return rc;
     if (log_enabled())
         std::fprintf(stderr, "[ips4o] host ms: plan+enqueue %.3f, wait for bounds %.3f, next plan %.3f, "
@@ -1244,6 +1364,14 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         if (log_enabled())
             std::fprintf(stderr, "[ips4o] level %u: %u tasks, %u stripes, %u workers, moves %llu skips %llu\n", l,
                          level_tasks[l], level_stripes[l], level_workers[l], now[0], now[1]);
+    }
+    if (!fused_marks.empty()) {
+        // elements the fused base case placed while cleaning (word 4 of
+        // every level's counters)
+        unsigned long long fc = 0;
+        for (uint32_t l = 0; l < kStatLevels; ++l)
+            for (int r = 0; r < STAT_SPREAD; ++r) fc += cnt[(size_t)l * kStatsBytes / 8 + r * 8 + 4];
+        tm.add_bytes(fused_marks[0], 2.0 * sizeof(typename Traits<DT>::Elem) * (double)fc);
     }
     tm.finish();
     return rc;
@@ -1472,12 +1600,12 @@ size_t workspace_bound(uint64_t n, const Resolved& R, uint32_t num_cus) {
         const uint64_t counts = bufs / (2 * b0) + 1;
         const uint64_t lv = al(T * sizeof(TaskD)) + al(S * sizeof(StripeD)) + al(T * sizeof(TaskS)) +
                             2 * al(sumk * ks) + al((sumkb + T) * 8) + al((sumkb + T) * 4) +
-                            al(sumkb * sizeof(BucketSlot)) + al(counts * 4) + 2 * al(S * 4) + 256;
+                            al(sumkb * sizeof(BucketSlot)) + al(counts * 4) + 2 * al(S * 4) + al(sumkb) + 256;
         work = 2 * slack(lv);
     }
     const uint64_t misc = slack(kStatsOffset + (uint64_t)kStatLevels * kStatsBytes);
     const uint64_t bins = std::min<uint64_t>(n / 2 + 1, kBaseChunk);
-    const uint64_t segs = slack(2 * bins * sizeof(SegD));
+    const uint64_t segs = slack(bins * (2 * sizeof(SegD) + sizeof(BinSrc)));
     uint64_t recs = 0;
     if (DT != DT_U64 && DT != DT_F64)
         recs = slack(std::max(std::min<uint64_t>(bins, 2 * kBaseGrid) * small_bin_cap<DT>(),

@@ -116,6 +116,7 @@ struct Ctx {
     uint32_t total_slots;
     uint32_t skip_inplace;
     uint32_t vtile;             // classification: virtual tiles of 2 tiles (8-byte keys)
+    const uint8_t* fused;       // [sum kbuf] (or null): bucket cleaned by the fused base case, not by k_cleanup
     uint32_t tree_cls;          // classification by the search-tree descent instead of the table
                                 // (8-byte keys; for timing the two against each other)
 };
@@ -1615,6 +1616,7 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint3
     const TaskS st = c.ts[t];
     const uint32_t j = blockIdx.x / parts, part = blockIdx.x % parts;
     if (j >= st.K) return;
+    if (c.fused && c.fused[td.slot_begin + j]) return;     // the fused base case cleans it
     const uint32_t b = c.b;
     bool bad;
     const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
@@ -1657,16 +1659,16 @@ __global__ __launch_bounds__(NT) void k_cleanup(Ctx<DT> c, uint32_t parts, uint3
     }
 }
 
-// The same for tasks with at most 62 stripes: one wave per bucket, four
-// buckets per workgroup; grid (bucket groups, tasks from task0).
-template <int DT>
-__global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task0) {
+// Cleanup of bucket j of task t (at most 62 stripes) by one wave: lane q
+// holds source q's size and start, and every round places 64 U elements,
+// all loads of a round issued before its stores, so a round costs one
+// memory latency, not U.  Counts the elements placed in statistics word
+// `which`.
+template <int DT, int U>
+__device__ inline void cleanup_bucket_wave(const Ctx<DT>& c, uint32_t t, const TaskD& td, const TaskS& st,
+                                           uint32_t j, int which, uint32_t key) {
     using Elem = typename Traits<DT>::Elem;
-    const uint32_t t = task0 + blockIdx.y;
-    const TaskD td = c.tasks[t];
-    const TaskS st = c.ts[t];
-    const uint32_t j = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x & 63;
-    if (j >= st.K) return;
+    const uint32_t lane = threadIdx.x & 63;
     const uint32_t b = c.b;
     bool bad;
     const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
@@ -1675,7 +1677,6 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
         return;
     }
     const uint32_t ns = td.nstripes, nq = ns + 2;
-    // lane q holds source q's size and start
     uint32_t v = 0;
     uint64_t src_off = 0;                       // element offset in bufs (q <= ns)
     if (lane == 0) {
@@ -1703,13 +1704,10 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
         if (lane == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
         return;
     }
-    if (lane == 0) stat_add(c.stats, 2, nsrc, threadIdx.x / 64 + blockIdx.x + blockIdx.y);
+    if (lane == 0 && nsrc) stat_add(c.stats, which, nsrc, key);
     const FreeMap fm{g.B0, tb, nhead};
     Elem* seg = c.data + td.off;
     const Elem* ovfp = ovf_block<DT>(c, td);
-    // U elements per lane per round: all loads of a round are issued before
-    // its stores, so a round costs one memory latency, not U
-    constexpr int U = 8;
     for (uint32_t base = 0; base < nsrc; base += 64 * U) {
         uint32_t qs[U];
 #pragma unroll
@@ -1734,6 +1732,83 @@ __global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task
             const uint32_t x = base + lane + 64u * u;
             if (x < nsrc) seg[fm(x)] = r[u];
         }
+    }
+}
+
+// The same for tasks with at most 62 stripes: one wave per bucket, four
+// buckets per workgroup; grid (bucket groups, tasks from task0).
+template <int DT>
+__global__ __launch_bounds__(256) void k_cleanup_narrow(Ctx<DT> c, uint32_t task0) {
+    const uint32_t t = task0 + blockIdx.y;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t j = blockIdx.x * 4 + threadIdx.x / 64;
+    if (j >= st.K) return;
+    if (c.fused && c.fused[td.slot_begin + j]) return;     // the fused base case cleans it
+    cleanup_bucket_wave<DT, 8>(c, t, td, st, j, 2, threadIdx.x / 64 + blockIdx.x + blockIdx.y);
+}
+
+// Cleanup of the buckets j0 .. j1 of one task (a base-case bin, Section 4,
+// Implementation Details: the base case sorts a bucket right after the
+// cleanup has filled it) by a whole workgroup: the placement of k_cleanup.
+// With at most 62 stripes in the task every wave cleans buckets of its own
+// (cleanup_bucket_wave), else the workgroup takes one bucket after the
+// other.  `lds` holds STRIPES_PER_TASK_MAX + 4 + NT/64 + 1 words of scratch.
+// The caller synchronizes before it reads the bin back.  Counts the elements
+// placed in statistics word 4.
+template <int DT, int NT>
+__device__ inline void cleanup_bin(const Ctx<DT>& c, const BinSrc& bs, uint32_t* lds) {
+    using Elem = typename Traits<DT>::Elem;
+    const uint32_t t = bs.task;
+    const TaskD td = c.tasks[t];
+    const TaskS st = c.ts[t];
+    const uint32_t b = c.b, ns = td.nstripes, nq = ns + 2;
+    if (nq <= 64) {
+        constexpr int U = sizeof(Elem) >= 64 ? 1 : (int)(64 / sizeof(Elem));
+        for (uint32_t j = bs.j0 + threadIdx.x / 64; j <= bs.j1; j += NT / 64)
+            cleanup_bucket_wave<DT, U>(c, t, td, st, j, 4, blockIdx.x + j);
+        return;
+    }
+    uint32_t* pre = lds;
+    uint32_t* sh = lds + STRIPES_PER_TASK_MAX + 4;
+    Elem* seg = c.data + td.off;
+    for (uint32_t j = bs.j0; j <= bs.j1; ++j) {
+        bool bad;
+        const BucketGeom g = bucket_geom<DT>(c, t, td, st, j, &bad);
+        if (bad) {
+            if (threadIdx.x == 0) raise_err(c.err, ERR_CLEANUP_COUNT);
+            continue;
+        }
+        for (uint32_t q = threadIdx.x; q < nq; q += NT) {
+            uint32_t v;
+            if (q == 0) v = (uint32_t)g.ohn;
+            else if (q <= ns) v = c.counts[td.cnt_begin + (uint64_t)(q - 1) * td.kbuf + j] % b;
+            else v = g.ovf_case ? b : 0;
+            pre[q] = v;
+        }
+        __syncthreads();
+        const uint32_t nsrc = lds_excl_scan<NT>(pre, nq, sh);
+        pre[nq] = nsrc;
+        __syncthreads();
+        const uint64_t he = g.cs < g.B1 ? g.cs : g.B1;
+        const uint64_t tb0 = g.ce > g.cs ? g.ce : g.cs;
+        const uint64_t tb = tb0 < g.B1 ? tb0 : g.B1;
+        const uint64_t nhead = he - g.B0, nfree = nhead + (g.B1 - tb);
+        if (nfree == nsrc) {
+            if (threadIdx.x == 0 && nsrc) stat_add(c.stats, 4, nsrc, blockIdx.x + j);
+            const FreeMap fm{g.B0, tb, nhead};
+            for (uint32_t q = 0; q < nq; ++q) {
+                const uint32_t x0 = pre[q], n = pre[q + 1] - x0;
+                if (n == 0) continue;
+                const Elem* src = q == 0 ? c.bufs + c.stripes[td.stripe_begin].buf_off + ((uint64_t)td.kbuf + j) * b
+                                : q <= ns ? c.bufs + c.stripes[td.stripe_begin + q - 1].buf_off + (uint64_t)j * b
+                                          : ovf_block<DT>(c, td);
+                for (uint32_t o = threadIdx.x; o < n; o += NT) seg[fm(x0 + o)] = src[o];
+            }
+        } else if (threadIdx.x == 0) {
+            raise_err(c.err, ERR_CLEANUP_COUNT);
+        }
+        __syncthreads();        // pre is rewritten for the next bucket
     }
 }
 
@@ -1858,10 +1933,14 @@ struct BaseLds {
 // Segments whose ranking would cost more than WMAX compares per item (keys
 // crowded into a few digits), and records with one leading word, are left
 // untouched and appended to `fail` for k_basecase (merge sort).
-template <int DT, int NT, int VT>
+// FUSED: the bins are base-case bins of the level just partitioned; before a
+// bin is read the workgroup runs the cleanup of its buckets (bsrc[si]): the
+// next bin is cleaned and its keys fetched while this one is written out.
+template <int DT, int NT, int VT, bool FUSED = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_basecase_count(Ctx<DT> c, const SegD* segs, uint32_t nseg,
                                                        typename Traits<DT>::Elem* scratch, SegD* fail,
-                                                       uint32_t* nfail, const uint32_t* dev_nseg) {
+                                                       uint32_t* nfail, const uint32_t* dev_nseg,
+                                                       const BinSrc* bsrc) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     using BI = BaseItem<DT>;
@@ -1901,8 +1980,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
     };
     if (dev_nseg) nseg = *dev_nseg;             // the count written by an earlier kernel
-    if (blockIdx.x < nseg) fetch(blockIdx.x);
+    // cleanup scratch: u64/f64 clean the next bin while this one's sorted
+    // keys sit in the item array, in the counters; records clean a bin at
+    // the start of its iteration, in the item array
+    constexpr size_t kCleanWords = STRIPES_PER_TASK_MAX + 4 + NT / 64 + 1;
+    static_assert(!FUSED || (kPlain ? LB::RADIX >= kCleanWords : LB::counters_at >= 4 * kCleanWords),
+                  "cleanup scratch");
+    if (blockIdx.x < nseg) {
+        if constexpr (FUSED && kPlain) {
+            cleanup_bin<DT, NT>(c, bsrc[blockIdx.x], cnt);
+            __syncthreads();
+        }
+        fetch(blockIdx.x);
+    }
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
+        if constexpr (FUSED && !kPlain) {
+            cleanup_bin<DT, NT>(c, bsrc[si], reinterpret_cast<uint32_t*>(smem_raw));
+            __syncthreads();
+        }
         const uint32_t len = sg.len;
         Elem* seg = c.data + sg.off;
         It x[VT];
@@ -2083,7 +2178,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         }
         __syncthreads();
         const SegD cur = sg;
-        if (si + gridDim.x < nseg) fetch(si + gridDim.x);
+        if (si + gridDim.x < nseg) {
+            if constexpr (FUSED && kPlain) {
+                // the counters are free now; the items hold this bin's output
+                cleanup_bin<DT, NT>(c, bsrc[si + gridDim.x], cnt);
+                __syncthreads();
+            }
+            fetch(si + gridDim.x);
+        }
         if (sorted) {
             Elem* out = c.data + cur.off;
             if constexpr (kPlain) {

@@ -22,6 +22,13 @@ struct SegD {
     uint32_t pad;
 };
 
+// The buckets a bin spans: buckets j0 .. j1 of task `task` of the level that
+// made it (every bucket in between included: equality buckets and buckets
+// of at most one element lie inside the span too).
+struct BinSrc {
+    uint32_t task, j0, j1, pad;
+};
+
 // A subproblem: elements [off, off+m); grp is the caller's segment it lies in;
 // dup: the task it came from used equality buckets (its keys repeat, so its
 // own sample likely repeats splitters too).
@@ -46,9 +53,11 @@ struct Seg {
 // own, and two bins sorted at once must not overlap.
 // Larger buckets are appended to `next` (grp inherited, dup = eq).  Returns false when
 // the bounds are inconsistent (bounds[0] != 0, bounds[K] != m, decreasing).
+// With `srcs`, every bin made here also gets its BinSrc (task `task`),
+// appended in the order of the bins.
 inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool eq, const uint64_t* bounds,
                        uint64_t cap, uint64_t bin_cap, std::vector<SegD>& bins, std::vector<Seg>& next,
-                       uint64_t* elements_base) {
+                       uint64_t* elements_base, std::vector<BinSrc>* srcs = nullptr, uint32_t task = 0) {
     if (K == 0 || bounds[0] != 0 || bounds[K] != m) return false;
     for (uint32_t i = 0; i < K; ++i)
         if (bounds[i + 1] < bounds[i]) return false;
@@ -67,10 +76,12 @@ inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool 
             SegD& cur = bins.back();
             if (at + sz - cur.off <= bin_cap) {
                 cur.len = (uint32_t)(at + sz - cur.off);
+                if (srcs) srcs->back().j1 = i;
                 continue;
             }
         }
         bins.push_back(SegD{at, (uint32_t)sz, 0});
+        if (srcs) srcs->push_back(BinSrc{task, i, i, 0});
     }
     return true;
 }

@@ -177,12 +177,24 @@ static int random_recursions() {
                 }
                 const size_t before = bins.size();
                 uint64_t eb = 0;
-                CHECK(split_task(t.off, t.m, t.grp, K, eq, bd.data(), cap, bin_cap, bins, next, &eb),
+                std::vector<BinSrc> srcs;
+                const uint32_t task_id = (uint32_t)(rnd() % 1000);
+                CHECK(split_task(t.off, t.m, t.grp, K, eq, bd.data(), cap, bin_cap, bins, next, &eb, &srcs, task_id),
                       "trial %d: consistent bounds refused", trial);
                 eb_total += eb;
+                CHECK(srcs.size() == bins.size() - before, "trial %d: %zu bin sources for %zu bins", trial,
+                      srcs.size(), bins.size() - before);
                 for (size_t i = before; i < bins.size(); ++i) {
                     owner.push_back(Range{t.off, t.off + t.m});
                     bin_level.push_back(level);
+                    // the bin spans exactly buckets j0 .. j1, none of them recursed into
+                    const BinSrc& bs = srcs[i - before];
+                    CHECK(bs.task == task_id && bs.j0 <= bs.j1 && bs.j1 < K, "trial %d: bad bin source", trial);
+                    CHECK(bins[i].off == t.off + bd[bs.j0] && bins[i].off + bins[i].len == t.off + bd[bs.j1 + 1],
+                          "trial %d: bin and its buckets differ", trial);
+                    for (uint32_t j = bs.j0; j <= bs.j1; ++j)
+                        CHECK(bd[j + 1] - bd[j] <= cap || (eq && (j & 1)),
+                              "trial %d: a bin spans a recursed bucket", trial);
                 }
             }
             for (const Seg& s : next) CHECK(s.m > cap, "trial %d: a subproblem within the capacity", trial);

@@ -397,6 +397,33 @@ def test_phase_invariants_checked_on_device(env, dist):
         assert np.array_equal(gb, bounds)
 
 
+# ---------------------------------------- last level: fused cleanup
+@pytest.mark.parametrize("dtype,dist,n,params", [
+    ("u64", "uniform", 1 << 22, None), ("u64", "twodup", 3000017, None), ("f64", "eightdup", 1 << 21, None),
+    ("u64", "rootdup", 2000003, None), ("u64", "uniform", 1000003, {"base_cap": 1000}),
+    ("u64", "exponential", 1 << 22, {"k": 16}), ("f64", "almost", 1 << 21, {"block_bytes": 256}),
+    ("pair", "uniform", 600011, None), ("quartet", "rootdup", 400009, None), ("bytes100", "twodup", 200003, None)])
+def test_sort_fused_cleanup(env, dtype, dist, n, params):
+    """With IPS4O_FLAG_FUSE the base case cleans the buckets of the bins it
+    sorts (Section 4, Implementation Details).  The default call (a cleanup
+    pass per level) and the fused one both equal the oracle; the fused one
+    also passes the device's phase checks, and its timed base-case pass
+    counts the elements it placed while cleaning."""
+    torch, ips, h = env
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(3, dist, dtype))
+    base = dict(params or {})
+    print(f"[gpu] fused cleanup {dtype} {dist} n={n} params={params}", flush=True)
+    for flags in (0, ips.FLAG_FUSE, ips.FLAG_FUSE | 4, ips.FLAG_FUSE | ips.FLAG_TIMING):
+        out = gpu_sort(env, inp, dtype, dict(base, flags=flags))
+        assert_sorted_like_oracle(out, inp, dtype)
+    passes = ips.ips4o_last_pass_stats(h)
+    assert passes and passes[-1]["base_case"]
+    s = ips.ELEM_BYTES[ips.DTYPES[dtype]]
+    st = ips.ips4o_last_stats(h)
+    assert passes[-1]["elements"] == st["elements_base"]
+    assert passes[-1]["alg_bytes"] >= 2.0 * s * st["elements_base"]
+
+
 # ------------------------------------------------------- classification
 @pytest.mark.parametrize("dtype", ["u64", "f64", "pair", "quartet", "bytes100"])
 @pytest.mark.parametrize("eq", [False, True])

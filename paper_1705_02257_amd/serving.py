@@ -23,6 +23,7 @@ The sorting itself is the library's (the recursion of Section 4 applied to
 many independent arrays); this module only schedules.
 """
 import collections
+import os
 import threading
 import time
 
@@ -68,13 +69,25 @@ class SortServer:
     submit; max_batch_bytes
     and max_batch: limits of one batch; workers: concurrent batches, one
     handle and stream each; batching=False sorts every request on its own,
-    first come first served (the one-at-a-time reference)."""
+    first come first served (the one-at-a-time reference); params: the
+    sort parameters of a batch -- "tuned" (the autotuner's table shipped
+    with the package, looked up by element type and batch size; library
+    defaults where it has no entry), None (library defaults) or one
+    ips4o_params dict for every batch."""
 
     def __init__(self, device=0, pool_bytes=64 << 30, workers=2, max_batch_bytes=8 << 30, max_batch=4096,
-                 batching=True, queue_limit=1 << 20, count_workspace=True):
+                 batching=True, queue_limit=1 << 20, count_workspace=True, params="tuned"):
         import torch
         self.torch = torch
         self.device = device
+        self.tuner = None
+        self.fixed_params = None
+        if params == "tuned":
+            from .autotune import TUNED, Tuner
+            if os.path.exists(TUNED):
+                self.tuner = Tuner(cache_path=TUNED)
+        elif params is not None:
+            self.fixed_params = dict(params)
         self.pool_bytes = pool_bytes
         self.max_batch_bytes = max_batch_bytes
         self.max_batch = max_batch if batching else 1
@@ -131,23 +144,42 @@ class SortServer:
             raise self._errors[0]
 
     # ------------------------------------------------------------ workers
-    def _growth(self, dtype, n, ws_have):
-        """Workspace a batch of n elements may add to a handle holding ws_have."""
+    def params_for(self, dtype, n):
+        """The parameters a batch of n elements of dtype is sorted with."""
+        if self.tuner is not None:
+            return self.tuner.params(dtype, n)
+        return self.fixed_params
+
+    def config_for(self, dtype, n):
+        """Element type and parameters of a batch of n elements."""
+        p = self.params_for(dtype, n)
+        return (dtype, tuple(sorted(p.items())) if p else None)
+
+    def _growth(self, dtype, n, ws_have, last=None):
+        """Workspace a batch of n elements may add to a handle holding
+        ws_have after a batch of configuration `last` (config_for): the
+        bound beyond what the handle holds when the configuration is the
+        same, else the whole bound (the handle's buffers were sized for
+        other parameters and may not cover this batch's)."""
         if not self.count_workspace:
             return 0
-        return max(0, ips4o_workspace_size(dtype, n) - ws_have)
+        bound = ips4o_workspace_size(dtype, n, self.params_for(dtype, n))
+        if ws_have and last is not None and self.config_for(dtype, n) != last:
+            return bound
+        return max(0, bound - ws_have)
 
-    def _take_batch(self, ws_have=0):
+    def _take_batch(self, ws_have=0, last=None):
         """Called with the lock held: the head request plus the queue's later
         requests of its element type that fit the batch and pool limits, and
         the pool bytes the batch holds (its requests, twice over when they
         are staged together, plus the workspace it may add to a handle that
-        holds ws_have), or None when the head must wait for memory."""
+        holds ws_have after a batch of configuration `last`), or None when
+        the head must wait for memory."""
         if not self.queue:
             return None
         head = self.queue[0]
         busy = self.inflight + self.resident
-        if self.inflight > 0 and busy + head.nbytes + self._growth(head.dtype, head.n, ws_have) > self.pool_bytes:
+        if self.inflight > 0 and busy + head.nbytes + self._growth(head.dtype, head.n, ws_have, last) > self.pool_bytes:
             return None
         batch, total, elems = [self.queue.popleft()], head.nbytes, head.n
         keep = collections.deque()
@@ -157,13 +189,13 @@ class SortServer:
                 keep.append(self.queue.popleft())
                 continue
             t2 = total + r.nbytes
-            if t2 > self.max_batch_bytes or busy + 2 * t2 + self._growth(head.dtype, elems + r.n, ws_have) > \
+            if t2 > self.max_batch_bytes or busy + 2 * t2 + self._growth(head.dtype, elems + r.n, ws_have, last) > \
                     self.pool_bytes:
                 break
             batch.append(self.queue.popleft())
             total, elems = t2, elems + r.n
         self.queue.extendleft(reversed(keep))
-        held = (2 * total if len(batch) > 1 else total) + self._growth(head.dtype, elems, ws_have)
+        held = (2 * total if len(batch) > 1 else total) + self._growth(head.dtype, elems, ws_have, last)
         self.inflight += held
         return batch, held
 
@@ -181,11 +213,12 @@ class SortServer:
     def _serve(self, h, stream):
         torch = self.torch
         ws_have = 0                     # workspace this worker's handle holds
+        last = None                     # configuration of its last batch
         while True:
             with self.cond:
                 got = None
                 while got is None:
-                    got = self._take_batch(ws_have)
+                    got = self._take_batch(ws_have, last)
                     if got is None:
                         if self.closed and not self.queue:
                             return
@@ -211,6 +244,7 @@ class SortServer:
                 self.completed.extend(batch)
                 self.cond.notify_all()
             ws_have = ws_now
+            last = self.config_for(batch[0].dtype, sum(r.n for r in batch))
             for r in batch:
                 r._done.set()
 
@@ -222,13 +256,13 @@ class SortServer:
                 stream.wait_event(r.ready)
         if len(batch) == 1:
             r = batch[0]
-            ips4o_sort(h, r.tensor, r.n, dtype, None, stream)
+            ips4o_sort(h, r.tensor, r.n, dtype, self.params_for(dtype, r.n), stream)
             return
         sizes = [r.n for r in batch]
         offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
         flat = [r.tensor.reshape(-1) for r in batch]
         staging = torch.cat(flat)
-        ips4o_sort_segmented(h, staging, offs, dtype, None, stream)
+        ips4o_sort_segmented(h, staging, offs, dtype, self.params_for(dtype, int(offs[-1])), stream)
         words = [f.numel() for f in flat]
         at = 0
         for r, f, w in zip(batch, flat, words):

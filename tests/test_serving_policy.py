@@ -18,6 +18,7 @@ def fake(n, dtype="u64"):
 
 def server(**kw):
     kw.setdefault("count_workspace", False)
+    kw.setdefault("params", None)
     return SortServer(workers=0, **kw)
 
 
@@ -101,3 +102,34 @@ def test_admission_counts_workspace():
     s3.inflight = 1
     s3.queue.append(fake(1000))
     assert s3._take_batch() is None
+
+
+def test_tuned_parameters_per_batch_size():
+    """By default a batch is sorted with the shipped autotuner table's
+    parameters for its element type and size class, and its workspace is
+    bounded with those; a worker whose last batch ran another configuration
+    counts the whole bound (its buffers were sized for other parameters)."""
+    from paper_1705_02257_amd import ips4o_workspace_size
+    from paper_1705_02257_amd.autotune import TUNED, Tuner
+    s = SortServer(workers=0, count_workspace=True, pool_bytes=1 << 40)
+    t = Tuner(cache_path=TUNED)
+    assert t.table, "the package ships a tuned table"
+    for n in (1 << 20, 1 << 24, 1 << 30):
+        assert s.params_for("u64", n) == t.params("u64", n)
+    n = 1 << 20
+    p = t.params("u64", n)
+    bound = ips4o_workspace_size("u64", n, p)
+    s.queue.append(fake(n))
+    _, held = s._take_batch()
+    assert held == n * 8 + bound
+    s.inflight = 0
+    s.queue.append(fake(n))
+    _, held = s._take_batch(ws_have=bound, last=s.config_for("u64", n))
+    assert held == n * 8                            # same configuration: the handle holds enough
+    s.inflight = 0
+    s.queue.append(fake(n))
+    _, held = s._take_batch(ws_have=bound, last=s.config_for("u64", 1 << 30))
+    if s.config_for("u64", 1 << 30) != s.config_for("u64", n):
+        assert held == n * 8 + bound                # other parameters: the whole bound
+    assert SortServer(workers=0, params=None).params_for("u64", n) is None
+    assert SortServer(workers=0, params={"k": 64}).params_for("u64", n) == {"k": 64}

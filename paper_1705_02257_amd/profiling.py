@@ -41,7 +41,8 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "traits.hpp", "driver.hip")]
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
+                  for f in ("kernels.hpp", "traits.hpp", "driver.hip", "planner.hpp", "wrword.hpp")]
 
 # kernel-name prefix -> the kernel kind the library reports timings under
 # (one timing record may span several launches: the overhang copy and the

@@ -159,6 +159,8 @@ struct ips4o_handle {
     HostArena hdesc2;     // the same for odd levels
     hipEvent_t scanned[2] = {nullptr, nullptr};   // a level's bounds have reached the host
     HostArena hsegs;      // pinned staging of the base-case bin list
+    hipEvent_t staged = nullptr;   // recorded after the copies out of hsegs of a launch not waited for
+    bool staged_pending = false;   // such a launch may still read hsegs and segs
     HostArena hfused;     // pinned staging of a level's fused-cleanup bucket flags
     HostArena hstage;     // pinned copies of caller arrays given in device memory
     ips4o_stats last{};
@@ -1018,10 +1020,15 @@ int launch_basecase(ips4o_handle* h, const Ctx<DT>& c, const SegD* segs, size_t 
 // (srcs[i] the buckets of bins[i], none of them tiny) and `lc` (the context
 // of the level that made the bins) the counting sort cleans the buckets
 // first; `mark` receives the timer record of the chunk.
+//
+// With wait = false the call returns once the launches are enqueued: the
+// staging buffers are then guarded by h->staged, and the next chunk waits
+// for the copies out of them before it writes them again (or for the whole
+// stream before it grows them).
 template <int DT>
 int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t count, hipStream_t st,
                        Timer& tm, const BinSrc* srcs = nullptr, const Ctx<DT>* lc = nullptr,
-                       int* mark = nullptr) {
+                       int* mark = nullptr, bool wait = true) {
     using TR = Traits<DT>;
     using Elem = typename TR::Elem;
     struct {
@@ -1043,6 +1050,13 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     for (const SegD& sg : list) ++ncls[cls(sg)];
     const size_t nsmall = ncls[0], nlarge = ncls[1], ntiny = ncls[2];
     const size_t srcb = fused ? list.size() * sizeof(BinSrc) : 0;
+    if (h->staged_pending) {
+        const bool grows = list.size() * sizeof(SegD) + srcb > h->hsegs.bytes ||
+                           2 * list.size() * sizeof(SegD) + srcb > h->segs.bytes || !plain;
+        if (grows) HIP_TRY(hipStreamSynchronize(st));      // buffers in use may be freed
+        else HIP_TRY(hipEventSynchronize(h->staged));       // the copies out of hsegs have run
+        h->staged_pending = false;
+    }
     int rc = h->hsegs.ensure(list.size() * sizeof(SegD) + srcb);
     if (rc) return rc;
     {
@@ -1072,6 +1086,11 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
     if (fused) {
         d_src = (const BinSrc*)((SegD*)h->segs.p + 2 * list.size());
         HIP_TRY(hipMemcpyAsync((void*)d_src, (SegD*)h->hsegs.p + list.size(), srcb, hipMemcpyHostToDevice, st));
+    }
+    const bool async = !wait && !log_enabled();
+    if (async) {
+        if (!h->staged) HIP_TRY(hipEventCreateWithFlags(&h->staged, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(h->staged, st));          // hsegs is free again once this fires
     }
     Ctx<DT> c{};
     if (lc) c = *lc;
@@ -1106,7 +1125,8 @@ int run_basecase_chunk(ips4o_handle* h, void* d_data, const SegD* bins, size_t c
         }
     }
     tm.end(r, 2.0 * sizeof(Elem) * elems);
-    HIP_TRY(hipStreamSynchronize(st));   // the staged list must outlive the copy
+    if (async) h->staged_pending = true;
+    else HIP_TRY(hipStreamSynchronize(st));   // the staged list must outlive the copy
     if (log_enabled()) {
         uint32_t nf[2] = {0, 0};
         HIP_TRY(hipMemcpy(nf, nfail, sizeof(nf), hipMemcpyDeviceToHost));
@@ -1131,6 +1151,27 @@ int run_basecase(ips4o_handle* h, void* d_data, std::vector<SegD>& list, const R
                                               st, tm);
         if (rc) return rc;
     }
+    return IPS4O_OK;
+}
+
+// The base case of the bins found so far, enqueued without waiting for it:
+// their ranges are final and no later level touches them, so they are
+// sorted behind the level just enqueued while the host waits for that
+// level's bounds and plans from them.  The timer records go to `marks`;
+// the caller moves them to the base-case pass once the number of levels is
+// known.
+template <int DT>
+int run_basecase_early(ips4o_handle* h, void* d_data, std::vector<SegD>& list, hipStream_t st, Timer& tm,
+                       std::vector<int>& marks, uint64_t* elems) {
+    for (const SegD& sg : list) *elems += sg.len;
+    for (size_t a = 0; a < list.size(); a += kBaseChunk) {
+        int mk = -1;
+        const int rc = run_basecase_chunk<DT>(h, d_data, list.data() + a, std::min(kBaseChunk, list.size() - a),
+                                              st, tm, nullptr, nullptr, &mk, false);
+        if (rc) return rc;
+        marks.push_back(mk);
+    }
+    list.clear();
     return IPS4O_OK;
 }
 
@@ -1204,8 +1245,8 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     const bool fuse = (R.flags & IPS4O_FLAG_FUSE) || fuse_on();
     std::vector<BinSrc> srcs, fs;
     std::vector<SegD> fb;
-    uint64_t fused_elems = 0;
-    std::vector<int> fused_marks;
+    uint64_t fused_elems = 0;          // elements of base-case launches made during the levels
+    std::vector<int> fused_marks;      // their timer records
     std::vector<uint32_t> level_tasks, level_stripes, level_workers, level_b;
     Timer tm(h, st, (R.flags & IPS4O_FLAG_TIMING) != 0);
     const bool check = (R.flags & IPS4O_FLAG_CHECK) != 0;
@@ -1250,6 +1291,13 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         // buckets of the level's bins
         rc = launch_level_tail<DT>(h, L, st, tm, marks.back(), check, !fuse);
         if (rc) return rc;
+        // the bins of the earlier levels follow on the stream: the device
+        // sorts them while the host waits for this level's bounds and plans
+        // from them
+        if (!base.empty()) {
+            rc = run_basecase_early<DT>(h, d_data, base, st, tm, fused_marks, &fused_elems);
+            if (rc) return rc;
+        }
         level_tasks.push_back((uint32_t)L.tasks.size());
         level_stripes.push_back((uint32_t)L.stripes.size());
         level_workers.push_back(L.total_workers);
@@ -1339,7 +1387,8 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
     }
     h->last.levels = level;
     const auto t3 = clk::now();
-    // the base-case pass follows the last level; the fused launches count there
+    // the base-case pass follows the last level; the fused and early
+    // launches count there
     for (int mk : fused_marks) tm.move_to_pass(mk, level);
     if (fused_elems) tm.set_pass(level, fused_elems);
     rc = run_basecase<DT>(h, d_data, base, R, st, tm, level);       // ends with a stream synchronize
@@ -1851,6 +1900,7 @@ void ips4o_destroy(ips4o_handle* h) {
     h->hdesc2.release();
     for (hipEvent_t& e : h->scanned)
         if (e) (void)hipEventDestroy(e);
+    if (h->staged) (void)hipEventDestroy(h->staged);
     h->misc.release();
     h->segs.release();
     h->rscratch.release();

@@ -1207,12 +1207,13 @@ int enqueue_readback(ips4o_handle* h, Level<DT>& L, HostArena& dst, hipEvent_t e
 // whole array, or the segments of a segmented sort.  A level's bounds are
 // read back as soon as its scan is done; while its permutation and cleanup
 // still run, the host turns them into the next level's plan (or the
-// base-case bins) and enqueues that work behind them.  Levels alternate
-// between two workspaces, so the one a new level takes was last used two
-// levels before, which has finished.
+// base-case bins) and enqueues that work behind them; the bins found by
+// the earlier levels are sorted behind each new level's launches.  Levels
+// alternate between two workspaces, so the one a new level takes was last
+// used two levels before, which has finished.
 template <int DT>
-int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg> init, const Resolved& R,
-                  bool segmented, hipStream_t st) {
+int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg> init, const Resolved& R,
+                       bool segmented, hipStream_t st) {
     h->last = ips4o_stats{};
     int rc = reset_misc(h, st);
     if (rc) return rc;
@@ -1423,6 +1424,24 @@ int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg
         tm.add_bytes(fused_marks[0], 2.0 * sizeof(typename Traits<DT>::Elem) * (double)fc);
     }
     tm.finish();
+    return rc;
+}
+
+// The recursion, and on every way out a wait for base-case launches that
+// were not waited for (an error can end the planning while they still read
+// the handle's bin lists).
+template <int DT>
+int run_sort_list(ips4o_handle* h, void* d_data, uint64_t n_end, std::vector<Seg> init, const Resolved& R,
+                  bool segmented, hipStream_t st) {
+    const int rc = run_sort_list_body<DT>(h, d_data, n_end, std::move(init), R, segmented, st);
+    if (h->staged_pending) {
+        const hipError_t e = hipStreamSynchronize(st);
+        h->staged_pending = false;
+        if (e != hipSuccess && rc == IPS4O_OK) {
+            h->last_hip = e;
+            return IPS4O_ERR_HIP;
+        }
+    }
     return rc;
 }
 

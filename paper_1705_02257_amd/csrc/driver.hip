@@ -1256,6 +1256,12 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
     using clk = std::chrono::steady_clock;
     double t_plan = 0, t_wait = 0, t_next = 0;
     auto since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
+    // the caller's segments within the base-case capacity are sorted while
+    // the host plans the first level (many segments make that plan long)
+    if (!cur.empty() && !base.empty()) {
+        rc = run_basecase_early<DT>(h, d_data, base, st, tm, fused_marks, &fused_elems);
+        if (rc) return rc;
+    }
     while (!cur.empty()) {
         if (level >= kMaxLevels) return IPS4O_ERR_DEVICE_FAULT;
         const auto t0 = clk::now();

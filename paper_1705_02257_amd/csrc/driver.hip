@@ -40,6 +40,7 @@ constexpr uint32_t kDefaultSpin = 1u << 16;      // waits last microseconds; thi
 constexpr uint32_t kMaxLevels = 48;
 constexpr uint64_t kStripeBlocksMax = 256 * 1024 - 2048;   // blocks per classification stripe
 constexpr uint32_t kLevelStripes = 512;      // classification workgroups per level
+constexpr uint32_t kMinStripes = 128;         // stripes a task may take whatever its size (see plan_level)
 constexpr int kSmallSample = 2048;           // sample capacity of the small sampling instance
 constexpr uint32_t kTinyBin = 512;           // u64/f64 base-case bins sorted by one wave
 constexpr size_t kExactOrder = 4096;         // stripes sorted exactly by cost for the launch order
@@ -547,8 +548,13 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
                            : ((first || s.dup) ? std::min<uint32_t>(2 * k, (uint32_t)KMAX) : k);
         const uint64_t nb = (s.m + b - 1) / b;
         // stripes: the task's share, but enough blocks per stripe to keep
-        // the partial buffers small (at least 8 buffer sets of k blocks each)
-        uint64_t by_size = nb / (8ull * k);
+        // the partial buffers small (at least 8 buffer sets of k blocks
+        // each) -- except that a task may take up to kMinStripes stripes of
+        // 32 blocks or more: below about 2^26 keys the first rule leaves
+        // the GPU idle (2^20 u64 keys: 2 stripes, 0.71 ms; 128 stripes,
+        // 0.27 ms; 2^24: 32 stripes 1.49 ms, 128 stripes 1.27 ms), while the
+        // partial buffers of such small tasks cost little
+        uint64_t by_size = std::max<uint64_t>(nb / (8ull * k), std::min<uint64_t>(kMinStripes, nb / 32));
         uint64_t ns = std::max<uint64_t>(1, std::min(by_size, share[i]));
         if (first && R.stripes) ns = R.stripes;
         // the classification's block lists fit its LDS for stripes of up

@@ -73,7 +73,8 @@ typedef enum {
 /* Tuning parameters (Section 4, Implementation Details).  A zero field takes
  * the default; a NULL params pointer takes all defaults.
  *   k           buckets of the first level, a power of two in [2, 1024]
- *               (default 256).  Deeper levels choose k adaptively.
+ *               (default 256, and 128 for arrays of fewer than 2^27
+ *               elements).  Deeper levels choose k adaptively.
  *   block_bytes target block size in bytes; b = max(1, 2^floor(log2(
  *               block_bytes / s))) elements (default 2048, as in the paper).
  *   base_cap    largest subproblem (elements) sorted by the base case

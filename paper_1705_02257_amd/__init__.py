@@ -27,7 +27,14 @@ DTYPES = {"u64": U64, "f64": F64, "pair": PAIR, "quartet": QUARTET, "bytes100": 
 ELEM_BYTES = {U64: 8, F64: 8, PAIR: 16, QUARTET: 32, BYTES100: 100}
 FLAG_NO_SKIP = 1
 FLAG_FUSE = 8            # base-case kernels clean the buckets of their bins (off by default)
-DEFAULT_K = 256          # first-level buckets when params leave k at 0
+DEFAULT_K = 256          # first-level buckets when params leave k at 0 ...
+DEFAULT_K_SMALL = 128    # ... for arrays of fewer than 2^27 elements
+
+
+def default_k(n: int) -> int:
+    """The first level's bucket count the library uses for n elements when
+    the parameters leave k at 0 (as documented for ips4o_params.k)."""
+    return DEFAULT_K_SMALL if n < (1 << 27) else DEFAULT_K
 DEFAULT_BLOCK_BYTES = 2048  # block size when params leave block_bytes at 0
 
 #: C symbols the library exports (as declared in include/ips4o.h)

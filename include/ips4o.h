@@ -82,8 +82,9 @@ typedef enum {
  *   alpha_x100  oversampling factor times 100, used on every level (default:
  *               0.2 * log2 m for a subproblem of m elements, raised to
  *               min(32, sample capacity / k)).
- *   stripes     classification workgroups for the first level (default:
- *               chosen from n).
+ *   stripes     classification workgroups for the first level of one array
+ *               (default: chosen from n; a segmented sort shares its own
+ *               count among the segments and ignores this field).
  *   workers     permutation workers (wavefronts) per level, rounded up to a
  *               multiple of four, at most 16380 (default 8192: one round of
  *               the permutation kernel's workgroups on the device).  A level shares them

@@ -70,10 +70,12 @@ class SortServer:
     and max_batch: limits of one batch; workers: concurrent batches, one
     handle and stream each; batching=False sorts every request on its own,
     first come first served (the one-at-a-time reference); params: the
-    sort parameters of a batch -- "tuned" (the autotuner's table shipped
-    with the package, looked up by element type and batch size; library
-    defaults where it has no entry), None (library defaults) or one
-    ips4o_params dict for every batch."""
+    sort parameters of a request sorted on its own -- "tuned" (the
+    autotuner's table shipped with the package, tuned on single arrays and
+    looked up by element type and size; library defaults where it has no
+    entry), None (library defaults) or one ips4o_params dict; batches of
+    several requests (one segmented sort) use the library defaults, which
+    choose k per segment."""
 
     def __init__(self, device=0, pool_bytes=64 << 30, workers=2, max_batch_bytes=8 << 30, max_batch=4096,
                  batching=True, queue_limit=1 << 20, count_workspace=True, params="tuned"):
@@ -144,18 +146,21 @@ class SortServer:
             raise self._errors[0]
 
     # ------------------------------------------------------------ workers
-    def params_for(self, dtype, n):
-        """The parameters a batch of n elements of dtype is sorted with."""
+    def params_for(self, dtype, n, single=True):
+        """The parameters a request of n elements of dtype is sorted with
+        (single: on its own; else a batch of n elements in all)."""
+        if not single:
+            return None
         if self.tuner is not None:
             return self.tuner.params(dtype, n)
         return self.fixed_params
 
-    def config_for(self, dtype, n):
+    def config_for(self, dtype, n, single=True):
         """Element type and parameters of a batch of n elements."""
-        p = self.params_for(dtype, n)
+        p = self.params_for(dtype, n, single)
         return (dtype, tuple(sorted(p.items())) if p else None)
 
-    def _growth(self, dtype, n, ws_have, last=None):
+    def _growth(self, dtype, n, ws_have, last=None, single=True):
         """Workspace a batch of n elements may add to a handle holding
         ws_have after a batch of configuration `last` (config_for): the
         bound beyond what the handle holds when the configuration is the
@@ -163,8 +168,8 @@ class SortServer:
         other parameters and may not cover this batch's)."""
         if not self.count_workspace:
             return 0
-        bound = ips4o_workspace_size(dtype, n, self.params_for(dtype, n))
-        if ws_have and last is not None and self.config_for(dtype, n) != last:
+        bound = ips4o_workspace_size(dtype, n, self.params_for(dtype, n, single))
+        if ws_have and last is not None and self.config_for(dtype, n, single) != last:
             return bound
         return max(0, bound - ws_have)
 
@@ -189,13 +194,13 @@ class SortServer:
                 keep.append(self.queue.popleft())
                 continue
             t2 = total + r.nbytes
-            if t2 > self.max_batch_bytes or busy + 2 * t2 + self._growth(head.dtype, elems + r.n, ws_have, last) > \
+            if t2 > self.max_batch_bytes or busy + 2 * t2 + self._growth(head.dtype, elems + r.n, ws_have, last, False) > \
                     self.pool_bytes:
                 break
             batch.append(self.queue.popleft())
             total, elems = t2, elems + r.n
         self.queue.extendleft(reversed(keep))
-        held = (2 * total if len(batch) > 1 else total) + self._growth(head.dtype, elems, ws_have, last)
+        held = (2 * total if len(batch) > 1 else total) + self._growth(head.dtype, elems, ws_have, last, len(batch) == 1)
         self.inflight += held
         return batch, held
 
@@ -244,7 +249,7 @@ class SortServer:
                 self.completed.extend(batch)
                 self.cond.notify_all()
             ws_have = ws_now
-            last = self.config_for(batch[0].dtype, sum(r.n for r in batch))
+            last = self.config_for(batch[0].dtype, sum(r.n for r in batch), len(batch) == 1)
             for r in batch:
                 r._done.set()
 
@@ -262,7 +267,7 @@ class SortServer:
         offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
         flat = [r.tensor.reshape(-1) for r in batch]
         staging = torch.cat(flat)
-        ips4o_sort_segmented(h, staging, offs, dtype, self.params_for(dtype, int(offs[-1])), stream)
+        ips4o_sort_segmented(h, staging, offs, dtype, self.params_for(dtype, int(offs[-1]), False), stream)
         words = [f.numel() for f in flat]
         at = 0
         for r, f, w in zip(batch, flat, words):

@@ -105,10 +105,12 @@ def test_admission_counts_workspace():
 
 
 def test_tuned_parameters_per_batch_size():
-    """By default a batch is sorted with the shipped autotuner table's
-    parameters for its element type and size class, and its workspace is
-    bounded with those; a worker whose last batch ran another configuration
-    counts the whole bound (its buffers were sized for other parameters)."""
+    """By default a request sorted on its own uses the shipped autotuner
+    table's parameters for its element type and size class, and its
+    workspace is bounded with those; a batch of several requests (one
+    segmented sort) uses the library defaults; a worker whose last batch
+    ran another configuration counts the whole bound (its buffers were
+    sized for other parameters)."""
     from paper_1705_02257_amd import ips4o_workspace_size
     from paper_1705_02257_amd.autotune import TUNED, Tuner
     s = SortServer(workers=0, count_workspace=True, pool_bytes=1 << 40)
@@ -131,5 +133,10 @@ def test_tuned_parameters_per_batch_size():
     _, held = s._take_batch(ws_have=bound, last=s.config_for("u64", 1 << 30))
     if s.config_for("u64", 1 << 30) != s.config_for("u64", n):
         assert held == n * 8 + bound                # other parameters: the whole bound
+    assert s.params_for("u64", n, single=False) is None    # batches: the library's per-segment choices
+    s.inflight = 0
+    s.queue.extend([fake(n), fake(n)])
+    batch, held = s._take_batch()
+    assert len(batch) == 2 and held == 2 * 2 * n * 8 + ips4o_workspace_size("u64", 2 * n)
     assert SortServer(workers=0, params=None).params_for("u64", n) is None
     assert SortServer(workers=0, params={"k": 64}).params_for("u64", n) == {"k": 64}

@@ -483,9 +483,16 @@ struct Level {
 // twice the buffers or half the stripes (its classification then took
 // 2.4 ms longer); with at most 512 buckets a small third level now and then
 // costs about 0.1 ms.
+// A subproblem that kDeepK buckets would leave at more than 3/4 of the
+// capacity on average takes 2 kDeepK instead: otherwise most of its buckets
+// overflow into a third level (2^31 u64 keys, level-2 subproblems of 8 M:
+// 68.8 ms with 512, most of it a large third level).
 constexpr uint32_t kDeepK = 512;
+static_assert(2 * kDeepK <= (uint32_t)KT_MAX, "deep bucket counts fit the tree");
 uint32_t adaptive_k(uint64_t m, const Resolved& R) {
-    return std::min<uint32_t>(kDeepK, std::max<uint32_t>(2u, next_pow2((2 * m + R.cap - 1) / R.cap)));
+    const uint64_t want = (2 * m + R.cap - 1) / R.cap;
+    if (want > (uint64_t)kDeepK * 3 / 2) return 2 * kDeepK;
+    return std::min<uint32_t>(kDeepK, std::max<uint32_t>(2u, next_pow2(want)));
 }
 
 // `first`: the top level of one array, whose k is the caller's (or the

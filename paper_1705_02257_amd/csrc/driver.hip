@@ -525,8 +525,11 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             given += share[i];
             rem.push_back({q - std::floor(q), i});
         }
-        std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-        for (size_t r = 0; given < kLevelStripes && r < rem.size(); ++r, ++given) share[rem[r].second] += 1;
+        // the largest remainders get one more (only as many as are left)
+        const size_t extra = std::min<size_t>(rem.size(), given < kLevelStripes ? kLevelStripes - given : 0);
+        std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
+                          [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (size_t r = 0; r < extra; ++r) share[rem[r].second] += 1;
     }
     // Permutation workers per task, in groups of four (one workgroup):
     // R.workers / 4 groups shared out in proportion to the task's blocks
@@ -547,8 +550,12 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
             given += wgroups[i];
             if (wgroups[i] < gmax) rem.push_back({q - std::floor(q), i});
         }
-        std::sort(rem.begin(), rem.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-        for (size_t r = 0; given < G && r < rem.size(); ++r, ++given) wgroups[rem[r].second] += 1;
+        // the largest remainders get one more group (only as many as are
+        // left: with more tasks than groups, none)
+        const size_t extra = std::min<size_t>(rem.size(), given < G ? G - given : 0);
+        std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
+                          [](const auto& a, const auto& b) { return a.first > b.first; });
+        for (size_t r = 0; r < extra; ++r) wgroups[rem[r].second] += 1;
     }
     // bucket count, buffer count and stripes of every task
     const size_t T = segs.size();

@@ -512,6 +512,8 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
     }
     L.tasks.clear();
     L.stripes.clear();
+    L.tasks.reserve(segs.size());
+    L.stripes.reserve(segs.size() + kLevelStripes);
     // Stripes per task: kLevelStripes shared out in proportion to the task
     // sizes (largest remainders, at least one each), so that a level that
     // fits in one round of workgroups per CU leaves no partial last round.
@@ -527,8 +529,9 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         }
         // the largest remainders get one more (only as many as are left)
         const size_t extra = std::min<size_t>(rem.size(), given < kLevelStripes ? kLevelStripes - given : 0);
-        std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
-                          [](const auto& a, const auto& b) { return a.first > b.first; });
+        if (extra)
+            std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
+                              [](const auto& a, const auto& b) { return a.first > b.first; });
         for (size_t r = 0; r < extra; ++r) share[rem[r].second] += 1;
     }
     // Permutation workers per task, in groups of four (one workgroup):
@@ -553,8 +556,9 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         // the largest remainders get one more group (only as many as are
         // left: with more tasks than groups, none)
         const size_t extra = std::min<size_t>(rem.size(), given < G ? G - given : 0);
-        std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
-                          [](const auto& a, const auto& b) { return a.first > b.first; });
+        if (extra)
+            std::partial_sort(rem.begin(), rem.begin() + extra, rem.end(),
+                              [](const auto& a, const auto& b) { return a.first > b.first; });
         for (size_t r = 0; r < extra; ++r) wgroups[rem[r].second] += 1;
     }
     // bucket count, buffer count and stripes of every task
@@ -607,9 +611,18 @@ void plan_level(Level<DT>& L, const std::vector<Seg>& segs, const Resolved& R, u
         };
         uint64_t tot = total();
         if (tot > buf_budget) {
+            // tasks by buffer count, largest first, ties in task order (a
+            // counting sort: kb is a power of two up to KMAX, and a level
+            // may hold tens of thousands of tasks)
             std::vector<size_t> idx(T);
-            for (size_t i = 0; i < T; ++i) idx[i] = i;
-            std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return kb[x] > kb[y]; });
+            {
+                constexpr int NC = 12;                          // log2 of kb: 0 .. 11
+                size_t start[NC + 1] = {0};
+                auto cls = [&](size_t i) { return NC - 1 - std::min(NC - 1, 31 - __builtin_clz(std::max(1u, kb[i]))); };
+                for (size_t i = 0; i < T; ++i) ++start[cls(i) + 1];
+                for (int c = 0; c < NC; ++c) start[c + 1] += start[c];
+                for (size_t i = 0; i < T; ++i) idx[start[cls(i)]++] = i;
+            }
             auto cut_kbuf = [&](bool dup) {
                 for (size_t i : idx) {
                     if (tot <= buf_budget) break;
@@ -1297,7 +1310,7 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
     // host time (IPS4O_LOG): planning and enqueueing, waiting for a level's
     // bounds, turning them into the next plan
     using clk = std::chrono::steady_clock;
-    double t_plan = 0, t_wait = 0, t_next = 0;
+    double t_plan = 0, t_wait = 0, t_next = 0, t_planlevel = 0, t_head = 0;
     auto since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
     // the caller's segments within the base-case capacity are sorted while
     // the host plans the first level (many segments make that plan long)
@@ -1322,6 +1335,7 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
         }
         level_b.push_back(RL.b);
         plan_level<DT>(L, cur, RL, level, level == 0, 0, segmented && level == 0, 0, buf_budget);
+        t_planlevel += since(t0);
         rc = work.ensure(level_bytes<DT>(L, RL.b));
         if (rc) return rc;
         rc = ensure_bufs<DT>(h, L, st);
@@ -1333,8 +1347,10 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
             tm.set_pass(level, lm);
         }
         marks.emplace_back();
+        const auto th = clk::now();
         rc = launch_level_head<DT>(h, L, st, nullptr, tm, check, par ? &h->hdesc2 : &h->hdesc);
         if (rc) return rc;
+        t_head += since(th);
         rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
         if (rc) return rc;
         // the cleanup waits for the bounds when the base case cleans the
@@ -1445,7 +1461,8 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
     if (rc) return rc;
     if (log_enabled())
         std::fprintf(stderr, "[ips4o] host ms: plan+enqueue %.3f, wait for bounds %.3f, next plan %.3f, "
-                     "base case (to the end) %.3f\n", t_plan, t_wait, t_next, since(t3));
+                     "base case (to the end) %.3f; of the first: level plans %.3f, first halves %.3f\n", t_plan,
+                     t_wait, t_next, since(t3), t_planlevel, t_head);
     rc = check_device_error(h, st);
     // per-level counters: block moves, skips, cleanup and fix element counts
     std::vector<unsigned long long> cnt(kStatLevels * kStatsBytes / 8);

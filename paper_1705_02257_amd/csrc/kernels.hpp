@@ -1928,8 +1928,8 @@ struct BaseLds {
 // about one item; each item's final place is the group start plus the
 // number of group members that precede it (smaller, or equal and placed
 // earlier), counted with the items taken in group order.  Where a digit
-// covers a single u64/f64 key value every group is a run of equal keys and
-// needs no ranking.  A segment whose keys are all equal is left as it is.
+// covers a single u64/f64 or Pair key value every group is a run of equal
+// keys and needs no ranking.  A segment whose keys are all equal is left as it is.
 // Segments whose ranking would cost more than WMAX compares per item (keys
 // crowded into a few digits), and records with one leading word, are left
 // untouched and appended to `fail` for k_basecase (merge sort).
@@ -2065,9 +2065,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const uint32_t bits = 64u - (uint32_t)__clzll(span);
             const uint32_t over = bits > LB::LOG_CAP ? bits - LB::LOG_CAP : 0u;
             sh = tz + over;
-            // u64/f64 keys with one key value per digit: every group is a
-            // run of equal keys, already in place once scattered
-            exact = kPlain && over == 0;
+            // one key value per digit: every group is a run of equal keys,
+            // already in place once scattered -- for u64/f64 keys, and for
+            // Pair records, whose key is the leading word (records with
+            // equal keys may come out in any order: the sort is not stable)
+            exact = (kPlain || DT == DT_PAIR) && over == 0;
 #pragma unroll
             for (int v = 0; v < VT; ++v) {
                 if (v * NT + tid < len) {

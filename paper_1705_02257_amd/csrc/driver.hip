@@ -745,14 +745,14 @@ size_t level_bytes(const Level<DT>& L, uint32_t b) {
     auto add = [&](size_t bytes) { off = Carve::size_of(off, bytes); };
     add(T * sizeof(TaskD));
     add(S * sizeof(StripeD));
+    add(S * sizeof(uint32_t));
     add(T * sizeof(TaskS));
-    add(L.total_tree * sizeof(Key));
-    add(L.total_tree * sizeof(Key));
     add((L.total_slots + T) * sizeof(uint64_t));
+    add(L.total_tree * sizeof(Key));
+    add(L.total_tree * sizeof(Key));
     add((L.total_slots + T) * sizeof(uint32_t));
     add(L.total_slots * sizeof(BucketSlot));
     add(L.total_cnt * sizeof(uint32_t));
-    add(S * sizeof(uint32_t));
     add(S * sizeof(uint32_t));
     add(L.total_slots);
     return off + 256;
@@ -767,17 +767,19 @@ void carve_level(Level<DT>& L, void* base, void* misc, void* data, void* bufs, c
     Carve cv(base);
     Ctx<DT>& c = L.c;
     c.data = (Elem*)data;
+    // the host-written descriptors next to each other (one copy in), then
+    // the task state and bounds the host reads back (one copy out)
     c.tasks = cv.take<TaskD>(T);
     c.stripes = cv.take<StripeD>(S);
+    c.order = cv.take<uint32_t>(S);
     c.ts = cv.take<TaskS>(T);
+    c.bounds = cv.take<uint64_t>(L.total_slots + T);
     c.tree = cv.take<Key>(L.total_tree);
     c.spl = cv.take<Key>(L.total_tree);
-    c.bounds = cv.take<uint64_t>(L.total_slots + T);
     c.delim = cv.take<uint32_t>(L.total_slots + T);
     c.slots = cv.take<BucketSlot>(L.total_slots);
     c.counts = cv.take<uint32_t>(L.total_cnt);
     c.stripe_full = cv.take<uint32_t>(S);
-    c.order = cv.take<uint32_t>(S);
     L.fused_flags = cv.take<uint8_t>(L.total_slots);
     c.fused = nullptr;
     c.bufs = (Elem*)bufs;
@@ -848,20 +850,23 @@ int launch_level_head(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostT
     const void* src_stripes = L.stripes.data();
     const void* src_order = L.order.data();
     if (stage) {
+        // the device layout (tasks, stripes, order, carved in that order)
+        // mirrored in the staging buffer: one copy
         const size_t bt = T * sizeof(TaskD), bs = S * sizeof(StripeD), bo = S * sizeof(uint32_t);
-        int rc = stage->ensure(bt + bs + bo);
+        const size_t os = (size_t)((const char*)c.stripes - (const char*)c.tasks);
+        const size_t oo = (size_t)((const char*)c.order - (const char*)c.tasks);
+        int rc = stage->ensure(oo + bo);
         if (rc) return rc;
         char* p = (char*)stage->p;
         std::memcpy(p, L.tasks.data(), bt);
-        std::memcpy(p + bt, L.stripes.data(), bs);
-        std::memcpy(p + bt + bs, L.order.data(), bo);
-        src_tasks = p;
-        src_stripes = p + bt;
-        src_order = p + bt + bs;
+        std::memcpy(p + os, L.stripes.data(), bs);
+        std::memcpy(p + oo, L.order.data(), bo);
+        HIP_TRY(hipMemcpyAsync((void*)c.tasks, p, oo + bo, hipMemcpyHostToDevice, st));
+    } else {
+        HIP_TRY(hipMemcpyAsync((void*)c.tasks, src_tasks, T * sizeof(TaskD), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync((void*)c.stripes, src_stripes, S * sizeof(StripeD), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync((void*)c.order, src_order, S * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     }
-    HIP_TRY(hipMemcpyAsync((void*)c.tasks, src_tasks, T * sizeof(TaskD), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync((void*)c.stripes, src_stripes, S * sizeof(StripeD), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync((void*)c.order, src_order, S * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (given) {
         HIP_TRY(hipMemcpyAsync(c.tree, given->tree.data(), given->tree.size() * sizeof(Key), hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(c.spl, given->spl.data(), given->spl.size() * sizeof(Key), hipMemcpyHostToDevice, st));
@@ -1244,17 +1249,27 @@ int ensure_bufs(ips4o_handle* h, const Level<DT>& L, hipStream_t st) {
     return h->bufs.ensure_exact(need);
 }
 
+// Offset of a level's bounds from its task state in the workspace (they
+// are carved one after the other, so one copy reads both back).
+template <int DT>
+size_t readback_bounds_off(const Level<DT>& L) {
+    return (size_t)((const char*)L.c.bounds - (const char*)L.c.ts);
+}
+
 // Copies of a level's error word, task state and bounds into pinned memory,
-// enqueued right after its scan; `ev` fires when they have arrived.
+// enqueued right after its scan; `ev` fires when they have arrived.  Layout
+// in `dst`: the error words (256 bytes), then the task state and the bounds
+// as they lie in the workspace (bounds at readback_bounds_off(L) from the
+// task state).
 template <int DT>
 int enqueue_readback(ips4o_handle* h, Level<DT>& L, HostArena& dst, hipEvent_t ev, hipStream_t st) {
-    const size_t T = L.tasks.size(), nb = L.total_slots + T;
-    int rc = dst.ensure(256 + T * sizeof(TaskS) + nb * sizeof(uint64_t));
+    const size_t nb = L.total_slots + L.tasks.size();
+    const size_t ob = readback_bounds_off(L), bytes = ob + nb * sizeof(uint64_t);
+    int rc = dst.ensure(256 + bytes);
     if (rc) return rc;
     char* p = (char*)dst.p;
     HIP_TRY(hipMemcpyAsync(p, h->misc.p, 256, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(p + 256, L.c.ts, T * sizeof(TaskS), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(p + 256 + T * sizeof(TaskS), L.c.bounds, nb * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(p + 256, L.c.ts, bytes, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(ev, st));
     return IPS4O_OK;
 }
@@ -1381,7 +1396,7 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
             return IPS4O_ERR_DEVICE_FAULT;
         }
         const TaskS* ts = (const TaskS*)(rp + 256);
-        const uint64_t* bounds = (const uint64_t*)(rp + 256 + T * sizeof(TaskS));
+        const uint64_t* bounds = (const uint64_t*)(rp + 256 + readback_bounds_off(L));
         std::vector<Seg> next;
         base.reserve(base.size() + L.total_slots);
         const size_t base_before = base.size();

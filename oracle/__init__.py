@@ -61,6 +61,11 @@ def _load():
         L.or_select_splitters_capped.restype = i32
         L.or_tree.argtypes = [vp, u32, vp]; L.or_tree.restype = None
         L.or_tree_descend.argtypes = [vp, u32, u64]; L.or_tree_descend.restype = u32
+        L.or_mark_bucket_max.argtypes = [vp, i32, vp, u32]; L.or_mark_bucket_max.restype = i32
+        L.or_search_next_largest.argtypes = [vp, vp, u64, u64, i32, ctypes.POINTER(u64)]
+        L.or_search_next_largest.restype = u64
+        L.or_sort_strict.argtypes = [vp, u64, i32, u32, u32, u64, u64, vp]
+        L.or_sort_strict.restype = i32
         _lib = L
     return _lib
 
@@ -285,3 +290,47 @@ def alpha_default(n: int) -> int:
     """Oversampling factor 0.2*log2(n), at least 1 (Section 4, Implementation Details)."""
     import math
     return max(1, int(0.2 * math.log2(n))) if n > 1 else 1
+
+
+def mark_bucket_max(arr: np.ndarray, bounds, dtype: str) -> np.ndarray:
+    """Copy of arr with the largest element of every bucket
+    [bounds[b], bounds[b+1]) moved to the bucket's first entry
+    (or_mark_bucket_max, Section 4.6)."""
+    out = np.ascontiguousarray(arr).copy()
+    bd = np.ascontiguousarray(bounds, dtype=np.uint64)
+    nb = max(bd.shape[0] - 1, 0)
+    if nb and int(bd[-1]) > out.shape[0]:
+        raise ValueError("bounds beyond the array")
+    if _load().or_mark_bucket_max(_ptr(out), DTYPES[dtype], _ptr(bd), nb) != 0:
+        raise ValueError("or_mark_bucket_max: bad arguments")
+    return out
+
+
+def search_next_largest(arr: np.ndarray, i: int, dtype: str, hi: int = None):
+    """(searchNextLargest(A[i], A, i+1, hi), keys compared) of Section 4.6,
+    0-based: the first position after i holding a key larger than A[i]'s, or
+    hi (default len(arr)) if none, by exponential search and bisection."""
+    a = np.ascontiguousarray(arr)
+    hi = _n(a) if hi is None else hi
+    if not 0 <= i < hi <= _n(a):
+        raise ValueError("position outside the array")
+    pivot = a[i].copy()
+    probes = ctypes.c_uint64(0)
+    j = _load().or_search_next_largest(_ptr(np.ascontiguousarray(pivot)), _ptr(a), i + 1, hi, DTYPES[dtype],
+                                       ctypes.byref(probes))
+    return int(j), int(probes.value)
+
+
+def sort_strict(arr: np.ndarray, dtype: str, k: int = 16, alpha: int = 2, n0: int = 16, seed: int = 1):
+    """(sorted copy, stats) by sequential samplesort whose recursion is
+    emulated in constant space through bucket maxima and searchNextLargest
+    (or_sort_strict, Section 4.6).  stats: partitions, insertion sorts,
+    ranges found constant, keys compared by the searches."""
+    out = np.ascontiguousarray(arr).copy()
+    st = np.zeros(4, dtype=np.uint64)
+    rc = _load().or_sort_strict(_ptr(out), _n(out), DTYPES[dtype], k, alpha, n0, seed & (2**64 - 1),
+                                st.ctypes.data)
+    if rc != 0:
+        raise ValueError("or_sort_strict: bad arguments")
+    return out, {"partitions": int(st[0]), "small_sorts": int(st[1]), "constant": int(st[2]),
+                 "probes": int(st[3])}

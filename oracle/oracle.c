@@ -314,3 +314,185 @@ uint32_t or_tree_descend(const uint64_t *a, uint32_t k, uint64_t e) {
     while (j < k) j = 2 * j + (a[j - 1] <= e ? 1u : 0u);
     return j - k;
 }
+
+/* ---- Section 4.6, From Almost In-Place to Strictly In-Place ----
+ *
+ * The partitioning step leaves the largest element of every bucket in the
+ * bucket's first entry; the end of a bucket is then found from the data
+ * alone, as the first later position holding a larger key, so the recursion
+ * keeps no bucket boundaries. */
+
+static void swap_elems(unsigned char *a, unsigned char *b, size_t s) {
+    unsigned char t[128];
+    memcpy(t, a, s);
+    memcpy(a, b, s);
+    memcpy(b, t, s);
+}
+
+/* The marking the partitioning step must do (Section 4.6): for every bucket
+ * [bounds[b], bounds[b+1]) of at least two elements, the first element whose
+ * key is the largest of the bucket trades places with the bucket's first
+ * element.  bounds[0..nb] are absolute positions, non-decreasing.  Returns
+ * 0, or -1 for a bad dtype or decreasing bounds. */
+int or_mark_bucket_max(void *data, int dtype, const uint64_t *bounds, uint32_t nb) {
+    size_t s = or_elem_size(dtype);
+    if (!s) return -1;
+    unsigned char *d = (unsigned char *)data;
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (bounds[b + 1] < bounds[b]) return -1;
+        uint64_t lo = bounds[b], hi = bounds[b + 1], best = lo;
+        if (hi - lo < 2) continue;
+        for (uint64_t p = lo + 1; p < hi; ++p)
+            if (or_compare(d + p * s, d + best * s, dtype) > 0) best = p;
+        if (best != lo) swap_elems(d + lo * s, d + best * s, s);
+    }
+    return 0;
+}
+
+/* searchNextLargest (Section 4.6): the first position j in [lo, hi) whose
+ * key is larger than the key of `pivot` (an element outside the searched
+ * range, typically A[lo-1]), or hi if there is none.  Exponential search
+ * probes lo, lo+1, lo+3, lo+7, ... (offsets 2^t - 1) until a larger key or
+ * the end, then bisection between the last two probes finds the first
+ * larger key.  The result is that first position whenever the positions
+ * of [lo, hi) holding larger keys form a suffix of it, as they do after a
+ * marked partition: the pivot is the largest key of its bucket and every
+ * later bucket holds only larger keys.  Otherwise it is some position in
+ * [lo, hi].  *probes (if given) receives the number of keys compared. */
+uint64_t or_search_next_largest(const void *pivot, const void *data, uint64_t lo, uint64_t hi, int dtype,
+                                uint64_t *probes) {
+    size_t s = or_elem_size(dtype);
+    const unsigned char *d = (const unsigned char *)data;
+    uint64_t cnt = 0;
+    /* exponential phase: the first probe lo + 2^t - 1 that is >= hi or larger */
+    uint64_t below = lo, step = 1;          /* every position in [lo, below) is known not larger */
+    uint64_t above = hi;                    /* the answer is at most `above` */
+    for (;;) {
+        uint64_t p = lo + step - 1;
+        if (p >= hi) break;
+        ++cnt;
+        if (or_compare(d + p * s, pivot, dtype) > 0) { above = p; break; }
+        below = p + 1;
+        step *= 2;
+    }
+    /* bisection over [below, above): the first position holding a larger key */
+    while (below < above) {
+        uint64_t mid = below + (above - below) / 2;
+        ++cnt;
+        if (or_compare(d + mid * s, pivot, dtype) > 0) above = mid;
+        else below = mid + 1;
+    }
+    if (probes) *probes = cnt;
+    return above;
+}
+
+/* Insertion sort of A[lo, hi): the base case below n0 (Section 4,
+ * Implementation Details). */
+static void insertion_sort(unsigned char *d, uint64_t lo, uint64_t hi, int dtype, size_t s) {
+    unsigned char t[128];
+    for (uint64_t i = lo + 1; i < hi; ++i) {
+        memcpy(t, d + i * s, s);
+        uint64_t j = i;
+        while (j > lo && or_compare(d + (j - 1) * s, t, dtype) > 0) {
+            memcpy(d + j * s, d + (j - 1) * s, s);
+            --j;
+        }
+        memcpy(d + j * s, t, s);
+    }
+}
+
+/* One partitioning step of A[lo, hi) as Section 4.6 requires it: splitters
+ * from a sample (or_select_splitters, sample stream splitmix64 output lo of
+ * `seed`), every element moved to its bucket (or_bucket) with the order
+ * inside a bucket kept (the arrangement inside a bucket is not fixed by the
+ * method; this one needs a buffer of hi - lo elements, which is no concern
+ * of a checker), then the bucket maxima marked (or_mark_bucket_max).
+ * Returns the number of non-empty buckets, or -1. */
+static int partition_marked(unsigned char *d, uint64_t lo, uint64_t hi, int dtype, uint32_t k, uint32_t alpha,
+                            uint64_t seed) {
+    size_t s = or_elem_size(dtype);
+    uint64_t m = hi - lo;
+    unsigned char *smp = malloc(((size_t)alpha * k) * s), *spl = malloc((size_t)k * s), *tmp = malloc(m * s);
+    uint64_t *bounds = malloc((2 * (size_t)k + 2) * sizeof(uint64_t));
+    uint32_t *bk = malloc(m * sizeof(uint32_t));
+    int rc = -1;
+    if (!smp || !spl || !tmp || !bounds || !bk) goto out;
+    uint32_t mu = 0;
+    int eq = 0;
+    if (or_select_splitters(d + lo * s, m, dtype, k, alpha, or_splitmix64_at(seed, lo), smp, spl, &mu, &eq))
+        goto out;
+    uint32_t K = or_num_buckets(dtype, spl, mu, eq);
+    for (uint32_t b = 0; b <= K; ++b) bounds[b] = 0;
+    for (uint64_t i = 0; i < m; ++i) {
+        bk[i] = or_bucket(d + (lo + i) * s, dtype, spl, mu, eq);
+        bounds[bk[i] + 1]++;
+    }
+    for (uint32_t b = 0; b < K; ++b) bounds[b + 1] += bounds[b];
+    {
+        uint64_t *fill = malloc(((size_t)K + 1) * sizeof(uint64_t));
+        if (!fill) goto out;
+        memcpy(fill, bounds, ((size_t)K + 1) * sizeof(uint64_t));
+        for (uint64_t i = 0; i < m; ++i) memcpy(tmp + (fill[bk[i]]++) * s, d + (lo + i) * s, s);
+        free(fill);
+    }
+    memcpy(d + lo * s, tmp, m * s);
+    rc = 0;
+    for (uint32_t b = 0; b <= K; ++b) bounds[b] += lo;
+    for (uint32_t b = 0; b < K; ++b) rc += bounds[b + 1] > bounds[b];
+    or_mark_bucket_max(d, dtype, bounds, K);
+out:
+    free(smp); free(spl); free(tmp); free(bounds); free(bk);
+    return rc;
+}
+
+/* Sequential samplesort with the recursion emulated in constant space
+ * (Section 4.6): i is the first element of the current bucket, j the first
+ * element of the next one.  While elements remain: a bucket of fewer than
+ * n0 elements is sorted by insertion sort and i moves to j; a larger one is
+ * partitioned (k buckets, oversampling alpha), which makes its first bucket
+ * the current one.  Either way the next j is searchNextLargest(A[i]) over
+ * A[i+1, n): A[i] holds the largest key of its bucket, put there by the
+ * partition that made the bucket.
+ *
+ * Reading (the loop as printed never ends on a range of equal keys, which
+ * every partition leaves in one bucket): a partition that leaves all of
+ * [i, j) in one bucket means the range holds a single key value, since with
+ * k >= 3 a range of two or more distinct keys always falls into at least
+ * two buckets (its smallest and largest sampled splitters classify apart,
+ * or, with equality buckets, a key differing from the one repeated splitter
+ * leaves that splitter's bucket).  Such a range is already sorted, and i
+ * moves to j.
+ *
+ * stats (if given, 4 entries): partitions, insertion sorts, ranges found
+ * constant, and keys compared by searchNextLargest.  Requires k >= 3,
+ * alpha >= 1, n0 >= 1.  Returns 0, or -1. */
+int or_sort_strict(void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha, uint64_t n0, uint64_t seed,
+                   uint64_t *stats) {
+    size_t s = or_elem_size(dtype);
+    if (!s || k < 3 || alpha < 1 || n0 < 1) return -1;
+    unsigned char *d = (unsigned char *)data, pivot[128];
+    uint64_t st[4] = {0, 0, 0, 0};
+    uint64_t i = 0, j = n;
+    while (i < n) {
+        if (j - i < n0) {
+            insertion_sort(d, i, j, dtype, s);
+            st[1]++;
+            i = j;
+        } else {
+            int nonempty = partition_marked(d, i, j, dtype, k, alpha, seed);
+            if (nonempty < 0) return -1;
+            st[0]++;
+            if (nonempty == 1) {        /* one key value: already sorted */
+                st[2]++;
+                i = j;
+            }
+        }
+        if (i >= n) break;
+        uint64_t pr = 0;
+        memcpy(pivot, d + i * s, s);
+        j = or_search_next_largest(pivot, d, i + 1, n, dtype, &pr);
+        st[3] += pr;
+    }
+    if (stats) memcpy(stats, st, sizeof st);
+    return 0;
+}

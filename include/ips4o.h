@@ -118,6 +118,16 @@ typedef struct {
                                    cleanup is done).  Same results; slower on gfx950 (the cleanup of
                                    a bin is a chain of dependent memory accesses inside one
                                    workgroup), so it is off by default */
+#define IPS4O_FLAG_STRICT  16u  /* strictly in-place hand-off between levels (Section 4.6): after a
+                                   level's cleanup every bucket's largest element is moved to its
+                                   first entry (ips4o_mark_bucket_max), and the next level is planned
+                                   from the buckets a walk over those marks finds with
+                                   searchNextLargest (ips4o_search_next_largest), not from the
+                                   partition's own boundaries.  Equality buckets are not known to
+                                   the walk: one larger than the base-case capacity is partitioned
+                                   once more and found to hold one key value.  Requires k >= 4;
+                                   same results, slower (a read pass and a walk per level, and the
+                                   next level is planned only after the cleanup) */
 
 typedef struct ips4o_handle ips4o_handle;
 
@@ -298,6 +308,31 @@ int ips4o_check_args(const void *d_data, uint64_t n, int dtype, const ips4o_para
 int ips4o_check_segments(const void *d_data, int dtype, const uint64_t *h_offsets, uint32_t num_segments,
                          const ips4o_params *params);
 
+/* The marking the strictly in-place recursion needs from a partition
+ * (Section 4.6, From Almost In-Place to Strictly In-Place): for every bucket
+ * b < num_buckets, elements [d_bounds[b], d_bounds[b+1]) of d_data, the first
+ * element with the largest key of the bucket trades places with the
+ * bucket's first element (buckets of fewer than two elements are left
+ * alone).  d_bounds: device pointer to num_buckets + 1 positions (8-byte
+ * aligned), non-decreasing and at most n; others are skipped and reported
+ * as IPS4O_ERR_DEVICE_FAULT with fault bit 256.  Waits for the stream.
+ * Buckets may be in any order and need not cover the array. */
+int ips4o_mark_bucket_max(ips4o_handle *h, void *d_data, uint64_t n, int dtype, const uint64_t *d_bounds,
+                          uint32_t num_buckets, void *hip_stream);
+
+/* searchNextLargest (Section 4.6) for `count` positions: d_out[q] = the first
+ * position j > d_pos[q], j < n, whose key is larger than the key of
+ * d_data[d_pos[q]], or n if there is none (also for d_pos[q] >= n).  Each
+ * query is an exponential search followed by a 64-way search, which finds
+ * that first position whenever the positions after d_pos[q] holding larger
+ * keys form a suffix of [d_pos[q]+1, n), as after a partition marked by
+ * ips4o_mark_bucket_max when d_pos[q] is a bucket's first entry; for other
+ * inputs the result is some position in (d_pos[q], n] whose key is larger
+ * (or n).  d_pos, d_out: device pointers to `count` uint64 (8-byte aligned).
+ * Reads only d_data[0, n).  Waits for the stream. */
+int ips4o_search_next_largest(ips4o_handle *h, const void *d_data, uint64_t n, int dtype, const uint64_t *d_pos,
+                              uint64_t count, uint64_t *d_out, void *hip_stream);
+
 /* The checks ips4o_distribute and ips4o_classify apply to caller-given
  * splitters (host pointer to num_splitters elements of `dtype`): count in
  * [1, 511], keys non-decreasing, equality_buckets 0 or 1. */
@@ -319,7 +354,10 @@ const char *ips4o_status_string(int status);
  *                  disagreed; with IPS4O_FLAG_CHECK also 16 a full block
  *                  mixed buckets, 32 recounted buckets differed, 64 a placed
  *                  block held another bucket; 128 ips4o_sort_segmented_small got a
- *                  segment above the capacity or decreasing offsets
+ *                  segment above the capacity or decreasing offsets; 256
+ *                  bucket bounds out of range (ips4o_mark_bucket_max), or a
+ *                  strictly in-place walk found more buckets than the
+ *                  partition made
  *   block_moves    blocks written by the permutations (all levels)
  *   block_skips    blocks found already in place and left there
  *   elements_base  elements sorted by the base case
@@ -339,11 +377,12 @@ int ips4o_last_stats(const ips4o_handle *h, ips4o_stats *out);
  * made with IPS4O_FLAG_TIMING (zeros otherwise), from HIP events recorded
  * around each launch on the call's stream.  out[] has IPS4O_KERNEL_KINDS
  * entries in this order: sample, classify, scan, fix_empty, permute,
- * cleanup, basecase.  alg_bytes is the data the launches had to move by the
+ * cleanup, basecase, mark (the bucket maxima and the walk of
+ * IPS4O_FLAG_STRICT).  alg_bytes is the data the launches had to move by the
  * method's definition: 2*s per element classified, per element of a moved
  * block (permutation and empty-block fix), per element placed by cleanup and
- * per element sorted by the base case. */
-#define IPS4O_KERNEL_KINDS 7
+ * per element sorted by the base case; s per element marked. */
+#define IPS4O_KERNEL_KINDS 8
 typedef struct {
     uint32_t launches;
     uint32_t reserved;

@@ -27,6 +27,7 @@ DTYPES = {"u64": U64, "f64": F64, "pair": PAIR, "quartet": QUARTET, "bytes100": 
 ELEM_BYTES = {U64: 8, F64: 8, PAIR: 16, QUARTET: 32, BYTES100: 100}
 FLAG_NO_SKIP = 1
 FLAG_FUSE = 8            # base-case kernels clean the buckets of their bins (off by default)
+FLAG_STRICT = 16         # levels hand over through bucket maxima and searchNextLargest (Section 4.6)
 DEFAULT_K = 256          # first-level buckets when params leave k at 0 ...
 DEFAULT_K_SMALL = 128    # ... for arrays of fewer than 2^27 elements
 
@@ -43,7 +44,7 @@ EXPORTS = ["ips4o_create", "ips4o_destroy", "ips4o_workspace_bytes", "ips4o_work
            "ips4o_sort_segmented_small", "ips4o_set_default_params",
            "ips4o_sort_segmented", "ips4o_distribute", "ips4o_classify", "ips4o_select_splitters",
            "ips4o_sync", "ips4o_status_string", "ips4o_last_stats", "ips4o_last_kernel_stats",
-           "ips4o_last_pass_stats",
+           "ips4o_last_pass_stats", "ips4o_mark_bucket_max", "ips4o_search_next_largest",
            "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments"]
 
 
@@ -67,7 +68,7 @@ class Stats(ctypes.Structure):
                 ("elements_base", ctypes.c_uint64), ("elements_distributed", ctypes.c_uint64)]
 
 
-KERNEL_KINDS = ["sample", "classify", "scan", "fix_empty", "permute", "cleanup", "basecase"]
+KERNEL_KINDS = ["sample", "classify", "scan", "fix_empty", "permute", "cleanup", "basecase", "mark"]
 FLAG_TIMING = 2
 
 
@@ -106,6 +107,8 @@ def _load():
     L.ips4o_classify.argtypes = [vp, vp, u64, i32, vp, u32, i32, vp, vp]
     L.ips4o_select_splitters.argtypes = [vp, vp, u64, i32, ctypes.POINTER(Params), vp,
                                          ctypes.POINTER(u32), ctypes.POINTER(i32), vp]
+    L.ips4o_mark_bucket_max.argtypes = [vp, vp, u64, i32, vp, u32, vp]
+    L.ips4o_search_next_largest.argtypes = [vp, vp, u64, i32, vp, u64, vp, vp]
     L.ips4o_check_args.argtypes = [vp, u64, i32, ctypes.POINTER(Params)]
     L.ips4o_check_splitters.argtypes = [vp, u32, i32, i32]
     L.ips4o_check_segments.argtypes = [vp, i32, vp, u32, ctypes.POINTER(Params)]
@@ -120,7 +123,8 @@ def _load():
                  "ips4o_set_default_params", "ips4o_sort", "ips4o_sort_segmented", "ips4o_distribute",
                  "ips4o_classify", "ips4o_select_splitters", "ips4o_sync", "ips4o_last_stats",
                  "ips4o_check_args", "ips4o_check_splitters", "ips4o_check_segments",
-                 "ips4o_last_kernel_stats", "ips4o_last_pass_stats"]:
+                 "ips4o_last_kernel_stats", "ips4o_last_pass_stats", "ips4o_mark_bucket_max",
+                 "ips4o_search_next_largest"]:
         getattr(L, name).restype = i32
     return L
 
@@ -312,6 +316,27 @@ def ips4o_classify(h, data, n, dtype, splitters: np.ndarray, equality_buckets: b
                               sp.shape[0], int(bool(equality_buckets)), _addr(out, 4 * n, "out"),
                               _stream(stream)),
            "ips4o_classify")
+
+
+def ips4o_mark_bucket_max(h, data, n, dtype, d_bounds, num_buckets, stream=None) -> None:
+    """Move the first largest element of every bucket [d_bounds[b],
+    d_bounds[b+1]) to the bucket's first entry (Section 4.6); d_bounds: a
+    device tensor of num_buckets + 1 int64 positions."""
+    d = _dtype(dtype)
+    _check(_L().ips4o_mark_bucket_max(h, _addr(data, n * ELEM_BYTES[d]), n, d,
+                                      _addr(d_bounds, 8 * (num_buckets + 1), "bounds") if num_buckets else None,
+                                      num_buckets, _stream(stream)), "ips4o_mark_bucket_max", h)
+
+
+def ips4o_search_next_largest(h, data, n, dtype, d_pos, count, d_out, stream=None) -> None:
+    """d_out[q] = searchNextLargest from position d_pos[q] (Section 4.6): the
+    first later position in [0, n) holding a larger key, or n; d_pos, d_out:
+    device tensors of `count` int64."""
+    d = _dtype(dtype)
+    _check(_L().ips4o_search_next_largest(h, _addr(data, n * ELEM_BYTES[d]), n, d,
+                                          _addr(d_pos, 8 * count, "positions") if count else None, count,
+                                          _addr(d_out, 8 * count, "out") if count else None, _stream(stream)),
+           "ips4o_search_next_largest", h)
 
 
 def ips4o_select_splitters(h, data, n, dtype, params=None, stream=None, like: np.ndarray = None):

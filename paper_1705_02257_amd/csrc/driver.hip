@@ -144,7 +144,7 @@ struct Carve {  // sequential sub-allocation with 256-byte alignment
 
 }  // namespace
 
-enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_BASE, KK_N };
+enum { KK_SAMPLE = 0, KK_CLASSIFY, KK_SCAN, KK_FIX, KK_PERMUTE, KK_CLEANUP, KK_BASE, KK_MARK, KK_N };
 
 struct ips4o_handle {
     int device = 0;
@@ -289,6 +289,9 @@ int resolve(const ips4o_params* p, Resolved* r) {
     r->k = d.k ? d.k : kDefaultK;
     r->k_default = d.k == 0;
     if (r->k < 2 || r->k > (uint32_t)KT_MAX || (r->k & (r->k - 1))) return IPS4O_ERR_INVALID_ARG;
+    // the strict hand-off reads a partition into one bucket as one key
+    // value, which needs at least three buckets
+    if ((d.flags & IPS4O_FLAG_STRICT) && r->k < 4) return IPS4O_ERR_INVALID_ARG;
     uint32_t bb = d.block_bytes ? d.block_bytes : kDefaultBlockBytes;
     if (bb < s || bb > kMaxBlockBytes) return IPS4O_ERR_INVALID_ARG;
     // b = max(1, 2^floor(log2(block_bytes / s))) (Section 4, Implementation Details)
@@ -981,6 +984,31 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
     return launch_level_cleanup<DT>(L, st, tm, mk, &h->last_hip);
 }
 
+// Strictly in-place hand-off (Section 4.6): every bucket's largest element
+// moved to its first entry, then each task's bucket boundaries overwritten
+// by the ones a walk over those marks finds (k_walk), so that the next
+// level is planned from what the data holds.  `elems`: the level's elements
+// (read once by the marking).
+template <int DT>
+int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, hipError_t* herr) {
+    Ctx<DT>& c = L.c;
+    const uint32_t T = (uint32_t)L.tasks.size();
+    uint32_t kmax = 0;
+    for (const TaskD& t : L.tasks) kmax = std::max(kmax, t.kbuf);
+    const int r = tm.begin(KK_MARK);
+    for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
+        const uint32_t nt = std::min<uint32_t>(65535, T - t0);
+        hipLaunchKernelGGL((k_mark_max<DT, 1024>), dim3(std::max(kmax, 1u), nt), dim3(1024), 0, st, c.data,
+                           (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
+        if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
+    }
+    hipLaunchKernelGGL((k_walk<DT>), dim3((T + 3) / 4), dim3(256), 0, st, c.data, c.bounds, c.tasks, c.ts, T,
+                       c.err);
+    if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
+    tm.end(r, (double)sizeof(typename Traits<DT>::Elem) * (double)elems);
+    return IPS4O_OK;
+}
+
 template <int DT>
 int run_level(ips4o_handle* h, Level<DT>& L, hipStream_t st, const HostTree<DT>* given, Timer& tm,
               LevelMarks& mk, bool check) {
@@ -1314,7 +1342,9 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
     // base case that cleans the buckets of its bins (Section 4,
     // Implementation Details), on request
     constexpr bool plain = (DT == DT_U64 || DT == DT_F64);
-    const bool fuse = (R.flags & IPS4O_FLAG_FUSE) || fuse_on();
+    // strictly in-place hand-off between levels (Section 4.6)
+    const bool strict = (R.flags & IPS4O_FLAG_STRICT) != 0;
+    const bool fuse = !strict && ((R.flags & IPS4O_FLAG_FUSE) || fuse_on());
     std::vector<BinSrc> srcs, fs;
     std::vector<SegD> fb;
     uint64_t fused_elems = 0;          // elements of base-case launches made during the levels
@@ -1366,12 +1396,24 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
         rc = launch_level_head<DT>(h, L, st, nullptr, tm, check, par ? &h->hdesc2 : &h->hdesc);
         if (rc) return rc;
         t_head += since(th);
-        rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
-        if (rc) return rc;
+        if (!strict) {
+            rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
+            if (rc) return rc;
+        }
         // the cleanup waits for the bounds when the base case cleans the
         // buckets of the level's bins
         rc = launch_level_tail<DT>(h, L, st, tm, marks.back(), check, !fuse);
         if (rc) return rc;
+        if (strict) {
+            // the plan comes from the buckets the walk finds once the
+            // level is done, not from the partition's own bounds
+            uint64_t lm = 0;
+            for (const Seg& sg : cur) lm += sg.m;
+            rc = launch_mark_walk<DT>(L, st, tm, lm, &h->last_hip);
+            if (rc) return rc;
+            rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
+            if (rc) return rc;
+        }
         // the bins of the earlier levels follow on the stream: the device
         // sorts them while the host waits for this level's bounds and plans
         // from them
@@ -1411,9 +1453,14 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
                              level, t, (unsigned long long)td.off, (unsigned long long)td.m, td.k, td.alpha, K,
                              ts[t].eq, td.nstripes);
             uint64_t eb = 0;
+            // strictly in place: the walk's buckets carry no equality
+            // flags; a task left in one bucket holds one key value (with
+            // k >= 4 a partition of two or more distinct keys makes at
+            // least two buckets), which is sorted already
+            if (strict && K >= 1 && bd[0] == 0 && bd[1] == td.m) continue;
             if (K > (uint32_t)KMAX || K > td.kbuf ||
-                !split_task(td.off, td.m, cur[t].grp, K, ts[t].eq != 0, bd, R.cap, bin_cap, base, next, &eb, &srcs,
-                            (uint32_t)t)) {
+                !split_task(td.off, td.m, cur[t].grp, K, !strict && ts[t].eq != 0, bd, R.cap, bin_cap, base, next,
+                            &eb, &srcs, (uint32_t)t)) {
                 (void)check_device_error(h, st);
                 return IPS4O_ERR_DEVICE_FAULT;
             }
@@ -1949,6 +1996,31 @@ int run_sort_small_segments(ips4o_handle* h, void* d_data, const uint64_t* d_off
     return IPS4O_OK;
 }
 
+// The marking and the search of the strictly in-place recursion (Section
+// 4.6) on caller-given buckets and positions.
+template <int DT>
+int run_mark_bucket_max(ips4o_handle* h, void* d_data, uint64_t n, const uint64_t* d_bounds, uint32_t nb,
+                        hipStream_t st) {
+    int rc = reset_misc(h, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_mark_max<DT, 1024>), dim3(std::min<uint32_t>(nb, 1u << 20), 1), dim3(1024), 0, st,
+                       (typename Traits<DT>::Elem*)d_data, n, d_bounds, (const TaskD*)nullptr,
+                       (const TaskS*)nullptr, 0u, nb, (uint32_t*)h->misc.p);
+    HIP_TRY(hipGetLastError());
+    return check_device_error(h, st);
+}
+
+template <int DT>
+int run_search_next_largest(ips4o_handle* h, const void* d_data, uint64_t n, const uint64_t* d_pos,
+                            uint64_t count, uint64_t* d_out, hipStream_t st) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((count + 3) / 4, 1u << 16);
+    hipLaunchKernelGGL((k_search_next<DT>), dim3(grid), dim3(256), 0, st,
+                       (const typename Traits<DT>::Elem*)d_data, n, d_pos, count, d_out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return IPS4O_OK;
+}
+
 #define DISPATCH(dt, CALL)                                   \
     switch (dt) {                                            \
     case DT_U64: { constexpr int D = DT_U64; return CALL; }  \
@@ -2183,6 +2255,32 @@ int ips4o_classify(ips4o_handle* h, const void* d_data, uint64_t n, int dtype, c
     hipStream_t st = (hipStream_t)hip_stream;
     DISPATCH(dtype, run_classify<D>(h, d_data, n, h_splitters, num_splitters, equality_buckets,
                                     d_bucket_out, st));
+}
+
+int ips4o_mark_bucket_max(ips4o_handle* h, void* d_data, uint64_t n, int dtype, const uint64_t* d_bounds,
+                          uint32_t num_buckets, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, nullptr);
+    if (rc) return rc;
+    if (num_buckets == 0) return IPS4O_OK;
+    if (!d_bounds || ((uintptr_t)d_bounds & 7)) return IPS4O_ERR_INVALID_ARG;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_mark_bucket_max<D>(h, d_data, n, d_bounds, num_buckets, st));
+}
+
+int ips4o_search_next_largest(ips4o_handle* h, const void* d_data, uint64_t n, int dtype, const uint64_t* d_pos,
+                              uint64_t count, uint64_t* d_out, void* hip_stream) {
+    if (!h) return IPS4O_ERR_INVALID_ARG;
+    int rc = ips4o_check_args(d_data, n, dtype, nullptr);
+    if (rc) return rc;
+    if (count == 0) return IPS4O_OK;
+    if (!d_pos || !d_out || ((uintptr_t)d_pos & 7) || ((uintptr_t)d_out & 7)) return IPS4O_ERR_INVALID_ARG;
+    rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DISPATCH(dtype, run_search_next_largest<D>(h, d_data, n, d_pos, count, d_out, st));
 }
 
 int ips4o_select_splitters(ips4o_handle* h, const void* d_data, uint64_t n, int dtype,

@@ -137,7 +137,9 @@ enum ErrCode : uint32_t {
     ERR_CHECK_BLOCK = 16,   // a full block after classification mixes buckets
     ERR_CHECK_COUNT = 32,   // recounted buckets differ from the stored counts
     ERR_CHECK_PLACED = 64,  // after the permutation a block in [d_i, w_i) is not of bucket i
-    ERR_SEGMENT = 128       // a small-segment sort got a segment above the capacity, or decreasing offsets
+    ERR_SEGMENT = 128,      // a small-segment sort got a segment above the capacity, or decreasing offsets
+    ERR_MARKS = 256         // bucket bounds beyond the array or decreasing, or a walk over marked
+                            // buckets found more buckets than the partition made
 };
 
 __device__ inline void raise_err(uint32_t* err, uint32_t code) {
@@ -2511,6 +2513,200 @@ __global__ __launch_bounds__(NT) void k_bucket_ids(Ctx<DT> c, uint64_t n, uint32
         classify_lut_batch<Key, 1>(k, bk, spl, lut, P, st.nuniq, st.eq);
         out[i] = bk[0];
     }
+}
+
+// ------------------------------ strictly in-place recursion (Section 4.6)
+// The partition leaves the largest element of every bucket in the bucket's
+// first entry.  The end of a bucket is then the first later position that
+// holds a larger key: every later bucket of the partition, and every bucket
+// of an earlier level after it, holds only larger keys, so the positions
+// holding larger keys form a suffix and can be searched for.  The
+// recursion then needs no bucket boundaries beyond the partition that made
+// them.
+
+// The first position in [lo, hi) holding a key larger than piv, or hi
+// (searchNextLargest).  One wavefront; the exponential search probes its
+// 63 positions lo + 2^l - 1 at once, one per lane, and the bracket it finds
+// is narrowed by 64-way search, each round probing 64 evenly spaced
+// positions: about log_64 of the bucket size dependent loads instead of
+// 2 log_2.  The result is the first larger key whenever the larger keys
+// form a suffix of [lo, hi); otherwise some position in [lo, hi] whose key
+// is larger (or hi).  Only positions in [lo, hi) are read.  Every lane
+// returns the same value.
+template <int DT>
+__device__ inline uint64_t wave_next_larger(const typename Traits<DT>::Elem* data,
+                                            const typename Traits<DT>::Key& piv, uint64_t lo, uint64_t hi) {
+    using TR = Traits<DT>;
+    if (lo >= hi) return hi;
+    const uint32_t lane = lane_id();
+    const uint64_t len = hi - lo;
+    const bool in = lane < 63 && (1ull << lane) <= len;
+    bool big = false;
+    if (in) big = piv < TR::key(data[lo + (1ull << lane) - 1]);
+    const uint64_t mb = __ballot(big), mi = __ballot(in);
+    uint64_t below, above;
+    if (mb) {
+        const uint32_t f = (uint32_t)__builtin_ctzll(mb);
+        above = lo + (1ull << f) - 1;
+        below = f ? lo + (1ull << (f - 1)) : lo;      // probe f-1 held no larger key
+    } else {
+        const uint32_t l = 63u - (uint32_t)__builtin_clzll(mi);   // lane 0 is always in range
+        below = lo + (1ull << l);
+        above = hi;
+    }
+    // invariant: no larger key in [lo, below) at a probed position, and
+    // `above` is hi or holds a larger key; [below, above) shrinks each round
+    while (below < above) {
+        const uint64_t step = ((above - below) + 63) >> 6;
+        const uint64_t q = below + (uint64_t)lane * step;
+        const bool qin = q < above;
+        bool qb = false;
+        if (qin) qb = piv < TR::key(data[q]);
+        const uint64_t m2 = __ballot(qb);
+        if (m2) {
+            const uint32_t f = (uint32_t)__builtin_ctzll(m2);
+            const uint64_t nb = f ? below + (uint64_t)(f - 1) * step + 1 : below;
+            above = below + (uint64_t)f * step;
+            below = nb;
+        } else {
+            const uint32_t last = (uint32_t)__builtin_popcountll(__ballot(qin)) - 1;
+            below = below + (uint64_t)last * step + 1;
+        }
+    }
+    return above;
+}
+
+// The marking the partition owes (Section 4.6): in bucket j the first
+// element with the largest key trades places with the bucket's first
+// element.  One workgroup per bucket (grid x, strided over the buckets);
+// grid y: the tasks of a level from t0, bounds relative to the task's
+// offset (equality buckets, which hold one key, are left alone); with
+// tasks == nullptr one list of nb buckets whose bounds[0..nb] are
+// positions in [0, n).
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data, uint64_t n,
+                                                 const uint64_t* bounds, const TaskD* tasks, const TaskS* ts,
+                                                 uint32_t t0, uint32_t nb, uint32_t* err) {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    using Elem = typename TR::Elem;
+    __shared__ Key sk[NT];
+    __shared__ uint64_t sp[NT];
+    const uint32_t t = t0 + blockIdx.y;
+    uint64_t off = 0, end = n;
+    const uint64_t* bd = bounds;
+    uint32_t K = nb;
+    bool eq = false;
+    if (tasks) {
+        const TaskD td = tasks[t];
+        off = td.off;
+        end = td.off + td.m;
+        bd = bounds + td.slot_begin + t;
+        K = ts[t].K;
+        eq = ts[t].eq != 0;
+    }
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t j = blockIdx.x; j < K; j += gridDim.x) {
+        if (eq && (j & 1)) continue;
+        const uint64_t lo = off + bd[j], hi = off + bd[j + 1];
+        if (hi < lo || hi > end) {
+            if (tid == 0) raise_err(err, ERR_MARKS);
+            continue;
+        }
+        if (hi - lo < 2) continue;
+        Key bk = TR::key(data[lo]);
+        uint64_t bp = lo;
+        uint64_t p = lo + tid;
+        for (; p + 3 * NT < hi; p += 4 * NT) {
+            Key kq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (bk < kq[u]) {
+                    bk = kq[u];
+                    bp = p + (uint64_t)u * NT;
+                }
+        }
+        for (; p < hi; p += NT) {
+            const Key kk = TR::key(data[p]);
+            if (bk < kk) {
+                bk = kk;
+                bp = p;
+            }
+        }
+        // each thread saw its positions in increasing order and kept the
+        // first of its largest keys; the reduction keeps the smallest position
+        sk[tid] = bk;
+        sp[tid] = bp;
+        __syncthreads();
+        for (uint32_t s = NT / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const Key ko = sk[tid + s];
+                const uint64_t po = sp[tid + s];
+                if (sk[tid] < ko || (ko == sk[tid] && po < sp[tid])) {
+                    sk[tid] = ko;
+                    sp[tid] = po;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && sp[0] != lo) {
+            const Elem a = data[lo];
+            data[lo] = data[sp[0]];
+            data[sp[0]] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// searchNextLargest for caller-given positions: out[q] = the first position
+// after pos[q] in [0, n) holding a larger key than data[pos[q]], or n (also
+// for pos[q] >= n).  One wavefront per query.
+template <int DT>
+__global__ __launch_bounds__(256) void k_search_next(const typename Traits<DT>::Elem* data, uint64_t n,
+                                                     const uint64_t* pos, uint64_t count, uint64_t* out) {
+    using TR = Traits<DT>;
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    for (uint64_t q = (uint64_t)blockIdx.x * 4 + threadIdx.x / 64; q < count; q += waves) {
+        const uint64_t i = pos[q];
+        uint64_t j = n;
+        if (i < n) j = wave_next_larger<DT>(data, TR::key(data[i]), i + 1, n);
+        if (lane_id() == 0) out[q] = j;
+    }
+}
+
+// The buckets of each task of a level found again from the data alone, after
+// k_mark_max: from the task's first element on, each bucket ends where the
+// next larger key begins (the recursion of Section 4.6, without its
+// sequential order: one wavefront per task).  The bucket boundaries
+// overwrite the task's bounds[0..K] (relative to its offset): the c
+// non-empty buckets found, then the task's end repeated (empty buckets).
+// More buckets than the partition made means the marks are missing.
+template <int DT>
+__global__ __launch_bounds__(256) void k_walk(const typename Traits<DT>::Elem* data, uint64_t* bounds,
+                                              const TaskD* tasks, const TaskS* ts, uint32_t ntasks,
+                                              uint32_t* err) {
+    using TR = Traits<DT>;
+    const uint32_t t = blockIdx.x * 4 + threadIdx.x / 64;
+    if (t >= ntasks) return;
+    const uint32_t lane = lane_id();
+    const TaskD td = tasks[t];
+    const uint32_t K = ts[t].K;
+    uint64_t* bd = bounds + td.slot_begin + t;
+    const uint64_t hi = td.off + td.m;
+    uint64_t i = td.off;
+    uint32_t c = 0;
+    while (i < hi) {
+        if (c >= K) {
+            if (lane == 0) raise_err(err, ERR_MARKS);
+            return;
+        }
+        if (lane == 0) bd[c] = i - td.off;
+        i = wave_next_larger<DT>(data, TR::key(data[i]), i + 1, hi);
+        ++c;
+    }
+    for (uint32_t q = c + lane; q <= K; q += 64) bd[q] = td.m;
 }
 
 }  // namespace ips4o

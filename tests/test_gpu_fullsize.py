@@ -142,6 +142,29 @@ def test_sort_2pow30_fused_cleanup(env, dist):
     assert at is None, f"{dist}: first difference at {at}: GPU {int(out[at]):#x}, oracle {int(want[at]):#x}"
 
 
+@pytest.mark.parametrize("dist", ["reverse", "eightdup"])
+def test_sort_2pow30_strict(env, dist):
+    """2^30 u64 keys with IPS4O_FLAG_STRICT (each level planned from the
+    buckets a walk over the bucket maxima finds, Section 4.6): equal element
+    by element to the oracle's sorted arrangement.  EightDup leaves equality
+    buckets above the base-case capacity, which the walk cannot tell apart:
+    they are partitioned once more and found to hold one key."""
+    torch, ips, h = env
+    seed = workloads.seed_for(1, dist, "u64")
+    print(f"[gpu] strict sort u64 {dist} n=2^30 seed={seed:#x}", flush=True)
+    inp = workloads.generate(dist, "u64", N30, seed)
+    d = torch.from_numpy(inp.view(np.int64)).to("cuda:0")
+    del inp
+    ips.ips4o_sort(h, d, N30, "u64", {"flags": ips.FLAG_STRICT})
+    torch.cuda.synchronize()
+    out = d.cpu().numpy().view(np.uint64)
+    del d
+    torch.cuda.empty_cache()
+    want = oracle.expected_sorted(dist, "u64", N30, seed).view(np.uint64)
+    at = first_difference(out, want)
+    assert at is None, f"{dist}: first difference at {at}: GPU {int(out[at]):#x}, oracle {int(want[at]):#x}"
+
+
 N32 = 1 << 32
 
 

@@ -994,12 +994,23 @@ int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, hi
     Ctx<DT>& c = L.c;
     const uint32_t T = (uint32_t)L.tasks.size();
     uint32_t kmax = 0;
-    for (const TaskD& t : L.tasks) kmax = std::max(kmax, t.kbuf);
+    uint64_t ksum = 0;
+    for (const TaskD& t : L.tasks) {
+        kmax = std::max(kmax, t.kbuf);
+        ksum += t.k;
+    }
+    // a workgroup per bucket: 1024 lanes for buckets of a million elements
+    // and more (the top level), 256 where there are many small ones
+    const bool wide = elems / std::max<uint64_t>(ksum, 1) >= (1u << 20);
     const int r = tm.begin(KK_MARK);
     for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
         const uint32_t nt = std::min<uint32_t>(65535, T - t0);
-        hipLaunchKernelGGL((k_mark_max<DT, 1024>), dim3(std::max(kmax, 1u), nt), dim3(1024), 0, st, c.data,
-                           (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
+        if (wide)
+            hipLaunchKernelGGL((k_mark_max<DT, 1024>), dim3(std::max(kmax, 1u), nt), dim3(1024), 0, st, c.data,
+                               (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
+        else
+            hipLaunchKernelGGL((k_mark_max<DT, 256>), dim3(std::max(kmax, 1u), nt), dim3(256), 0, st, c.data,
+                               (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
         if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
     }
     hipLaunchKernelGGL((k_walk<DT>), dim3((T + 3) / 4), dim3(256), 0, st, c.data, c.bounds, c.tasks, c.ts, T,

@@ -2576,13 +2576,32 @@ __device__ inline uint64_t wave_next_larger(const typename Traits<DT>::Elem* dat
     return above;
 }
 
+// Wavefront exchange of a key (every word of it) with lane ^ d.
+__device__ inline Key1 shfl_xor_key(const Key1& k, int d) { return Key1{(uint64_t)__shfl_xor(k.v, d, 64)}; }
+__device__ inline Key3 shfl_xor_key(const Key3& k, int d) {
+    return Key3{(uint64_t)__shfl_xor(k.a, d, 64), (uint64_t)__shfl_xor(k.b, d, 64), (uint64_t)__shfl_xor(k.c, d, 64)};
+}
+__device__ inline Key10 shfl_xor_key(const Key10& k, int d) {
+    return Key10{(uint64_t)__shfl_xor(k.hi, d, 64), (uint32_t)__shfl_xor((int)k.lo, d, 64), 0u};
+}
+
+// (key, position) of the largest key, the smaller position among equal keys
+template <typename Key>
+__device__ inline void keep_max(Key& bk, uint64_t& bp, const Key& k, uint64_t p) {
+    if (bk < k || (k == bk && p < bp)) {
+        bk = k;
+        bp = p;
+    }
+}
+
 // The marking the partition owes (Section 4.6): in bucket j the first
 // element with the largest key trades places with the bucket's first
 // element.  One workgroup per bucket (grid x, strided over the buckets);
 // grid y: the tasks of a level from t0, bounds relative to the task's
 // offset (equality buckets, which hold one key, are left alone); with
 // tasks == nullptr one list of nb buckets whose bounds[0..nb] are
-// positions in [0, n).
+// positions in [0, n).  Each lane keeps eight loads in flight; the lanes'
+// maxima meet by wavefront exchanges, then across the waves in LDS.
 template <int DT, int NT>
 __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data, uint64_t n,
                                                  const uint64_t* bounds, const TaskD* tasks, const TaskS* ts,
@@ -2590,8 +2609,10 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
     using TR = Traits<DT>;
     using Key = typename TR::Key;
     using Elem = typename TR::Elem;
-    __shared__ Key sk[NT];
-    __shared__ uint64_t sp[NT];
+    constexpr int W = NT / 64;
+    constexpr int U = 8;
+    __shared__ Key sk[W];
+    __shared__ uint64_t sp[W];
     const uint32_t t = t0 + blockIdx.y;
     uint64_t off = 0, end = n;
     const uint64_t* bd = bounds;
@@ -2605,7 +2626,7 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
         K = ts[t].K;
         eq = ts[t].eq != 0;
     }
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, wave = tid / 64;
     for (uint32_t j = blockIdx.x; j < K; j += gridDim.x) {
         if (eq && (j & 1)) continue;
         const uint64_t lo = off + bd[j], hi = off + bd[j + 1];
@@ -2617,44 +2638,31 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
         Key bk = TR::key(data[lo]);
         uint64_t bp = lo;
         uint64_t p = lo + tid;
-        for (; p + 3 * NT < hi; p += 4 * NT) {
-            Key kq[4];
+        for (; p + (U - 1) * NT < hi; p += U * NT) {
+            Key kq[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
+            for (int u = 0; u < U; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (bk < kq[u]) {
-                    bk = kq[u];
-                    bp = p + (uint64_t)u * NT;
-                }
+            for (int u = 0; u < U; ++u) keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
         }
-        for (; p < hi; p += NT) {
-            const Key kk = TR::key(data[p]);
-            if (bk < kk) {
-                bk = kk;
-                bp = p;
-            }
+        for (; p < hi; p += NT) keep_max(bk, bp, TR::key(data[p]), p);
+        for (int d = 32; d >= 1; d >>= 1) {
+            const Key ko = shfl_xor_key(bk, d);
+            const uint64_t po = (uint64_t)__shfl_xor(bp, d, 64);
+            keep_max(bk, bp, ko, po);
         }
-        // each thread saw its positions in increasing order and kept the
-        // first of its largest keys; the reduction keeps the smallest position
-        sk[tid] = bk;
-        sp[tid] = bp;
+        if (lane_id() == 0) {
+            sk[wave] = bk;
+            sp[wave] = bp;
+        }
         __syncthreads();
-        for (uint32_t s = NT / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                const Key ko = sk[tid + s];
-                const uint64_t po = sp[tid + s];
-                if (sk[tid] < ko || (ko == sk[tid] && po < sp[tid])) {
-                    sk[tid] = ko;
-                    sp[tid] = po;
-                }
+        if (tid == 0) {
+            for (int w = 1; w < W; ++w) keep_max(bk, bp, sk[w], sp[w]);
+            if (bp != lo) {
+                const Elem a = data[lo];
+                data[lo] = data[bp];
+                data[bp] = a;
             }
-            __syncthreads();
-        }
-        if (tid == 0 && sp[0] != lo) {
-            const Elem a = data[lo];
-            data[lo] = data[sp[0]];
-            data[sp[0]] = a;
         }
         __syncthreads();
     }

@@ -49,7 +49,8 @@ KERNEL_SOURCES = [os.path.join(HERE, "csrc", f)
 # cleanup; the counting sort and its merge-sort fallback)
 KINDS = [("k_sample", "sample"), ("k_classify", "classify"), ("k_scan", "scan"),
          ("k_fix_empty", "fix_empty"), ("k_permute", "permute"), ("k_overhang", "cleanup"),
-         ("k_cleanup", "cleanup"), ("k_basecase", "basecase")]
+         ("k_cleanup", "cleanup"), ("k_basecase", "basecase"), ("k_mark_max", "mark"), ("k_walk", "mark"),
+         ("k_search_next", "mark")]
 COPY = "__amd_rocclr_copyBuffer"
 
 

@@ -999,18 +999,32 @@ int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, hi
         kmax = std::max(kmax, t.kbuf);
         ksum += t.k;
     }
-    // a workgroup per bucket: 1024 lanes for buckets of a million elements
-    // and more (the top level), 256 where there are many small ones
-    const bool wide = elems / std::max<uint64_t>(ksum, 1) >= (1u << 20);
+    // a workgroup per bucket where buckets are small; buckets of a million
+    // elements and more (the top level) are cut into parts of about 2^18
+    // elements whose maxima go to the stripe buffers, free once the cleanup
+    // has run (the next level's classification fills them after the walk)
+    using Key = typename Traits<DT>::Key;
+    const uint64_t avg = elems / std::max<uint64_t>(ksum, 1);
+    const uint32_t P = (uint32_t)std::min<uint64_t>(64, (avg + (1u << 18) - 1) >> 18);
+    const size_t part_key_bytes = ((size_t)L.total_slots * P * sizeof(Key) + 255) & ~(size_t)255;
+    const bool parts = avg >= (1u << 20) &&
+                       part_key_bytes + (size_t)L.total_slots * P * sizeof(uint64_t) <=
+                           (size_t)L.total_buf * sizeof(typename Traits<DT>::Elem);
+    Key* pk = (Key*)c.bufs;
+    uint64_t* pp = (uint64_t*)((char*)c.bufs + part_key_bytes);
     const int r = tm.begin(KK_MARK);
     for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
         const uint32_t nt = std::min<uint32_t>(65535, T - t0);
-        if (wide)
-            hipLaunchKernelGGL((k_mark_max<DT, 1024>), dim3(std::max(kmax, 1u), nt), dim3(1024), 0, st, c.data,
-                               (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
-        else
+        if (parts) {
+            hipLaunchKernelGGL((k_mark_part<DT, 256>), dim3(kmax * P, nt), dim3(256), 0, st, c.data, c.bounds,
+                               c.tasks, c.ts, t0, P, pk, pp, c.err);
+            if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
+            hipLaunchKernelGGL((k_mark_pick<DT>), dim3((kmax + 255) / 256, nt), dim3(256), 0, st, c.data, c.bounds,
+                               c.tasks, c.ts, t0, P, pk, pp);
+        } else {
             hipLaunchKernelGGL((k_mark_max<DT, 256>), dim3(std::max(kmax, 1u), nt), dim3(256), 0, st, c.data,
                                (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
+        }
         if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
     }
     hipLaunchKernelGGL((k_walk<DT>), dim3((T + 3) / 4), dim3(256), 0, st, c.data, c.bounds, c.tasks, c.ts, T,

@@ -2524,55 +2524,122 @@ __global__ __launch_bounds__(NT) void k_bucket_ids(Ctx<DT> c, uint64_t n, uint32
 // recursion then needs no bucket boundaries beyond the partition that made
 // them.
 
+// Wavefront read of a key (every word of it) from lane `src`.
+__device__ inline Key1 shfl_key(const Key1& k, int src) { return Key1{(uint64_t)__shfl(k.v, src, 64)}; }
+__device__ inline Key3 shfl_key(const Key3& k, int src) {
+    return Key3{(uint64_t)__shfl(k.a, src, 64), (uint64_t)__shfl(k.b, src, 64), (uint64_t)__shfl(k.c, src, 64)};
+}
+__device__ inline Key10 shfl_key(const Key10& k, int src) {
+    return Key10{(uint64_t)__shfl(k.hi, src, 64), (uint32_t)__shfl((int)k.lo, src, 64), 0u};
+}
+
 // The first position in [lo, hi) holding a key larger than piv, or hi
-// (searchNextLargest).  One wavefront; the exponential search probes its
-// 63 positions lo + 2^l - 1 at once, one per lane, and the bracket it finds
-// is narrowed by 64-way search, each round probing 64 evenly spaced
-// positions: about log_64 of the bucket size dependent loads instead of
-// 2 log_2.  The result is the first larger key whenever the larger keys
-// form a suffix of [lo, hi); otherwise some position in [lo, hi] whose key
-// is larger (or hi).  Only positions in [lo, hi) are read.  Every lane
-// returns the same value.
+// (searchNextLargest).  One wavefront.  The first round is the exponential
+// search's probes lo + 2^l - 1, all at once, one per lane; given a guess g
+// of the answer's distance from lo (the previous bucket's length, in a walk
+// over buckets of similar size), half of the lanes probe the exponential
+// positions and the other half a window of 32 evenly spaced positions
+// around lo + g, and the answer lies in both brackets.  The bracket is then
+// narrowed by 64-way search, each round probing 64 evenly spaced positions:
+// about log_64 of the bucket size dependent loads instead of 2 log_2, one
+// round fewer when the guess is close.  The result is the first larger key
+// whenever the larger keys form a suffix of [lo, hi); otherwise some
+// position in [lo, hi] whose key is larger (or hi).  Only positions in
+// [lo, hi) are read.  Every lane returns the same value, and *found receives
+// the key at the returned position when it is below hi (the probe that
+// found it loaded it).
 template <int DT>
 __device__ inline uint64_t wave_next_larger(const typename Traits<DT>::Elem* data,
-                                            const typename Traits<DT>::Key& piv, uint64_t lo, uint64_t hi) {
+                                            const typename Traits<DT>::Key& piv, uint64_t lo, uint64_t hi,
+                                            typename Traits<DT>::Key* found = nullptr, uint64_t guess = 0) {
     using TR = Traits<DT>;
+    using Key = typename TR::Key;
     if (lo >= hi) return hi;
     const uint32_t lane = lane_id();
     const uint64_t len = hi - lo;
-    const bool in = lane < 63 && (1ull << lane) <= len;
-    bool big = false;
-    if (in) big = piv < TR::key(data[lo + (1ull << lane) - 1]);
-    const uint64_t mb = __ballot(big), mi = __ballot(in);
-    uint64_t below, above;
-    if (mb) {
-        const uint32_t f = (uint32_t)__builtin_ctzll(mb);
-        above = lo + (1ull << f) - 1;
-        below = f ? lo + (1ull << (f - 1)) : lo;      // probe f-1 held no larger key
+    // lanes [0, ne) probe lo + 2^lane - 1; with a guess, lanes 32.. probe
+    // lo + w0 + (lane - 32) * ws
+    const uint32_t ne = guess ? 32u : 63u;
+    const uint64_t ws = guess / 16 ? guess / 16 : 1;
+    const uint64_t w0 = guess > 16 * ws ? guess - 16 * ws : 0;
+    bool in;
+    uint64_t pos;
+    if (lane < ne) {
+        in = (1ull << lane) <= len;
+        pos = lo + (1ull << lane) - 1;
     } else {
-        const uint32_t l = 63u - (uint32_t)__builtin_clzll(mi);   // lane 0 is always in range
-        below = lo + (1ull << l);
-        above = hi;
+        const uint64_t o = w0 + (uint64_t)(lane - 32) * ws;
+        in = guess != 0 && o < len;
+        pos = lo + o;
     }
+    Key k{};
+    bool big = false;
+    if (in) {
+        k = TR::key(data[pos]);
+        big = piv < k;
+    }
+    const uint64_t mb = __ballot(big), mi = __ballot(in);
+    const uint64_t lowm = ne == 63u ? ~0ull : 0xffffffffull;
+    uint64_t below, above;
+    int src = -1;
+    {
+        const uint64_t b = mb & lowm, i = mi & lowm;
+        if (b) {
+            const uint32_t f = (uint32_t)__builtin_ctzll(b);
+            above = lo + (1ull << f) - 1;
+            below = f ? lo + (1ull << (f - 1)) : lo;      // probe f-1 held no larger key
+            src = (int)f;
+        } else {
+            const uint32_t l = 63u - (uint32_t)__builtin_clzll(i);   // lane 0 is always in range
+            below = lo + (1ull << l);
+            above = hi;
+        }
+    }
+    if (ne == 32u) {
+        const uint64_t b = mb >> 32, i = mi >> 32;
+        if (b) {
+            const uint32_t f = (uint32_t)__builtin_ctzll(b);
+            const uint64_t a2 = lo + w0 + (uint64_t)f * ws;
+            const uint64_t b2 = f ? lo + w0 + (uint64_t)(f - 1) * ws + 1 : lo;
+            if (a2 < above) {
+                above = a2;
+                src = (int)(32 + f);
+            }
+            below = below > b2 ? below : b2;
+        } else if (i) {
+            const uint32_t l = 63u - (uint32_t)__builtin_clzll(i);
+            const uint64_t b2 = lo + w0 + (uint64_t)l * ws + 1;
+            below = below > b2 ? below : b2;
+        }
+    }
+    Key ak{};
+    if (src >= 0) ak = shfl_key(k, src);
     // invariant: no larger key in [lo, below) at a probed position, and
-    // `above` is hi or holds a larger key; [below, above) shrinks each round
+    // `above` is hi or holds a larger key (ak); [below, above) shrinks
+    // each round
     while (below < above) {
         const uint64_t step = ((above - below) + 63) >> 6;
         const uint64_t q = below + (uint64_t)lane * step;
         const bool qin = q < above;
         bool qb = false;
-        if (qin) qb = piv < TR::key(data[q]);
+        Key kq{};
+        if (qin) {
+            kq = TR::key(data[q]);
+            qb = piv < kq;
+        }
         const uint64_t m2 = __ballot(qb);
         if (m2) {
             const uint32_t f = (uint32_t)__builtin_ctzll(m2);
             const uint64_t nb = f ? below + (uint64_t)(f - 1) * step + 1 : below;
             above = below + (uint64_t)f * step;
             below = nb;
+            ak = shfl_key(kq, (int)f);
         } else {
             const uint32_t last = (uint32_t)__builtin_popcountll(__ballot(qin)) - 1;
             below = below + (uint64_t)last * step + 1;
         }
     }
+    if (found) *found = ak;
     return above;
 }
 
@@ -2668,6 +2735,111 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
     }
 }
 
+// The same marking for buckets of millions of elements, in two steps: each
+// bucket is cut into P equal parts, one workgroup per part writes the part's
+// first largest key and its position to pk/pp[(slot_begin + j) * P + q]
+// (position ~0: an empty part, or a bucket left alone), then k_mark_pick
+// trades the bucket's first element with the largest of its parts' maxima.
+// One workgroup per bucket is bound by what one CU keeps in flight, and the
+// largest bucket sets the time; parts spread every bucket over the device.
+template <int DT, int NT>
+__global__ __launch_bounds__(NT) void k_mark_part(const typename Traits<DT>::Elem* data, const uint64_t* bounds,
+                                                  const TaskD* tasks, const TaskS* ts, uint32_t t0, uint32_t P,
+                                                  typename Traits<DT>::Key* pk, uint64_t* pp, uint32_t* err) {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    constexpr int W = NT / 64;
+    constexpr int U = 8;
+    __shared__ Key sk[W];
+    __shared__ uint64_t sp[W];
+    const uint32_t t = t0 + blockIdx.y;
+    const uint32_t j = blockIdx.x / P, q = blockIdx.x % P;
+    const TaskD td = tasks[t];
+    const TaskS st = ts[t];
+    if (j >= st.K) return;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t at = ((uint64_t)td.slot_begin + j) * P + q;
+    const uint64_t* bd = bounds + td.slot_begin + t;
+    const uint64_t lo = td.off + bd[j], hi = td.off + bd[j + 1];
+    if (hi < lo || hi > td.off + td.m) {
+        if (tid == 0) {
+            pp[at] = ~0ull;
+            if (q == 0) raise_err(err, ERR_MARKS);
+        }
+        return;
+    }
+    const uint64_t len = hi - lo, a = lo + len * q / P, b = lo + len * (q + 1) / P;
+    if ((st.eq && (j & 1)) || len < 2 || a == b) {
+        if (tid == 0) pp[at] = ~0ull;
+        return;
+    }
+    Key bk = TR::key(data[a]);
+    uint64_t bp = a;
+    uint64_t p = a + tid;
+    for (; p + (U - 1) * NT < b; p += U * NT) {
+        Key kq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
+    }
+    for (; p < b; p += NT) keep_max(bk, bp, TR::key(data[p]), p);
+    for (int d = 32; d >= 1; d >>= 1) {
+        const Key ko = shfl_xor_key(bk, d);
+        const uint64_t po = (uint64_t)__shfl_xor(bp, d, 64);
+        keep_max(bk, bp, ko, po);
+    }
+    if (lane_id() == 0) {
+        sk[tid / 64] = bk;
+        sp[tid / 64] = bp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < W; ++w) keep_max(bk, bp, sk[w], sp[w]);
+        pk[at] = bk;
+        pp[at] = bp;
+    }
+}
+
+// One lane per bucket: the largest of the parts' maxima (the first position
+// among equal keys; parts lie in position order) trades places with the
+// bucket's first element.
+template <int DT>
+__global__ __launch_bounds__(256) void k_mark_pick(typename Traits<DT>::Elem* data, const uint64_t* bounds,
+                                                   const TaskD* tasks, const TaskS* ts, uint32_t t0, uint32_t P,
+                                                   const typename Traits<DT>::Key* pk, const uint64_t* pp) {
+    using TR = Traits<DT>;
+    using Key = typename TR::Key;
+    using Elem = typename TR::Elem;
+    const uint32_t t = t0 + blockIdx.y;
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    const TaskD td = tasks[t];
+    if (j >= ts[t].K) return;
+    const uint64_t base = ((uint64_t)td.slot_begin + j) * P;
+    bool have = false;
+    Key bk{};
+    uint64_t bp = 0;
+    for (uint32_t q = 0; q < P; ++q) {
+        const uint64_t p = pp[base + q];
+        if (p == ~0ull) continue;
+        const Key k = pk[base + q];
+        if (!have) {
+            bk = k;
+            bp = p;
+            have = true;
+        } else {
+            keep_max(bk, bp, k, p);
+        }
+    }
+    if (!have) return;
+    const uint64_t lo = td.off + bounds[td.slot_begin + t + j];
+    if (bp != lo) {
+        const Elem e = data[lo];
+        data[lo] = data[bp];
+        data[bp] = e;
+    }
+}
+
 // searchNextLargest for caller-given positions: out[q] = the first position
 // after pos[q] in [0, n) holding a larger key than data[pos[q]], or n (also
 // for pos[q] >= n).  One wavefront per query.
@@ -2705,13 +2877,20 @@ __global__ __launch_bounds__(256) void k_walk(const typename Traits<DT>::Elem* d
     const uint64_t hi = td.off + td.m;
     uint64_t i = td.off;
     uint32_t c = 0;
+    // each search returns the key at the bucket start it finds, which is
+    // the next search's pivot, and the bucket's length guides the next
+    // search (the first one guesses the average)
+    typename TR::Key piv = TR::key(data[i]);
+    uint64_t guess = td.m / (K ? K : 1);
     while (i < hi) {
         if (c >= K) {
             if (lane == 0) raise_err(err, ERR_MARKS);
             return;
         }
         if (lane == 0) bd[c] = i - td.off;
-        i = wave_next_larger<DT>(data, TR::key(data[i]), i + 1, hi);
+        const uint64_t j = wave_next_larger<DT>(data, piv, i + 1, hi, &piv, guess ? guess - 1 : 0);
+        guess = j - i;
+        i = j;
         ++c;
     }
     for (uint32_t q = c + lane; q <= K; q += 64) bd[q] = td.m;

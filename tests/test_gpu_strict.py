@@ -137,3 +137,21 @@ def test_sort_strict_needs_four_buckets(env):
     d = torch.zeros(1 << 16, dtype=torch.int64, device="cuda:0")
     with pytest.raises(ips.Ips4oError):
         ips.ips4o_sort(h, d, 1 << 16, "u64", {"k": 2, "flags": ips.FLAG_STRICT})
+
+
+@pytest.mark.parametrize("dtype", ["u64", "f64", "pair"])
+@pytest.mark.parametrize("dist", ["uniform", "eightdup"])
+def test_sort_segmented_strict(env, dtype, dist):
+    """A segmented sort with the strictly in-place hand-off: every segment
+    above the base-case capacity is a subproblem of the top level, and its
+    buckets are found by walking the marks inside the segment only."""
+    from test_gpu_segmented import BASE_CAP, _layout, assert_segments_like_oracle, gpu_sort_segmented
+    cap = BASE_CAP[dtype]
+    sizes = [0, 1, 17, cap, cap + 1, 3 * cap + 7, 40 * cap + 3, 2, 9 * cap, 0]
+    sizes = list(np.random.default_rng(len(dtype) + len(dist)).permutation(sizes))
+    offs, n = _layout(sizes, lead=13, trail=29)
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(3, dist, dtype))
+    torch, ips, h = env
+    print(f"[gpu] strict segmented {dtype} {dist} n={n} segments={len(sizes)}", flush=True)
+    out = gpu_sort_segmented(env, inp, offs, dtype, {"flags": ips.FLAG_STRICT})
+    assert_segments_like_oracle(out, inp, offs, dtype)

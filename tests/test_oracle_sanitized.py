@@ -2,7 +2,7 @@
 code, gcc): a small C driver built together with oracle/oracle.c runs every
 entry point on all five element types at small and ragged sizes (empty
 arrays, empty segments, one splitter, duplicate splitters, k = 2 .. 1024
-trees) and checks the plain properties of each result; any out-of-bounds
+trees, empty and one-element buckets for the marking) and checks the plain properties of each result; any out-of-bounds
 access, overflow or misaligned load aborts the run."""
 import os
 import shutil
@@ -35,6 +35,11 @@ int or_select_splitters_capped(const void *data, uint64_t n, int dtype, uint32_t
 void or_tree(const uint64_t *s, uint32_t k, uint64_t *a);
 uint32_t or_tree_descend(const uint64_t *a, uint32_t k, uint64_t e);
 int or_sort_small_integers(void *data, uint64_t n, int dtype, uint64_t vmax, uint32_t *counts);
+int or_mark_bucket_max(void *data, int dtype, const uint64_t *bounds, uint32_t nb);
+uint64_t or_search_next_largest(const void *pivot, const void *data, uint64_t lo, uint64_t hi, int dtype,
+                                uint64_t *probes);
+int or_sort_strict(void *data, uint64_t n, int dtype, uint32_t k, uint32_t alpha, uint64_t n0, uint64_t seed,
+                   uint64_t *stats);
 
 static uint64_t st = 0x9E3779B97F4A7C15ull;
 static uint64_t rnd(void) { st ^= st << 13; st ^= st >> 7; st ^= st << 17; return st; }
@@ -138,6 +143,25 @@ int main(void) {
                 if (or_sort_small_integers(d, n, dt, vmax, cnt) != -2) FAIL("a bad key accepted");
             }
             free(d); free(cnt);
+        }
+    /* the strictly in-place recursion: marking, searchNextLargest, the loop */
+    for (int dt = 0; dt < 5; ++dt)
+        for (uint64_t n = 0; n < 300; n += 37) {
+            const size_t s = or_elem_size(dt);
+            unsigned char *d = malloc(n * s + 1);
+            for (uint64_t i = 0; i < n * s; ++i) d[i] = (unsigned char)(rnd() % 3);
+            uint64_t bd[6] = {0, n / 5, n / 5, n / 2, n - n / 7, n};
+            if (or_mark_bucket_max(d, dt, bd, 5) != 0) FAIL("or_mark_bucket_max");
+            for (int b = 0; b < 5; ++b)
+                for (uint64_t p = bd[b]; p < bd[b + 1]; ++p)
+                    if (or_compare(d + p * s, d + bd[b] * s, dt) > 0) FAIL("marked entry not the largest");
+            if (n > 1) {
+                uint64_t pr = 0, j = or_search_next_largest(d, d, 1, n, dt, &pr);
+                if (j < 1 || j > n) FAIL("or_search_next_largest range");
+            }
+            uint64_t stats[4];
+            if (or_sort_strict(d, n, dt, 4, 1, 3, 5, stats) != 0 || !sorted(d, n, s, dt)) FAIL("or_sort_strict");
+            free(d);
         }
     printf("ok\n");
     return 0;

@@ -142,25 +142,25 @@ def test_sort_2pow30_fused_cleanup(env, dist):
     assert at is None, f"{dist}: first difference at {at}: GPU {int(out[at]):#x}, oracle {int(want[at]):#x}"
 
 
-@pytest.mark.parametrize("dist", ["reverse", "eightdup"])
-def test_sort_2pow30_strict(env, dist):
-    """2^30 u64 keys with IPS4O_FLAG_STRICT (each level planned from the
-    buckets a walk over the bucket maxima finds, Section 4.6): equal element
-    by element to the oracle's sorted arrangement.  EightDup leaves equality
+@pytest.mark.parametrize("dist,dtype", [("reverse", "u64"), ("eightdup", "u64"), ("rootdup", "f64")])
+def test_sort_2pow30_strict(env, dist, dtype):
+    """2^30 keys with IPS4O_FLAG_STRICT (each level planned from the buckets
+    a walk over the bucket maxima finds, Section 4.6): equal element by
+    element to the oracle's sorted arrangement.  EightDup leaves equality
     buckets above the base-case capacity, which the walk cannot tell apart:
     they are partitioned once more and found to hold one key."""
     torch, ips, h = env
-    seed = workloads.seed_for(1, dist, "u64")
-    print(f"[gpu] strict sort u64 {dist} n=2^30 seed={seed:#x}", flush=True)
-    inp = workloads.generate(dist, "u64", N30, seed)
+    seed = workloads.seed_for(1, dist, dtype)
+    print(f"[gpu] strict sort {dtype} {dist} n=2^30 seed={seed:#x}", flush=True)
+    inp = workloads.generate(dist, dtype, N30, seed)
     d = torch.from_numpy(inp.view(np.int64)).to("cuda:0")
     del inp
-    ips.ips4o_sort(h, d, N30, "u64", {"flags": ips.FLAG_STRICT})
+    ips.ips4o_sort(h, d, N30, dtype, {"flags": ips.FLAG_STRICT})
     torch.cuda.synchronize()
     out = d.cpu().numpy().view(np.uint64)
     del d
     torch.cuda.empty_cache()
-    want = oracle.expected_sorted(dist, "u64", N30, seed).view(np.uint64)
+    want = oracle.expected_sorted(dist, dtype, N30, seed).view(np.uint64)
     at = first_difference(out, want)
     assert at is None, f"{dist}: first difference at {at}: GPU {int(out[at]):#x}, oracle {int(want[at]):#x}"
 
@@ -243,19 +243,21 @@ def rows_nondecreasing(torch, cols):
     return bool((less | eq).all())
 
 
-@pytest.mark.parametrize("dtype,dist", RECORD_CELLS)
-def test_sort_records_2pow28(env, dtype, dist):
+@pytest.mark.parametrize("dtype,dist,flags", [(t, d, 0) for t, d in RECORD_CELLS] +
+                         [("pair", "rootdup", 16), ("quartet", "uniform", 16)])
+def test_sort_records_2pow28(env, dtype, dist, flags):
     """2^28 records at their full size (Pair 4.3 GB, Quartet 8.6 GB, 100Bytes
     26.8 GB): keys in order, payloads a permutation of the indices, every
-    record intact."""
+    record intact; two cells also with the strictly in-place hand-off
+    (flags 16, IPS4O_FLAG_STRICT)."""
     torch, ips, h = env
     n = 1 << 28
     s = workloads.ELEM_BYTES[dtype]
     seed = workloads.seed_for(2, dist, dtype)
-    print(f"[gpu] sort {dtype} {dist} n=2^28 seed={seed:#x}", flush=True)
+    print(f"[gpu] sort {dtype} {dist} n=2^28 seed={seed:#x} flags={flags}", flush=True)
     d = upload_chunked(torch, dist, dtype, n, seed)
     d0 = d.clone()
-    ips.ips4o_sort(h, d, n, dtype)
+    ips.ips4o_sort(h, d, n, dtype, {"flags": flags})
     torch.cuda.synchronize()
     rows, rows0 = d.view(n, s), d0.view(n, s)
     seen = torch.zeros(n, dtype=torch.bool, device="cuda:0")

@@ -191,3 +191,34 @@ def test_sort_strict_rejects_two_way(oracle_mod):
     bucket, so the constant-range reading needs k >= 3."""
     with pytest.raises(ValueError):
         oracle_mod.sort_strict(np.arange(10, dtype=np.uint64), "u64", k=2)
+
+
+@pytest.mark.parametrize("k", [3, 4, 8])
+def test_partition_of_distinct_keys_makes_two_buckets(oracle_mod, k):
+    """The reading the loop's termination rests on: with k >= 3 buckets, a
+    range holding two or more distinct keys never falls into a single
+    bucket (splitters drawn from the range, duplicates switching equality
+    buckets on).  Brute force over small ranges of few key values, every
+    oversampling factor up to 3 and many sample streams."""
+    rng = np.random.default_rng(40 + k)
+    for trial in range(400):
+        n = int(rng.integers(2, 24))
+        a = rng.integers(0, int(rng.integers(2, 5)), n).astype(np.uint64)
+        if np.unique(a).shape[0] < 2:
+            continue
+        alpha = int(rng.integers(1, 4))
+        sp, eq = oracle_mod.select_splitters(a, "u64", k, alpha, int(rng.integers(0, 2**63)))
+        counts, _ = oracle_mod.bucket_bounds(a, sp, "u64", eq)
+        assert int((counts > 0).sum()) >= 2, (a.tolist(), sp.tolist(), eq)
+
+
+def test_two_way_partition_can_leave_one_bucket(oracle_mod):
+    """With k = 2 (one splitter) the same range can stay in one bucket,
+    which is why the constant-range reading needs k >= 3."""
+    a = np.array([1, 5, 5, 5], dtype=np.uint64)
+    found = False
+    for seed in range(200):
+        sp, eq = oracle_mod.select_splitters(a, "u64", 2, 1, seed)
+        counts, _ = oracle_mod.bucket_bounds(a, sp, "u64", eq)
+        found |= int((counts > 0).sum()) == 1
+    assert found

@@ -123,9 +123,11 @@ typedef struct {
                                    first entry (ips4o_mark_bucket_max), and the next level is planned
                                    from the buckets a walk over those marks finds with
                                    searchNextLargest (ips4o_search_next_largest), not from the
-                                   partition's own boundaries.  Equality buckets are not known to
-                                   the walk: one larger than the base-case capacity is partitioned
-                                   once more and found to hold one key value.  Requires k >= 4;
+                                   partition's own boundaries.  The walk does not know which
+                                   buckets were equality buckets: the sort's marking also moves each
+                                   bucket's smallest element to its last entry, and a bucket above
+                                   the base-case capacity whose two ends hold equal keys is taken as
+                                   one key value and not partitioned again.  Requires k >= 4;
                                    same results, slower (a read pass and a walk per level, and the
                                    next level is planned only after the cleanup) */
 

@@ -990,7 +990,7 @@ int launch_level_tail(ips4o_handle* h, Level<DT>& L, hipStream_t st, Timer& tm, 
 // level is planned from what the data holds.  `elems`: the level's elements
 // (read once by the marking).
 template <int DT>
-int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, hipError_t* herr) {
+int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, uint64_t cap, hipError_t* herr) {
     Ctx<DT>& c = L.c;
     const uint32_t T = (uint32_t)L.tasks.size();
     uint32_t kmax = 0;
@@ -1007,28 +1007,31 @@ int launch_mark_walk(Level<DT>& L, hipStream_t st, Timer& tm, uint64_t elems, hi
     const uint64_t avg = elems / std::max<uint64_t>(ksum, 1);
     const uint32_t P = (uint32_t)std::min<uint64_t>(64, (avg + (1u << 18) - 1) >> 18);
     const size_t part_key_bytes = ((size_t)L.total_slots * P * sizeof(Key) + 255) & ~(size_t)255;
-    const bool parts = avg >= (1u << 20) &&
-                       part_key_bytes + (size_t)L.total_slots * P * sizeof(uint64_t) <=
-                           (size_t)L.total_buf * sizeof(typename Traits<DT>::Elem);
+    const size_t part_pos_bytes = ((size_t)L.total_slots * P * sizeof(uint64_t) + 255) & ~(size_t)255;
+    const bool parts = avg >= (1u << 20) && 2 * (part_key_bytes + part_pos_bytes) <=
+                                                (size_t)L.total_buf * sizeof(typename Traits<DT>::Elem);
+    // maxima, their positions, minima, their positions
     Key* pk = (Key*)c.bufs;
     uint64_t* pp = (uint64_t*)((char*)c.bufs + part_key_bytes);
+    Key* qk = (Key*)((char*)pp + part_pos_bytes);
+    uint64_t* qp = (uint64_t*)((char*)qk + part_key_bytes);
     const int r = tm.begin(KK_MARK);
     for (uint32_t t0 = 0; t0 < T; t0 += 65535) {
         const uint32_t nt = std::min<uint32_t>(65535, T - t0);
         if (parts) {
-            hipLaunchKernelGGL((k_mark_part<DT, 256>), dim3(kmax * P, nt), dim3(256), 0, st, c.data, c.bounds,
-                               c.tasks, c.ts, t0, P, pk, pp, c.err);
+            hipLaunchKernelGGL((k_mark_part<DT, 256, true>), dim3(kmax * P, nt), dim3(256), 0, st, c.data,
+                               c.bounds, c.tasks, c.ts, t0, P, pk, pp, qk, qp, c.err);
             if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
-            hipLaunchKernelGGL((k_mark_pick<DT>), dim3((kmax + 255) / 256, nt), dim3(256), 0, st, c.data, c.bounds,
-                               c.tasks, c.ts, t0, P, pk, pp);
+            hipLaunchKernelGGL((k_mark_pick<DT, true>), dim3((kmax + 255) / 256, nt), dim3(256), 0, st, c.data,
+                               c.bounds, c.tasks, c.ts, t0, P, pk, pp, qk, qp);
         } else {
-            hipLaunchKernelGGL((k_mark_max<DT, 256>), dim3(std::max(kmax, 1u), nt), dim3(256), 0, st, c.data,
-                               (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
+            hipLaunchKernelGGL((k_mark_max<DT, 256, true>), dim3(std::max(kmax, 1u), nt), dim3(256), 0, st,
+                               c.data, (uint64_t)0, c.bounds, c.tasks, c.ts, t0, 0u, c.err);
         }
         if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
     }
-    hipLaunchKernelGGL((k_walk<DT>), dim3((T + 3) / 4), dim3(256), 0, st, c.data, c.bounds, c.tasks, c.ts, T,
-                       c.err);
+    hipLaunchKernelGGL((k_walk<DT, true>), dim3((T + 3) / 4), dim3(256), 0, st, c.data, c.bounds, c.tasks, c.ts,
+                       T, cap, c.err);
     if ((*herr = hipGetLastError()) != hipSuccess) return IPS4O_ERR_HIP;
     tm.end(r, (double)sizeof(typename Traits<DT>::Elem) * (double)elems);
     return IPS4O_OK;
@@ -1434,7 +1437,7 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
             // level is done, not from the partition's own bounds
             uint64_t lm = 0;
             for (const Seg& sg : cur) lm += sg.m;
-            rc = launch_mark_walk<DT>(L, st, tm, lm, &h->last_hip);
+            rc = launch_mark_walk<DT>(L, st, tm, lm, R.cap, &h->last_hip);
             if (rc) return rc;
             rc = enqueue_readback<DT>(h, L, rb, h->scanned[par], st);
             if (rc) return rc;
@@ -1469,6 +1472,8 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
         const size_t base_before = base.size();
         srcs.clear();
         const uint64_t bin_cap = std::min(R.cap, small_bin_cap<DT>());
+        std::vector<uint64_t> sb;      // a task's walked bounds without their flags (strict)
+        std::vector<uint8_t> sone;     // and which of its buckets hold one key value
         for (size_t t = 0; t < T; ++t) {
             const TaskD& td = L.tasks[t];
             const uint64_t* bd = bounds + td.slot_begin + t;
@@ -1481,14 +1486,35 @@ int run_sort_list_body(ips4o_handle* h, void* d_data, uint64_t n_end, std::vecto
             // strictly in place: the walk's buckets carry no equality
             // flags; a task left in one bucket holds one key value (with
             // k >= 4 a partition of two or more distinct keys makes at
-            // least two buckets), which is sorted already
-            if (strict && K >= 1 && bd[0] == 0 && bd[1] == td.m) continue;
+            // least two buckets), which is sorted already, and so does a
+            // bucket the walk found with equal keys at its two ends
+            const uint8_t* one = nullptr;
+            if (strict) {
+                if (K > (uint32_t)KMAX || K > td.kbuf) {
+                    (void)check_device_error(h, st);
+                    return IPS4O_ERR_DEVICE_FAULT;
+                }
+                sb.resize(K + 1);
+                sone.assign(K, 0);
+                for (uint32_t q = 0; q <= K; ++q) {
+                    sb[q] = bd[q] & ~kOneKeyBit;
+                    if (q < K) sone[q] = (bd[q] & kOneKeyBit) ? 1 : 0;
+                }
+                if (K >= 1 && sb[0] == 0 && sb[1] == td.m) continue;
+                bd = sb.data();
+                one = sone.data();
+            }
+            const size_t next_before = next.size();
             if (K > (uint32_t)KMAX || K > td.kbuf ||
                 !split_task(td.off, td.m, cur[t].grp, K, !strict && ts[t].eq != 0, bd, R.cap, bin_cap, base, next,
-                            &eb, &srcs, (uint32_t)t)) {
+                            &eb, &srcs, (uint32_t)t, one)) {
                 (void)check_device_error(h, st);
                 return IPS4O_ERR_DEVICE_FAULT;
             }
+            // the subproblems of a task whose keys repeat size their buffers
+            // for equality buckets (a hint of the task, not of its buckets)
+            if (strict && ts[t].eq)
+                for (size_t q = next_before; q < next.size(); ++q) next[q].dup = 1;
             h->last.elements_base += eb;
         }
         // the level's bins (but the ones one wave sorts) go to the fused

@@ -2661,25 +2661,58 @@ __device__ inline void keep_max(Key& bk, uint64_t& bp, const Key& k, uint64_t p)
     }
 }
 
+// (key, position) of the smallest key, the smaller position among equal keys
+template <typename Key>
+__device__ inline void keep_min(Key& bk, uint64_t& bp, const Key& k, uint64_t p) {
+    if (k < bk || (k == bk && p < bp)) {
+        bk = k;
+        bp = p;
+    }
+}
+
+// Bucket [lo, hi) of at least two elements: the element at pmax (holding
+// its largest key) trades places with the first; with MIN, then the
+// element holding its smallest key (pmin before the first exchange) with
+// the last, so that a bucket of one key value shows it at its two ends.
+// The first element keeps the largest key either way.
+template <int DT, bool MIN>
+__device__ inline void mark_ends(typename Traits<DT>::Elem* data, uint64_t lo, uint64_t hi, uint64_t pmax,
+                                 uint64_t pmin) {
+    using Elem = typename Traits<DT>::Elem;
+    if (pmax != lo) {
+        const Elem a = data[lo];
+        data[lo] = data[pmax];
+        data[pmax] = a;
+    }
+    if constexpr (MIN) {
+        if (pmin == lo) pmin = pmax;            // the first element went to pmax
+        if (pmin != lo && pmin != hi - 1) {
+            const Elem a = data[hi - 1];
+            data[hi - 1] = data[pmin];
+            data[pmin] = a;
+        }
+    }
+}
+
 // The marking the partition owes (Section 4.6): in bucket j the first
 // element with the largest key trades places with the bucket's first
-// element.  One workgroup per bucket (grid x, strided over the buckets);
+// element (with MIN, then the first with the smallest key with the last:
+// mark_ends).  One workgroup per bucket (grid x, strided over the buckets);
 // grid y: the tasks of a level from t0, bounds relative to the task's
 // offset (equality buckets, which hold one key, are left alone); with
 // tasks == nullptr one list of nb buckets whose bounds[0..nb] are
 // positions in [0, n).  Each lane keeps eight loads in flight; the lanes'
-// maxima meet by wavefront exchanges, then across the waves in LDS.
-template <int DT, int NT>
+// extremes meet by wavefront exchanges, then across the waves in LDS.
+template <int DT, int NT, bool MIN = false>
 __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data, uint64_t n,
                                                  const uint64_t* bounds, const TaskD* tasks, const TaskS* ts,
                                                  uint32_t t0, uint32_t nb, uint32_t* err) {
     using TR = Traits<DT>;
     using Key = typename TR::Key;
-    using Elem = typename TR::Elem;
     constexpr int W = NT / 64;
     constexpr int U = 8;
-    __shared__ Key sk[W];
-    __shared__ uint64_t sp[W];
+    __shared__ Key sk[W], sk2[W];
+    __shared__ uint64_t sp[W], sp2[W];
     const uint32_t t = t0 + blockIdx.y;
     uint64_t off = 0, end = n;
     const uint64_t* bd = bounds;
@@ -2702,34 +2735,47 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
             continue;
         }
         if (hi - lo < 2) continue;
-        Key bk = TR::key(data[lo]);
-        uint64_t bp = lo;
+        Key bk = TR::key(data[lo]), mk = bk;
+        uint64_t bp = lo, mp = lo;
         uint64_t p = lo + tid;
         for (; p + (U - 1) * NT < hi; p += U * NT) {
             Key kq[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
 #pragma unroll
-            for (int u = 0; u < U; ++u) keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
+            for (int u = 0; u < U; ++u) {
+                keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
+                if constexpr (MIN) keep_min(mk, mp, kq[u], p + (uint64_t)u * NT);
+            }
         }
-        for (; p < hi; p += NT) keep_max(bk, bp, TR::key(data[p]), p);
+        for (; p < hi; p += NT) {
+            const Key kk = TR::key(data[p]);
+            keep_max(bk, bp, kk, p);
+            if constexpr (MIN) keep_min(mk, mp, kk, p);
+        }
         for (int d = 32; d >= 1; d >>= 1) {
             const Key ko = shfl_xor_key(bk, d);
             const uint64_t po = (uint64_t)__shfl_xor(bp, d, 64);
             keep_max(bk, bp, ko, po);
+            if constexpr (MIN) {
+                const Key k2 = shfl_xor_key(mk, d);
+                const uint64_t p2 = (uint64_t)__shfl_xor(mp, d, 64);
+                keep_min(mk, mp, k2, p2);
+            }
         }
         if (lane_id() == 0) {
             sk[wave] = bk;
             sp[wave] = bp;
+            sk2[wave] = mk;
+            sp2[wave] = mp;
         }
         __syncthreads();
         if (tid == 0) {
-            for (int w = 1; w < W; ++w) keep_max(bk, bp, sk[w], sp[w]);
-            if (bp != lo) {
-                const Elem a = data[lo];
-                data[lo] = data[bp];
-                data[bp] = a;
+            for (int w = 1; w < W; ++w) {
+                keep_max(bk, bp, sk[w], sp[w]);
+                if constexpr (MIN) keep_min(mk, mp, sk2[w], sp2[w]);
             }
+            mark_ends<DT, MIN>(data, lo, hi, bp, mp);
         }
         __syncthreads();
     }
@@ -2738,20 +2784,22 @@ __global__ __launch_bounds__(NT) void k_mark_max(typename Traits<DT>::Elem* data
 // The same marking for buckets of millions of elements, in two steps: each
 // bucket is cut into P equal parts, one workgroup per part writes the part's
 // first largest key and its position to pk/pp[(slot_begin + j) * P + q]
-// (position ~0: an empty part, or a bucket left alone), then k_mark_pick
-// trades the bucket's first element with the largest of its parts' maxima.
-// One workgroup per bucket is bound by what one CU keeps in flight, and the
-// largest bucket sets the time; parts spread every bucket over the device.
-template <int DT, int NT>
+// (with MIN its first smallest to qk/qp at the same index; position ~0: an
+// empty part, or a bucket left alone), then k_mark_pick marks the bucket's
+// ends from the parts' extremes.  One workgroup per bucket is bound by what
+// one CU keeps in flight, and the largest bucket sets the time; parts
+// spread every bucket over the device.
+template <int DT, int NT, bool MIN = false>
 __global__ __launch_bounds__(NT) void k_mark_part(const typename Traits<DT>::Elem* data, const uint64_t* bounds,
                                                   const TaskD* tasks, const TaskS* ts, uint32_t t0, uint32_t P,
-                                                  typename Traits<DT>::Key* pk, uint64_t* pp, uint32_t* err) {
+                                                  typename Traits<DT>::Key* pk, uint64_t* pp,
+                                                  typename Traits<DT>::Key* qk, uint64_t* qp, uint32_t* err) {
     using TR = Traits<DT>;
     using Key = typename TR::Key;
     constexpr int W = NT / 64;
     constexpr int U = 8;
-    __shared__ Key sk[W];
-    __shared__ uint64_t sp[W];
+    __shared__ Key sk[W], sk2[W];
+    __shared__ uint64_t sp[W], sp2[W];
     const uint32_t t = t0 + blockIdx.y;
     const uint32_t j = blockIdx.x / P, q = blockIdx.x % P;
     const TaskD td = tasks[t];
@@ -2773,52 +2821,73 @@ __global__ __launch_bounds__(NT) void k_mark_part(const typename Traits<DT>::Ele
         if (tid == 0) pp[at] = ~0ull;
         return;
     }
-    Key bk = TR::key(data[a]);
-    uint64_t bp = a;
+    Key bk = TR::key(data[a]), mk = bk;
+    uint64_t bp = a, mp = a;
     uint64_t p = a + tid;
     for (; p + (U - 1) * NT < b; p += U * NT) {
         Key kq[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) kq[u] = TR::key(data[p + (uint64_t)u * NT]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
+        for (int u = 0; u < U; ++u) {
+            keep_max(bk, bp, kq[u], p + (uint64_t)u * NT);
+            if constexpr (MIN) keep_min(mk, mp, kq[u], p + (uint64_t)u * NT);
+        }
     }
-    for (; p < b; p += NT) keep_max(bk, bp, TR::key(data[p]), p);
+    for (; p < b; p += NT) {
+        const Key kk = TR::key(data[p]);
+        keep_max(bk, bp, kk, p);
+        if constexpr (MIN) keep_min(mk, mp, kk, p);
+    }
     for (int d = 32; d >= 1; d >>= 1) {
         const Key ko = shfl_xor_key(bk, d);
         const uint64_t po = (uint64_t)__shfl_xor(bp, d, 64);
         keep_max(bk, bp, ko, po);
+        if constexpr (MIN) {
+            const Key k2 = shfl_xor_key(mk, d);
+            const uint64_t p2 = (uint64_t)__shfl_xor(mp, d, 64);
+            keep_min(mk, mp, k2, p2);
+        }
     }
     if (lane_id() == 0) {
         sk[tid / 64] = bk;
         sp[tid / 64] = bp;
+        sk2[tid / 64] = mk;
+        sp2[tid / 64] = mp;
     }
     __syncthreads();
     if (tid == 0) {
-        for (int w = 1; w < W; ++w) keep_max(bk, bp, sk[w], sp[w]);
+        for (int w = 1; w < W; ++w) {
+            keep_max(bk, bp, sk[w], sp[w]);
+            if constexpr (MIN) keep_min(mk, mp, sk2[w], sp2[w]);
+        }
         pk[at] = bk;
         pp[at] = bp;
+        if constexpr (MIN) {
+            qk[at] = mk;
+            qp[at] = mp;
+        }
     }
 }
 
 // One lane per bucket: the largest of the parts' maxima (the first position
-// among equal keys; parts lie in position order) trades places with the
-// bucket's first element.
-template <int DT>
+// among equal keys; parts lie in position order) goes to the bucket's first
+// entry, and with MIN the smallest of their minima to its last (mark_ends).
+template <int DT, bool MIN = false>
 __global__ __launch_bounds__(256) void k_mark_pick(typename Traits<DT>::Elem* data, const uint64_t* bounds,
                                                    const TaskD* tasks, const TaskS* ts, uint32_t t0, uint32_t P,
-                                                   const typename Traits<DT>::Key* pk, const uint64_t* pp) {
+                                                   const typename Traits<DT>::Key* pk, const uint64_t* pp,
+                                                   const typename Traits<DT>::Key* qk, const uint64_t* qp) {
     using TR = Traits<DT>;
     using Key = typename TR::Key;
-    using Elem = typename TR::Elem;
     const uint32_t t = t0 + blockIdx.y;
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
     const TaskD td = tasks[t];
     if (j >= ts[t].K) return;
     const uint64_t base = ((uint64_t)td.slot_begin + j) * P;
     bool have = false;
-    Key bk{};
-    uint64_t bp = 0;
+    Key bk{}, mk{};
+    uint64_t bp = 0, mp = 0;
     for (uint32_t q = 0; q < P; ++q) {
         const uint64_t p = pp[base + q];
         if (p == ~0ull) continue;
@@ -2826,18 +2895,19 @@ __global__ __launch_bounds__(256) void k_mark_pick(typename Traits<DT>::Elem* da
         if (!have) {
             bk = k;
             bp = p;
+            if constexpr (MIN) {
+                mk = qk[base + q];
+                mp = qp[base + q];
+            }
             have = true;
         } else {
             keep_max(bk, bp, k, p);
+            if constexpr (MIN) keep_min(mk, mp, qk[base + q], qp[base + q]);
         }
     }
     if (!have) return;
-    const uint64_t lo = td.off + bounds[td.slot_begin + t + j];
-    if (bp != lo) {
-        const Elem e = data[lo];
-        data[lo] = data[bp];
-        data[bp] = e;
-    }
+    const uint64_t* bd = bounds + td.slot_begin + t;
+    mark_ends<DT, MIN>(data, td.off + bd[j], td.off + bd[j + 1], bp, mp);
 }
 
 // searchNextLargest for caller-given positions: out[q] = the first position
@@ -2862,11 +2932,15 @@ __global__ __launch_bounds__(256) void k_search_next(const typename Traits<DT>::
 // sequential order: one wavefront per task).  The bucket boundaries
 // overwrite the task's bounds[0..K] (relative to its offset): the c
 // non-empty buckets found, then the task's end repeated (empty buckets).
-// More buckets than the partition made means the marks are missing.
-template <int DT>
+// More buckets than the partition made means the marks are missing.  With
+// MIN (the marking also put each bucket's smallest key last) a bucket above
+// `cap` elements whose two ends hold equal keys is one key value, and its
+// start carries kOneKeyBit.
+constexpr uint64_t kOneKeyBit = 1ull << 63;
+template <int DT, bool MIN = false>
 __global__ __launch_bounds__(256) void k_walk(const typename Traits<DT>::Elem* data, uint64_t* bounds,
                                               const TaskD* tasks, const TaskS* ts, uint32_t ntasks,
-                                              uint32_t* err) {
+                                              uint64_t cap, uint32_t* err) {
     using TR = Traits<DT>;
     const uint32_t t = blockIdx.x * 4 + threadIdx.x / 64;
     if (t >= ntasks) return;
@@ -2887,8 +2961,15 @@ __global__ __launch_bounds__(256) void k_walk(const typename Traits<DT>::Elem* d
             if (lane == 0) raise_err(err, ERR_MARKS);
             return;
         }
-        if (lane == 0) bd[c] = i - td.off;
+        const typename TR::Key top = piv;
         const uint64_t j = wave_next_larger<DT>(data, piv, i + 1, hi, &piv, guess ? guess - 1 : 0);
+        // with MIN, a bucket above the capacity whose last entry (its
+        // smallest key) equals its first (its largest) holds one key value
+        bool one = false;
+        if constexpr (MIN) {
+            if (j - i > cap) one = TR::key(data[j - 1]) == top;
+        }
+        if (lane == 0) bd[c] = (i - td.off) | (one ? kOneKeyBit : 0ull);
         guess = j - i;
         i = j;
         ++c;

@@ -54,10 +54,12 @@ struct Seg {
 // Larger buckets are appended to `next` (grp inherited, dup = eq).  Returns false when
 // the bounds are inconsistent (bounds[0] != 0, bounds[K] != m, decreasing).
 // With `srcs`, every bin made here also gets its BinSrc (task `task`),
-// appended in the order of the bins.
+// appended in the order of the bins.  With `one`, a bucket i with one[i]
+// set is known to hold one key value and is final like an equality bucket.
 inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool eq, const uint64_t* bounds,
                        uint64_t cap, uint64_t bin_cap, std::vector<SegD>& bins, std::vector<Seg>& next,
-                       uint64_t* elements_base, std::vector<BinSrc>* srcs = nullptr, uint32_t task = 0) {
+                       uint64_t* elements_base, std::vector<BinSrc>* srcs = nullptr, uint32_t task = 0,
+                       const uint8_t* one = nullptr) {
     if (K == 0 || bounds[0] != 0 || bounds[K] != m) return false;
     for (uint32_t i = 0; i < K; ++i)
         if (bounds[i + 1] < bounds[i]) return false;
@@ -66,6 +68,7 @@ inline bool split_task(uint64_t off, uint64_t m, uint32_t grp, uint32_t K, bool 
         const uint64_t sz = bounds[i + 1] - bounds[i];
         if (sz <= 1) continue;
         if (eq && (i & 1)) continue;             // equality bucket: one key value
+        if (one && one[i]) continue;             // found to hold one key value
         const uint64_t at = off + bounds[i];
         if (sz > cap) {
             next.push_back(Seg{at, sz, grp, eq ? 1u : 0u});

@@ -121,6 +121,29 @@ static int inconsistent_bounds() {
     return 0;
 }
 
+// Buckets flagged as one key value (the strictly in-place hand-off finds
+// them by their two ends) are final whatever their size: neither recursed
+// into nor binned.
+static int one_key_buckets() {
+    std::vector<SegD> bins;
+    std::vector<Seg> next;
+    uint64_t eb = 0;
+    const uint64_t bd[] = {0, 50, 2050, 2100, 4100};
+    const uint8_t one[] = {0, 1, 0, 0};
+    CHECK(split_task(0, 4100, 0, 4, false, bd, 1000, 400, bins, next, &eb, nullptr, 0, one), "split");
+    CHECK(next.size() == 1 && next[0].off == 2100 && next[0].m == 2000, "only the unflagged large bucket recurses");
+    CHECK(bins.size() == 2 && bins[0].off == 0 && bins[0].len == 50 && bins[1].off == 2050 && bins[1].len == 50,
+          "bins %zu", bins.size());
+    CHECK(eb == 100, "elements to the base case %llu", (unsigned long long)eb);
+    std::vector<SegD> bins2;
+    std::vector<Seg> next2;
+    uint64_t eb2 = 0;
+    const uint8_t small_one[] = {1, 0, 1, 0};
+    CHECK(split_task(0, 4100, 0, 4, false, bd, 1000, 400, bins2, next2, &eb2, nullptr, 0, small_one), "split");
+    CHECK(bins2.empty() && eb2 == 0 && next2.size() == 2, "flagged small buckets are not binned");
+    return 0;
+}
+
 // Random recursions over random segment lists: every property above.
 static int random_recursions() {
     for (int trial = 0; trial < 400; ++trial) {
@@ -240,6 +263,7 @@ int main() {
     if (regression_gap_between_tasks()) return 1;
     if (merging_inside_a_task()) return 1;
     if (inconsistent_bounds()) return 1;
+    if (one_key_buckets()) return 1;
     if (random_recursions()) return 1;
     std::printf("planner ok\n");
     return 0;

@@ -155,3 +155,22 @@ def test_sort_segmented_strict(env, dtype, dist):
     print(f"[gpu] strict segmented {dtype} {dist} n={n} segments={len(sizes)}", flush=True)
     out = gpu_sort_segmented(env, inp, offs, dtype, {"flags": ips.FLAG_STRICT})
     assert_segments_like_oracle(out, inp, offs, dtype)
+
+
+@pytest.mark.parametrize("dtype,dist,n", [("u64", "eightdup", 1 << 22), ("u64", "rootdup", 1 << 22),
+                                          ("f64", "eightdup", 3000017), ("pair", "rootdup", 1 << 21)])
+def test_sort_strict_skips_one_key_buckets(env, dtype, dist, n):
+    """The sort's marking also puts each bucket's smallest key last, so the
+    walk recognises a bucket above the base-case capacity that holds one key
+    by its two ends: equality buckets are not partitioned again, and the
+    strict hand-off distributes exactly the elements the default one does."""
+    torch, ips, h = env
+    inp = workloads.generate(dist, dtype, n, workloads.seed_for(3, dist, dtype))
+    print(f"[gpu] strict one-key buckets {dtype} {dist} n={n}", flush=True)
+    gpu_sort(env, inp, dtype, None)
+    ref = ips.ips4o_last_stats(h)
+    out = gpu_sort(env, inp, dtype, {"flags": ips.FLAG_STRICT})
+    st = ips.ips4o_last_stats(h)
+    assert_sorted_like_oracle(out, inp, dtype)
+    assert st["levels"] == ref["levels"]
+    assert st["elements_distributed"] == ref["elements_distributed"]
